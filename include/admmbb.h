@@ -1,0 +1,225 @@
+/*
+ * admmbb.h — C ABI of the MI355X (gfx950) ADMM-BB robust proton planning library.
+ *
+ * Problem (Sec. 2.1, scenario objective and robust problem): spot intensities
+ * x in R^n minimise
+ *
+ *     f(x) = sum_s c_s sum_i w_i (a_{s,i}^T x - p_i)^2     subject to lb <= x <= ub
+ *
+ * where A_s (m voxels x n spots, nonnegative) is the dose-influence matrix of
+ * uncertainty scenario s, w_i >= 0 is the weight of voxel i (constant within a
+ * structure), p the prescription and c_s the scenario probability (end of
+ * Sec. 2.1; c_s = 1 reproduces the equal-probability problem).  The paper's
+ * constraint x >= 0 is lb = 0, ub = +inf.
+ *
+ * Method (Sec. 2.2 and Appendix A): consensus ADMM over scenarios with a
+ * Barzilai-Borwein dual step.  Each iteration solves, for every scenario, the
+ * regularised WLS subproblem through its normal equations
+ *     (A_s^T diag(c_s w) A_s + rho/2 I) x_s = A_s^T diag(c_s w) p + rho/2 (z - y_s/rho),
+ * here by warm-started conjugate gradients on the GPU (the paper factors the
+ * matrix once by Cholesky); then z = P(mean_s(x_s + y_s/rho)), the BB step
+ * beta = -<dd, dy>/||dd||^2 replacing rho in y_s += tau (x_s - z) when
+ * positive, and the residual stopping test of Sec. 2.2 combined with a
+ * relative-objective-change test (Sec. 2.3).  pgd_solve is the comparison
+ * method of Sec. 2.1 (projected gradient with Armijo backtracking).
+ *
+ * Conventions
+ *   - Every function returns admm_status and never throws or aborts across the
+ *     ABI.  Negative codes mean the outputs were not written; ADMM_MAX_ITER
+ *     means outputs are valid but the stopping test was not met.
+ *     admm_last_error() gives a message for the last failure.
+ *   - Input arrays are host memory, borrowed only for the duration of the call;
+ *     the library copies and repacks what it needs into device memory it owns.
+ *   - Output arrays are caller-allocated host memory.
+ *   - One context is used by one host thread at a time.  All device work of a
+ *     context is issued on its stream (admm_options.stream; NULL means a
+ *     stream the library creates).
+ *   - Validation of a problem happens entirely on the host before any device
+ *     work, so malformed input is reported without touching the GPU.
+ */
+#ifndef ADMMBB_H
+#define ADMMBB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct admm_ctx admm_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  ADMM_OK = 0,
+  ADMM_MAX_ITER = 1,     /* outputs valid, stopping test not met */
+  ADMM_E_ARG = -1,       /* bad argument (NULL pointer, size, option) */
+  ADMM_E_CSR = -2,       /* malformed CSR: row_ptr not monotone, column out of range or not increasing */
+  ADMM_E_NEGATIVE = -3,  /* negative matrix value, weight or prescription */
+  ADMM_E_NONFINITE = -4, /* NaN or Inf in an input */
+  ADMM_E_OOM = -5,       /* device or host allocation failed */
+  ADMM_E_HIP = -6,       /* HIP runtime error (no device, launch failure) */
+  ADMM_E_DIVERGED = -7,  /* iterates became non-finite */
+  ADMM_E_STATE = -8      /* call not valid in the context's current state */
+} admm_status;
+
+enum { ADMM_PREC_FP32 = 0, ADMM_PREC_BF16 = 1, ADMM_PREC_FP16 = 2 };
+
+/* One scenario's dose-influence matrix A_s in CSR (Sec. 2.1: A_s in R_+^{m x n}).
+ * row_ptr: m+1 nondecreasing offsets, row_ptr[0] = 0, row_ptr[m] = nnz.
+ * col: column (spot) indices, strictly increasing within a row, in [0, n).
+ * val: entries, finite and >= 0.
+ * prob: scenario probability c_s >= 0 (0 is read as 1). */
+typedef struct {
+  int64_t nnz;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  double prob;
+} admm_csr;
+
+/* One patient: num_scen matrices with the same m, n.
+ * w_i = struct_weight[struct_id[i]] >= 0 (weights constant per structure, Sec. 2.1);
+ * presc[i] = p_i >= 0 (Sec. 2.1); lb/ub: n bounds each, NULL means 0 / +inf. */
+typedef struct {
+  int32_t m, n, num_scen;
+  const admm_csr* A;
+  const uint8_t* struct_id;
+  int32_t num_struct;
+  const double* struct_weight;
+  const double* presc;
+  const double* lb;
+  const double* ub;
+} admm_problem;
+
+typedef struct {
+  double rho;          /* penalty; <= 0 selects 2 * mean_s mean_j (A_s^T c_s W A_s)_jj */
+  double eps_abs;      /* stopping tolerances of Sec. 2.2; default 1e-6 (Sec. 2.3) */
+  double eps_rel;      /* default 1e-6 */
+  double obj_rel_tol;  /* relative objective change combined with the residual test; default 1e-5; 0 disables */
+  int32_t max_iter;    /* default 1000 */
+  int32_t bb;          /* 1: Barzilai-Borwein dual step (default), 0: fixed rho */
+  int32_t z_mode;      /* 0: z = P(mean(x_s + y_s/rho)) (default); 1: z = P(mean x_s) as printed in Sec. 2.2 */
+  double bb_clamp;     /* 0: none (default); c > 0: tau clamped to [rho/c, rho*c] */
+  int32_t cg_max;      /* CG steps per ADMM iteration, 1..64; default 8 */
+  double cg_eta;       /* CG stops at ||r|| <= eta ||c_s||, eta = max(eta_floor, cg_eta*min(1, r_prim/||x||)); default 0.1 */
+  double cg_eta_floor; /* default 1e-6 */
+  int32_t precision;   /* ADMM_PREC_*: value type of A_s inside CG; the objective and the
+                          per-iteration residual always use the fp32 matrix; default FP32 */
+  int32_t precond;     /* 1: Jacobi-preconditioned CG; default 0 */
+  int32_t use_graph;   /* 1: capture one iteration in a HIP graph and replay it (default) */
+  int32_t check_every; /* host reads the stop flags every k iterations; default 1 */
+  int32_t lds_fp64;    /* column accumulators in LDS: -1 auto (fp64 when max n <= 4096), 0 fp32, 1 fp64 */
+  int32_t tile_nnz;    /* target nonzeros per workgroup tile; 0 = automatic */
+  void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
+} admm_options;
+
+/* Per-iteration record (also the summary returned by solve / iterate). */
+typedef struct {
+  int32_t iter;      /* ADMM iterations completed */
+  int32_t cg_steps;  /* CG steps summed over scenarios: last iteration (trace) or total (summary) */
+  int32_t status;    /* admm_status of the patient */
+  int32_t pad;
+  double obj;        /* f(z) (fp32 matrix, fp64 accumulation) */
+  double r_prim, r_dual, eps_prim, eps_dual;
+  double tau;        /* dual step used */
+} admm_info;
+
+/* PGD options (Sec. 2.1). alpha <= 0 selects 10 / lambda_max(H) (30 power iterations). */
+typedef struct {
+  double alpha, beta, gamma; /* initial step, sufficient-decrease constant, shrink factor; defaults 0 / 1e-4 / 0.5 */
+  double obj_rel_tol;        /* stop when |f_k - f_{k+1}| <= tol |f_k|; default 1e-5 */
+  int32_t max_iter;          /* default 10000 */
+  int32_t max_trials;        /* backtracking trials per iteration; default 60 */
+} pgd_options;
+
+/* Fill opts / popts with the defaults documented above. */
+admm_status admm_default_options(admm_options* opts);
+admm_status pgd_default_options(pgd_options* popts);
+
+/* Validate the problem on the host, copy it to the device (length-sorted CSR,
+ * optional bf16/fp16 copy of the values with per-row scales), and prepare the
+ * ADMM state at z = P(0), y = 0.  On failure *out = NULL and nothing leaks. */
+admm_status admm_setup(const admm_problem* prob, const admm_options* opts, admm_ctx** out);
+
+/* Several independent patients in one context: every kernel launch covers all
+ * of them (one launch per phase per iteration). */
+admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, const admm_options* opts,
+                             admm_ctx** out);
+
+/* Reset every patient to z = P(z0) (z0 NULL: 0), y = 0, iteration 0.
+ * rho > 0 replaces the penalty of that patient (rho <= 0 keeps it). */
+admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, double rho);
+admm_status admm_reset(admm_ctx* ctx);
+
+/* Run exactly k ADMM iterations for every patient, without the stopping test.
+ * info (one per patient, may be NULL) receives the state after the last one. */
+admm_status admm_iterate(admm_ctx* ctx, int32_t k, admm_info* info);
+
+/* Iterate until every patient meets the stopping test or max_iter.
+ * z_out: n doubles per patient, concatenated (may be NULL); info: one per patient. */
+admm_status admm_solve(admm_ctx* ctx, double* z_out, admm_info* info);
+
+/* Projected gradient descent with Armijo backtracking for one patient, from
+ * P(x0) (x0 NULL: 0); x_out: n doubles. */
+admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, const double* x0, double* x_out,
+                      admm_info* info);
+
+/* f(x) with the fp32 matrix and fp64 accumulation; x: n doubles (rounded to fp32). */
+admm_status admm_objective(admm_ctx* ctx, int32_t patient, const double* x, double* f_out);
+
+/* grad f(x) (n doubles) and f(x). */
+admm_status admm_gradient(admm_ctx* ctx, int32_t patient, const double* x, double* grad_out, double* f_out);
+
+/* Scaled KKT residual ||x - P(x - grad f(x))||_inf / max(1, ||grad f(0) ... g0||_inf), g0 = 2 sum_s c_s A_s^T W p. */
+admm_status admm_kkt(admm_ctx* ctx, int32_t patient, const double* x, double* r_out);
+
+/* Single products with the device matrices (fp32 values), for checking:
+ *   matvec:  out[m] = A_s v          (v: n floats)
+ *   rmatvec: out[n] = A_s^T t        (t: m floats)
+ *   normal:  out[n] = (A_s^T diag(c_s w) A_s + rho/2 I) v, rho the patient's penalty;
+ *            precision selects the value copy used (ADMM_PREC_*), as inside CG. */
+admm_status admm_matvec(admm_ctx* ctx, int32_t patient, int32_t scen, const float* v, float* out);
+admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const float* t, float* out);
+admm_status admm_normal_apply(admm_ctx* ctx, int32_t patient, int32_t scen, int32_t precision, const float* v,
+                              float* out);
+
+/* Penalty rho in use for a patient. */
+admm_status admm_get_rho(const admm_ctx* ctx, int32_t patient, double* rho);
+
+/* Current consensus iterate z (n doubles). */
+admm_status admm_get_z(admm_ctx* ctx, int32_t patient, double* z);
+
+/* Checkpoint / resume.  The state that determines the next iterations is
+ * z (n), y (N*n, scenario-major), d = x - z of the last iteration (N*n) and
+ * 8 scalars {iter, tau, f_prev, pending, stopped, status, rho, cg_total}. */
+admm_status admm_get_state(admm_ctx* ctx, int32_t patient, double* z, double* y, double* d, double* scalars);
+admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, const double* y, const double* d,
+                           const double* scalars);
+
+/* Per-iteration records of the last solve / iterate calls (up to cap). */
+admm_status admm_get_trace(admm_ctx* ctx, int32_t patient, admm_info* buf, int32_t cap, int32_t* count);
+
+/* Sizes: num_patients; per patient n, m, num_scen, total nonzeros. */
+admm_status admm_get_sizes(const admm_ctx* ctx, int32_t patient, int32_t* n, int32_t* m, int32_t* num_scen,
+                           int64_t* nnz);
+
+/* Device timing.  admm_enable_timing(ctx, 1) makes later solve / iterate calls
+ * record HIP events on the context stream: around the whole call, and around
+ * every launch of the fused CG pass (the dominant kernel, including launches
+ * whose scenarios have all converged and exit early).  admm_get_timing returns
+ * the total milliseconds of the most recent call and the average duration and
+ * count of those pass launches. */
+admm_status admm_enable_timing(admm_ctx* ctx, int32_t on);
+admm_status admm_get_timing(const admm_ctx* ctx, double* total_ms, double* pass_ms, int32_t* pass_launches);
+
+/* Message of the last failure on ctx (ctx NULL: the last failed setup of this thread). */
+const char* admm_last_error(const admm_ctx* ctx);
+
+void admm_destroy(admm_ctx* ctx);
+
+/* Host-only validation of a problem (the checks admm_setup performs first). */
+admm_status admm_validate(const admm_problem* prob);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADMMBB_H */

@@ -1,0 +1,1013 @@
+// Host runtime: device state of a context, the launch sequence of one ADMM-BB
+// iteration (captured once into a HIP graph and replayed), the PGD loop and the
+// extern "C" entry points of include/admmbb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "host.h"
+
+using namespace admmbb;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct HipError {
+  hipError_t code;
+  const char* what;
+};
+
+inline void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{e, what};
+}
+
+}  // namespace
+
+struct admm_ctx {
+  std::string err;
+  admm_options opts{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Packed H;  // host image (kept for sizes, g0, bounds)
+  int P = 0, G = 0, T = 0, NB = 0, NPB = 0;
+  std::vector<double> rho;  // per patient
+  std::vector<void*> allocs;
+  // device tables
+  Scen* d_scen = nullptr;
+  Pat* d_pat = nullptr;
+  Tile* d_tiles = nullptr;
+  Blk* d_blk = nullptr;
+  Blk* d_pblk = nullptr;
+  MatDev mat32{}, matlp{};
+  // device vectors
+  float *d_x = nullptr, *d_r = nullptr, *d_v = nullptr, *d_q = nullptr, *d_zp = nullptr, *d_y = nullptr;
+  float *d_b = nullptr, *d_dinv = nullptr, *d_z = nullptr, *d_lb = nullptr, *d_ub = nullptr;
+  float *d_pvec = nullptr, *d_pvec2 = nullptr, *d_pvec3 = nullptr, *d_mvec = nullptr;
+  double* d_dprev = nullptr;
+  float* d_part = nullptr;
+  double* d_objpart = nullptr;
+  double *d_bpart = nullptr, *d_bpartp = nullptr, *d_scratch = nullptr;
+  uint8_t* d_act = nullptr;
+  double *d_rz = nullptr, *d_tol2 = nullptr;
+  int32_t* d_cgcount = nullptr;
+  PatState* d_ps = nullptr;
+  IterRecord* d_trace = nullptr;
+  int trace_cap = 0;
+  PatState* h_ps = nullptr;  // pinned
+  double* h_scr = nullptr;   // pinned scratch
+  hipGraphExec_t g_solve = nullptr, g_iter = nullptr;
+  hipGraph_t gr_solve = nullptr, gr_iter = nullptr;
+  bool acc64 = false;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs around the CG passes inside the captured iteration
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  double total_ms = 0.0, pass_ms_sum = 0.0;
+  int64_t pass_count = 0;
+
+  template <class T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+    return p;
+  }
+  ~admm_ctx() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (g_solve) (void)hipGraphExecDestroy(g_solve);
+    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    if (gr_solve) (void)hipGraphDestroy(gr_solve);
+    if (gr_iter) (void)hipGraphDestroy(gr_iter);
+    for (auto e : ev) (void)hipEventDestroy(e);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_ps) (void)hipHostFree(h_ps);
+    if (h_scr) (void)hipHostFree(h_scr);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  PassArgs pass_args(const MatDev& m) const {
+    PassArgs a{};
+    a.tiles = d_tiles;
+    a.scen = d_scen;
+    a.pat = d_pat;
+    a.mat = m;
+    a.part = d_part;
+    a.objpart = d_objpart;
+    a.nmax = H.nmax;
+    a.acc64 = acc64 ? 1 : 0;
+    return a;
+  }
+
+  VecArgs vec_args(int stop_enabled) const {
+    VecArgs a{};
+    a.scen = d_scen;
+    a.pat = d_pat;
+    a.blk = d_blk;
+    a.pblk = d_pblk;
+    a.tiles = d_tiles;
+    a.part = d_part;
+    a.objpart = d_objpart;
+    a.ps = d_ps;
+    a.act = d_act;
+    a.rz = d_rz;
+    a.tol2 = d_tol2;
+    a.cgcount = d_cgcount;
+    a.x = d_x;
+    a.r = d_r;
+    a.v = d_v;
+    a.q = d_q;
+    a.zp = d_zp;
+    a.y = d_y;
+    a.b = d_b;
+    a.dinv = d_dinv;
+    a.z = d_z;
+    a.lb = d_lb;
+    a.ub = d_ub;
+    a.dprev = d_dprev;
+    a.bpart = d_bpart;
+    a.bpartp = d_bpartp;
+    a.trace = d_trace;
+    a.prm.eps_abs = opts.eps_abs;
+    a.prm.eps_rel = opts.eps_rel;
+    a.prm.obj_rel_tol = opts.obj_rel_tol;
+    a.prm.bb_clamp = opts.bb_clamp;
+    a.prm.eta_factor = opts.cg_eta;
+    a.prm.eta_floor = opts.cg_eta_floor;
+    a.prm.bb = opts.bb;
+    a.prm.z_mode = opts.z_mode;
+    a.prm.stop_enabled = stop_enabled;
+    a.prm.precond = opts.precond;
+    a.prm.trace_cap = trace_cap;
+    a.prm.num_pat = P;
+    return a;
+  }
+
+  // head: gradient pass at z (objective + residual of the x-update system at x = z),
+  // completion of the previous iteration, CG set-up
+  void launch_head(int stop_enabled, int cg_setup) {
+    PassArgs pa = pass_args(mat32);
+    pa.src = d_z;
+    pa.src_per_scen = 0;
+    pa.ps = d_ps;
+    launch_pass(PASS_GRAD, pa, 0, T, stream);
+    VecArgs va = vec_args(stop_enabled);
+    launch_reduce(RED_HEAD, va, 0, NB, stream);
+    launch_head_scalars(va, G, cg_setup, stream);
+  }
+
+  void launch_body(int stop_enabled, bool with_events) {
+    const MatDev& m = (opts.precision == ADMM_PREC_FP32) ? mat32 : matlp;
+    VecArgs va = vec_args(stop_enabled);
+    for (int k = 0; k < opts.cg_max; ++k) {
+      PassArgs pa = pass_args(m);
+      pa.src = d_v;
+      pa.src_per_scen = 1;
+      pa.step = k;
+      pa.act = d_act;
+      pa.ps = d_ps;
+      pa.objpart = nullptr;
+      if (with_events) check(hipEventRecord(ev[2 * k], stream), "hipEventRecord");
+      launch_pass(PASS_CG, pa, 0, T, stream);
+      if (with_events) check(hipEventRecord(ev[2 * k + 1], stream), "hipEventRecord");
+      va.step = k;
+      launch_reduce(RED_CG, va, 0, NB, stream);
+      launch_cg_update(va, NB, stream);
+      launch_cg_dir(va, NB, stream);
+    }
+    launch_zres(va, NPB, stream);
+    launch_body_scalars(va, stream);
+  }
+
+  void capture(int stop_enabled, hipGraph_t* gr, hipGraphExec_t* ge) {
+    check(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      launch_head(stop_enabled, 1);
+      launch_body(stop_enabled, timing);
+    } catch (...) {
+      hipGraph_t tmp = nullptr;
+      (void)hipStreamEndCapture(stream, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      throw;
+    }
+    check(hipStreamEndCapture(stream, gr), "hipStreamEndCapture");
+    check(hipGraphInstantiate(ge, *gr, nullptr, nullptr, 0), "hipGraphInstantiate");
+  }
+
+  void one_iteration(int stop_enabled) {
+    if (opts.use_graph) {
+      hipGraphExec_t& ge = stop_enabled ? g_solve : g_iter;
+      hipGraph_t& gr = stop_enabled ? gr_solve : gr_iter;
+      if (!ge) capture(stop_enabled, &gr, &ge);
+      check(hipGraphLaunch(ge, stream), "hipGraphLaunch");
+    } else {
+      launch_head(stop_enabled, 1);
+      launch_body(stop_enabled, timing);
+    }
+  }
+
+  void accumulate_pass_times() {
+    if (!timing) return;
+    for (int k = 0; k < opts.cg_max; ++k) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess) {
+        pass_ms_sum += ms;
+        pass_count += 1;
+      }
+    }
+  }
+
+  void read_state() {
+    check(hipMemcpyAsync(h_ps, d_ps, sizeof(PatState) * P, hipMemcpyDeviceToHost, stream), "hipMemcpyAsync");
+    check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  }
+
+  // Run up to `k` iterations.  With stop_enabled the loop ends early once every
+  // patient has stopped.  A final head completes the bookkeeping of the last iteration.
+  void run(int k, int stop_enabled) {
+    if (timing) {
+      check(hipEventRecord(ev_a, stream), "hipEventRecord");
+      pass_ms_sum = 0.0;
+      pass_count = 0;
+    }
+    const int every = std::max(1, opts.check_every);
+    for (int it = 0; it < k; ++it) {
+      one_iteration(stop_enabled);
+      const bool last = (it + 1 == k);
+      if (timing || last || ((it + 1) % every == 0)) {
+        read_state();
+        accumulate_pass_times();
+        bool all = true;
+        for (int p = 0; p < P; ++p) all = all && (h_ps[p].stopped != 0);
+        if (all) break;
+      }
+    }
+    launch_head(stop_enabled, 0);
+    if (timing) {
+      check(hipEventRecord(ev_b, stream), "hipEventRecord");
+      check(hipEventSynchronize(ev_b), "hipEventSynchronize");
+      float ms = 0.0f;
+      check(hipEventElapsedTime(&ms, ev_a, ev_b), "hipEventElapsedTime");
+      total_ms = ms;
+    }
+    read_state();
+  }
+
+  void fill_info(admm_info* info) {
+    if (!info) return;
+    for (int p = 0; p < P; ++p) {
+      const PatState& s = h_ps[p];
+      admm_info& o = info[p];
+      std::memset(&o, 0, sizeof(o));
+      o.iter = s.iter;
+      o.cg_steps = s.cg_total;
+      o.status = s.status == 2 ? ADMM_E_DIVERGED : (s.status == 1 ? ADMM_OK : ADMM_MAX_ITER);
+      o.obj = s.f_cur;
+      o.r_prim = s.r_prim;
+      o.r_dual = s.r_dual;
+      o.eps_prim = s.eps_prim;
+      o.eps_dual = s.eps_dual;
+      o.tau = s.tau;
+    }
+  }
+
+  void reset_patient(int p, const double* z0, double new_rho) {
+    const Pat& pt = H.pat[p];
+    std::vector<float> z(pt.n);
+    for (int j = 0; j < pt.n; ++j) {
+      double v = z0 ? z0[j] : 0.0;
+      v = std::min(std::max(v, static_cast<double>(H.lb[pt.zvec_base + j])), static_cast<double>(H.ub[pt.zvec_base + j]));
+      z[j] = static_cast<float>(v);
+    }
+    check(hipMemcpyAsync(d_z + pt.zvec_base, z.data(), sizeof(float) * pt.n, hipMemcpyHostToDevice, stream), "H2D");
+    const Scen& s0 = H.scen[pt.scen_begin];
+    const int64_t len = static_cast<int64_t>(pt.num_scen) * pt.n;
+    launch_fill_f32(d_y + s0.vec_base, 0.0f, len, stream);
+    launch_fill_f32(d_x + s0.vec_base, 0.0f, len, stream);
+    launch_fill_f64(d_dprev + s0.vec_base, 0.0, len, stream);
+    if (new_rho > 0) rho[p] = new_rho;
+    PatState st{};
+    st.rho = rho[p];
+    st.tau = rho[p];
+    std::memcpy(h_ps + p, &st, sizeof(st));
+    check(hipMemcpyAsync(d_ps + p, h_ps + p, sizeof(PatState), hipMemcpyHostToDevice, stream), "H2D");
+    check(hipStreamSynchronize(stream), "sync");
+  }
+
+  void upload_pvec(int p, const double* x, float* dst) {
+    const Pat& pt = H.pat[p];
+    std::vector<float> v(pt.n);
+    for (int j = 0; j < pt.n; ++j) v[j] = static_cast<float>(x[j]);
+    check(hipMemcpyAsync(dst + pt.zvec_base, v.data(), sizeof(float) * pt.n, hipMemcpyHostToDevice, stream), "H2D");
+    check(hipStreamSynchronize(stream), "sync");
+  }
+
+  // f(x) and (optionally) grad f(x) for patient p, x already in d_pvec at zvec_base
+  double objective_dev(int p, float* grad_dev) {
+    const Pat& pt = H.pat[p];
+    PassArgs pa = pass_args(mat32);
+    pa.src = d_pvec;
+    pa.src_per_scen = 0;
+    if (!grad_dev) pa.part = nullptr;
+    launch_pass(PASS_GRAD, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, stream);
+    if (grad_dev)
+      launch_gsum(d_scen, d_pat, d_pblk, d_tiles, d_part, pt.blk_begin, pt.nblk, 2.0f, grad_dev, stream);
+    launch_objsum(d_tiles, d_objpart, pt.tile_begin, pt.tile_end - pt.tile_begin, d_scratch, stream);
+    check(hipMemcpyAsync(h_scr, d_scratch, sizeof(double), hipMemcpyDeviceToHost, stream), "D2H");
+    check(hipStreamSynchronize(stream), "sync");
+    return h_scr[0] + pt.fzero;
+  }
+};
+
+namespace {
+
+admm_status set_err(admm_ctx* c, admm_status st, const std::string& m) {
+  if (c)
+    c->err = m;
+  else
+    g_setup_error = m;
+  return st;
+}
+
+admm_status from_hip(admm_ctx* c, const HipError& e) {
+  std::string m = std::string(e.what) + ": " + hipGetErrorString(e.code);
+  return set_err(c, e.code == hipErrorOutOfMemory ? ADMM_E_OOM : ADMM_E_HIP, m);
+}
+
+#define GUARD_BEGIN try {
+#define GUARD_END(ctx)                                              \
+  }                                                                 \
+  catch (const HipError& e) {                                       \
+    return from_hip(ctx, e);                                        \
+  }                                                                 \
+  catch (const std::bad_alloc&) {                                   \
+    return set_err(ctx, ADMM_E_OOM, "host allocation failed");      \
+  }                                                                 \
+  catch (...) {                                                     \
+    return set_err(ctx, ADMM_E_HIP, "unexpected exception");        \
+  }
+
+admm_status check_patient(const admm_ctx* c, int32_t p) {
+  if (!c) return ADMM_E_ARG;
+  if (p < 0 || p >= c->P) return set_err(const_cast<admm_ctx*>(c), ADMM_E_ARG, "patient index out of range");
+  return ADMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+admm_status admm_default_options(admm_options* o) {
+  if (!o) return ADMM_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->rho = 0.0;
+  o->eps_abs = 1e-6;
+  o->eps_rel = 1e-6;
+  o->obj_rel_tol = 1e-5;
+  o->max_iter = 1000;
+  o->bb = 1;
+  o->z_mode = 0;
+  o->bb_clamp = 0.0;
+  o->cg_max = 8;
+  o->cg_eta = 0.1;
+  o->cg_eta_floor = 1e-6;
+  o->precision = ADMM_PREC_FP32;
+  o->precond = 0;
+  o->use_graph = 1;
+  o->check_every = 1;
+  o->lds_fp64 = -1;
+  o->tile_nnz = 0;
+  o->stream = nullptr;
+  return ADMM_OK;
+}
+
+admm_status pgd_default_options(pgd_options* o) {
+  if (!o) return ADMM_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->alpha = 0.0;
+  o->beta = 1e-4;
+  o->gamma = 0.5;
+  o->obj_rel_tol = 1e-5;
+  o->max_iter = 10000;
+  o->max_trials = 60;
+  return ADMM_OK;
+}
+
+admm_status admm_validate(const admm_problem* prob) {
+  std::string m;
+  admm_status st = validate_problem(prob, &m);
+  if (st != ADMM_OK) g_setup_error = m;
+  return st;
+}
+
+const char* admm_last_error(const admm_ctx* ctx) {
+  if (!ctx) return g_setup_error.c_str();
+  return ctx->err.c_str();
+}
+
+admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, const admm_options* opts,
+                             admm_ctx** out) {
+  if (!out) return set_err(nullptr, ADMM_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!probs || num_patients <= 0) return set_err(nullptr, ADMM_E_ARG, "no problems given");
+  admm_options o;
+  admm_default_options(&o);
+  if (opts) o = *opts;
+  std::string msg;
+  admm_status st = validate_options(&o, &msg);
+  if (st != ADMM_OK) return set_err(nullptr, st, msg);
+  for (int p = 0; p < num_patients; ++p) {
+    st = validate_problem(&probs[p], &msg);
+    if (st != ADMM_OK) return set_err(nullptr, st, "patient " + std::to_string(p) + ": " + msg);
+  }
+  std::unique_ptr<admm_ctx> c;
+  try {
+    c.reset(new admm_ctx());
+  } catch (const std::bad_alloc&) {
+    return set_err(nullptr, ADMM_E_OOM, "host allocation failed");
+  }
+  c->opts = o;
+  st = pack_problems(probs, num_patients, o, &c->H, &msg);
+  if (st != ADMM_OK) return set_err(nullptr, st, msg);
+  try {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+      return set_err(nullptr, ADMM_E_HIP, "no HIP device available");
+    Packed& H = c->H;
+    c->P = num_patients;
+    c->G = static_cast<int>(H.scen.size());
+    c->T = static_cast<int>(H.tiles.size());
+    c->NB = static_cast<int>(H.blk.size());
+    c->NPB = static_cast<int>(H.pblk.size());
+    c->acc64 = o.lds_fp64 == 1 || (o.lds_fp64 == -1 && H.nmax <= 4096);
+    if (o.stream) {
+      c->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+      check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+      c->own_stream = true;
+    }
+    c->rho.resize(num_patients);
+    for (int p = 0; p < num_patients; ++p) c->rho[p] = o.rho > 0 ? o.rho : 2.0 * H.gdiag_mean[p];
+    c->trace_cap = std::max(1, o.max_iter + 2);
+
+    c->d_scen = c->upload(H.scen);
+    c->d_pat = c->upload(H.pat);
+    c->d_tiles = c->upload(H.tiles);
+    c->d_blk = c->upload(H.blk);
+    c->d_pblk = c->upload(H.pblk);
+    const uint32_t* d_rp = c->upload(H.rp);
+    const void* d_col = H.col16_used ? static_cast<const void*>(c->upload(H.col16))
+                                     : static_cast<const void*>(c->upload(H.col32));
+    const float* d_rw = c->upload(H.rw);
+    const float* d_rpres = c->upload(H.rpres);
+    const int32_t* d_rorig = c->upload(H.rorig);
+    c->mat32 = MatDev{d_rp, d_col, c->upload(H.val), nullptr, d_rw, d_rpres, d_rorig, H.col16_used ? 1 : 0, VAL_F32};
+    // the host copies of the largest arrays are not needed after upload
+    std::vector<float>().swap(H.val);
+    if (o.precision != ADMM_PREC_FP32) {
+      c->matlp = MatDev{d_rp, d_col, c->upload(H.val_lp), c->upload(H.rscale), d_rw, d_rpres, d_rorig,
+                        H.col16_used ? 1 : 0, o.precision == ADMM_PREC_BF16 ? VAL_BF16 : VAL_F16};
+      std::vector<uint16_t>().swap(H.val_lp);
+    }
+    std::vector<uint16_t>().swap(H.col16);
+    std::vector<int32_t>().swap(H.col32);
+    std::vector<uint32_t>().swap(H.rp);
+
+    const size_t V = static_cast<size_t>(H.vec_total);
+    c->d_x = c->alloc<float>(V);
+    c->d_r = c->alloc<float>(V);
+    c->d_v = c->alloc<float>(V);
+    c->d_q = c->alloc<float>(V);
+    c->d_y = c->alloc<float>(V);
+    c->d_zp = o.precond ? c->alloc<float>(V) : c->d_r;
+    c->d_dinv = o.precond ? c->upload(H.dinv) : nullptr;
+    c->d_b = c->upload(H.b);
+    c->d_dprev = c->alloc<double>(V);
+    c->d_z = c->alloc<float>(H.zvec_total);
+    c->d_lb = c->upload(H.lb);
+    c->d_ub = c->upload(H.ub);
+    c->d_pvec = c->alloc<float>(H.zvec_total);
+    c->d_pvec2 = c->alloc<float>(H.zvec_total);
+    c->d_pvec3 = c->alloc<float>(H.zvec_total);
+    c->d_mvec = c->alloc<float>(H.mmax);
+    c->d_part = c->alloc<float>(static_cast<size_t>(H.part_total));
+    c->d_objpart = c->alloc<double>(c->T);
+    c->d_bpart = c->alloc<double>(static_cast<size_t>(c->NB) * 8);
+    c->d_bpartp = c->alloc<double>(static_cast<size_t>(c->NPB) * 8);
+    c->d_scratch = c->alloc<double>(std::max(64, (H.nmax + kThreads - 1) / kThreads + 8));
+    c->d_act = c->alloc<uint8_t>(static_cast<size_t>(c->G) * kRing);
+    c->d_rz = c->alloc<double>(static_cast<size_t>(c->G) * kRing);
+    c->d_tol2 = c->alloc<double>(c->G);
+    c->d_cgcount = c->alloc<int32_t>(c->G);
+    c->d_ps = c->alloc<PatState>(c->P);
+    c->d_trace = c->alloc<IterRecord>(static_cast<size_t>(c->P) * c->trace_cap);
+    check(hipHostMalloc(reinterpret_cast<void**>(&c->h_ps), sizeof(PatState) * c->P, hipHostMallocDefault),
+          "hipHostMalloc");
+    check(hipHostMalloc(reinterpret_cast<void**>(&c->h_scr), sizeof(double) * 64, hipHostMallocDefault),
+          "hipHostMalloc");
+    launch_fill_f32(c->d_v, 0.0f, V, c->stream);
+    launch_fill_f32(c->d_q, 0.0f, V, c->stream);
+    launch_fill_f32(c->d_r, 0.0f, V, c->stream);
+    launch_fill_u8(c->d_act, 0, static_cast<int64_t>(c->G) * kRing, c->stream);
+    launch_fill_f64(c->d_rz, 0.0, static_cast<int64_t>(c->G) * kRing, c->stream);
+    for (int p = 0; p < num_patients; ++p) c->reset_patient(p, nullptr, 0.0);
+    check(hipEventCreate(&c->ev_a), "hipEventCreate");
+    check(hipEventCreate(&c->ev_b), "hipEventCreate");
+    check(hipStreamSynchronize(c->stream), "setup sync");
+  } catch (const HipError& e) {
+    std::string m = std::string(e.what) + ": " + hipGetErrorString(e.code);
+    return set_err(nullptr, e.code == hipErrorOutOfMemory ? ADMM_E_OOM : ADMM_E_HIP, m);
+  } catch (const std::bad_alloc&) {
+    return set_err(nullptr, ADMM_E_OOM, "host allocation failed");
+  }
+  *out = c.release();
+  return ADMM_OK;
+}
+
+admm_status admm_setup(const admm_problem* prob, const admm_options* opts, admm_ctx** out) {
+  return admm_setup_batch(prob, 1, opts, out);
+}
+
+void admm_destroy(admm_ctx* ctx) { delete ctx; }
+
+admm_status admm_enable_timing(admm_ctx* ctx, int32_t on) {
+  if (!ctx) return ADMM_E_ARG;
+  GUARD_BEGIN
+  const bool want = on != 0;
+  if (want == ctx->timing) return ADMM_OK;
+  ctx->timing = want;
+  if (want && ctx->ev.empty()) {
+    ctx->ev.resize(2 * static_cast<size_t>(ctx->opts.cg_max));
+    for (auto& e : ctx->ev) check(hipEventCreate(&e), "hipEventCreate");
+  }
+  // graphs captured with the other setting are rebuilt on next use
+  if (ctx->g_solve) { (void)hipGraphExecDestroy(ctx->g_solve); ctx->g_solve = nullptr; }
+  if (ctx->g_iter) { (void)hipGraphExecDestroy(ctx->g_iter); ctx->g_iter = nullptr; }
+  if (ctx->gr_solve) { (void)hipGraphDestroy(ctx->gr_solve); ctx->gr_solve = nullptr; }
+  if (ctx->gr_iter) { (void)hipGraphDestroy(ctx->gr_iter); ctx->gr_iter = nullptr; }
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_get_timing(const admm_ctx* ctx, double* total_ms, double* pass_ms, int32_t* pass_launches) {
+  if (!ctx) return ADMM_E_ARG;
+  if (total_ms) *total_ms = ctx->total_ms;
+  if (pass_ms) *pass_ms = ctx->pass_count ? ctx->pass_ms_sum / ctx->pass_count : 0.0;
+  if (pass_launches) *pass_launches = static_cast<int32_t>(ctx->pass_count);
+  return ADMM_OK;
+}
+
+admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, double rho) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!std::isfinite(rho)) return set_err(ctx, ADMM_E_ARG, "rho not finite");
+  if (z0)
+    for (int j = 0; j < ctx->H.pat[patient].n; ++j)
+      if (!std::isfinite(z0[j])) return set_err(ctx, ADMM_E_NONFINITE, "z0 has a non-finite entry");
+  if (rho > 0 && ctx->opts.precond)
+    return set_err(ctx, ADMM_E_STATE, "changing rho is not supported with the Jacobi preconditioner");
+  GUARD_BEGIN
+  ctx->reset_patient(patient, z0, rho);
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_reset(admm_ctx* ctx) {
+  if (!ctx) return ADMM_E_ARG;
+  GUARD_BEGIN
+  for (int p = 0; p < ctx->P; ++p) ctx->reset_patient(p, nullptr, 0.0);
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_iterate(admm_ctx* ctx, int32_t k, admm_info* info) {
+  if (!ctx || k < 0) return set_err(ctx, ADMM_E_ARG, "bad argument");
+  GUARD_BEGIN
+  // iterate ignores earlier stops: clear the stop flags
+  ctx->read_state();
+  for (int p = 0; p < ctx->P; ++p) ctx->h_ps[p].stopped = ctx->h_ps[p].status == 2 ? 1 : 0;
+  check(hipMemcpyAsync(ctx->d_ps, ctx->h_ps, sizeof(PatState) * ctx->P, hipMemcpyHostToDevice, ctx->stream), "H2D");
+  ctx->run(k, 0);
+  ctx->fill_info(info);
+  for (int p = 0; p < ctx->P; ++p)
+    if (ctx->h_ps[p].status == 2) return set_err(ctx, ADMM_E_DIVERGED, "iterates became non-finite");
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_solve(admm_ctx* ctx, double* z_out, admm_info* info) {
+  if (!ctx) return ADMM_E_ARG;
+  GUARD_BEGIN
+  ctx->read_state();
+  int done = 0;
+  for (int p = 0; p < ctx->P; ++p) done = std::max(done, ctx->h_ps[p].iter);
+  const int k = std::max(0, ctx->opts.max_iter - done);
+  ctx->run(k, 1);
+  ctx->fill_info(info);
+  if (z_out) {
+    std::vector<float> z(static_cast<size_t>(ctx->H.zvec_total));
+    check(hipMemcpy(z.data(), ctx->d_z, sizeof(float) * z.size(), hipMemcpyDeviceToHost), "D2H");
+    for (size_t i = 0; i < z.size(); ++i) z_out[i] = z[i];
+  }
+  admm_status worst = ADMM_OK;
+  for (int p = 0; p < ctx->P; ++p) {
+    if (ctx->h_ps[p].status == 2) return set_err(ctx, ADMM_E_DIVERGED, "iterates became non-finite");
+    if (ctx->h_ps[p].status != 1) worst = ADMM_MAX_ITER;
+  }
+  return worst;
+  GUARD_END(ctx)
+}
+
+admm_status admm_get_z(admm_ctx* ctx, int32_t patient, double* z) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!z) return set_err(ctx, ADMM_E_ARG, "z is NULL");
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  std::vector<float> v(pt.n);
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  check(hipMemcpy(v.data(), ctx->d_z + pt.zvec_base, sizeof(float) * pt.n, hipMemcpyDeviceToHost), "D2H");
+  for (int j = 0; j < pt.n; ++j) z[j] = v[j];
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_get_rho(const admm_ctx* ctx, int32_t patient, double* rho) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (rho) *rho = ctx->rho[patient];
+  return ADMM_OK;
+}
+
+admm_status admm_get_sizes(const admm_ctx* ctx, int32_t patient, int32_t* n, int32_t* m, int32_t* num_scen,
+                           int64_t* nnz) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  const Pat& pt = ctx->H.pat[patient];
+  if (n) *n = pt.n;
+  if (m) *m = pt.m;
+  if (num_scen) *num_scen = pt.num_scen;
+  if (nnz) {
+    int64_t t = 0;
+    for (int s = 0; s < pt.num_scen; ++s) {
+      const Scen& sc = ctx->H.scen[pt.scen_begin + s];
+      const int64_t next = (pt.scen_begin + s + 1 < ctx->G) ? ctx->H.scen[pt.scen_begin + s + 1].nnz_base
+                                                           : ctx->H.nnz_total;
+      t += next - sc.nnz_base;
+    }
+    *nnz = t;
+  }
+  return ADMM_OK;
+}
+
+admm_status admm_objective(admm_ctx* ctx, int32_t patient, const double* x, double* f_out) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!x || !f_out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  GUARD_BEGIN
+  ctx->upload_pvec(patient, x, ctx->d_pvec);
+  *f_out = ctx->objective_dev(patient, nullptr);
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_gradient(admm_ctx* ctx, int32_t patient, const double* x, double* grad_out, double* f_out) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!x || !grad_out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  ctx->upload_pvec(patient, x, ctx->d_pvec);
+  const double f = ctx->objective_dev(patient, ctx->d_pvec2 + pt.zvec_base);
+  std::vector<float> g(pt.n);
+  check(hipMemcpy(g.data(), ctx->d_pvec2 + pt.zvec_base, sizeof(float) * pt.n, hipMemcpyDeviceToHost), "D2H");
+  for (int j = 0; j < pt.n; ++j) grad_out[j] = g[j];
+  if (f_out) *f_out = f;
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_kkt(admm_ctx* ctx, int32_t patient, const double* x, double* r_out) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!x || !r_out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  const Pat& pt = ctx->H.pat[patient];
+  std::vector<double> g(pt.n);
+  st = admm_gradient(ctx, patient, x, g.data(), nullptr);
+  if (st != ADMM_OK) return st;
+  double gi = 0.0, r = 0.0;
+  for (int j = 0; j < pt.n; ++j) gi = std::max(gi, std::fabs(ctx->H.g0[patient][j]));
+  for (int j = 0; j < pt.n; ++j) {
+    const double lo = ctx->H.lb[pt.zvec_base + j], hi = ctx->H.ub[pt.zvec_base + j];
+    const double pj = std::min(std::max(x[j] - g[j], lo), hi);
+    r = std::max(r, std::fabs(x[j] - pj));
+  }
+  *r_out = r / std::max(1.0, gi);
+  return ADMM_OK;
+}
+
+static admm_status scen_index(admm_ctx* ctx, int32_t patient, int32_t scen, int* g) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  const Pat& pt = ctx->H.pat[patient];
+  if (scen < 0 || scen >= pt.num_scen) return set_err(ctx, ADMM_E_ARG, "scenario index out of range");
+  *g = pt.scen_begin + scen;
+  return ADMM_OK;
+}
+
+admm_status admm_matvec(admm_ctx* ctx, int32_t patient, int32_t scen, const float* v, float* out) {
+  int g = 0;
+  admm_status st = scen_index(ctx, patient, scen, &g);
+  if (st != ADMM_OK) return st;
+  if (!v || !out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  const Scen& sc = ctx->H.scen[g];
+  check(hipMemcpyAsync(ctx->d_pvec + pt.zvec_base, v, sizeof(float) * pt.n, hipMemcpyHostToDevice, ctx->stream), "H2D");
+  launch_fill_f32(ctx->d_mvec, 0.0f, pt.m, ctx->stream);
+  PassArgs pa = ctx->pass_args(ctx->mat32);
+  pa.src = ctx->d_pvec;
+  pa.src_per_scen = 0;
+  pa.tout = ctx->d_mvec;
+  pa.objpart = nullptr;
+  launch_pass(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+  check(hipMemcpyAsync(out, ctx->d_mvec, sizeof(float) * pt.m, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const float* t, float* out) {
+  int g = 0;
+  admm_status st = scen_index(ctx, patient, scen, &g);
+  if (st != ADMM_OK) return st;
+  if (!t || !out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  const Scen& sc = ctx->H.scen[g];
+  check(hipMemcpyAsync(ctx->d_mvec, t, sizeof(float) * pt.m, hipMemcpyHostToDevice, ctx->stream), "H2D");
+  PassArgs pa = ctx->pass_args(ctx->mat32);
+  pa.tin = ctx->d_mvec;
+  pa.objpart = nullptr;
+  launch_pass(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+  VecArgs va = ctx->vec_args(0);
+  va.out = ctx->d_pvec2 + pt.zvec_base;
+  launch_reduce(RED_RMAT, va, sc.blk_begin, sc.nblk, ctx->stream);
+  check(hipMemcpyAsync(out, va.out, sizeof(float) * pt.n, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_normal_apply(admm_ctx* ctx, int32_t patient, int32_t scen, int32_t precision, const float* v,
+                              float* out) {
+  int g = 0;
+  admm_status st = scen_index(ctx, patient, scen, &g);
+  if (st != ADMM_OK) return st;
+  if (!v || !out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  if (precision != ADMM_PREC_FP32 && precision != ctx->opts.precision)
+    return set_err(ctx, ADMM_E_ARG, "that value precision was not set up for this context");
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  const Scen& sc = ctx->H.scen[g];
+  // the input goes where the CG direction of this scenario lives (scratch between iterations)
+  check(hipMemcpyAsync(ctx->d_v + sc.vec_base, v, sizeof(float) * pt.n, hipMemcpyHostToDevice, ctx->stream), "H2D");
+  PassArgs pa = ctx->pass_args(precision == ADMM_PREC_FP32 ? ctx->mat32 : ctx->matlp);
+  pa.src = ctx->d_v;
+  pa.src_per_scen = 1;
+  pa.objpart = nullptr;
+  launch_pass(PASS_CG, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+  VecArgs va = ctx->vec_args(0);
+  va.out = ctx->d_pvec2 + pt.zvec_base;
+  va.rho_out = ctx->rho[patient];
+  launch_reduce(RED_NORMAL, va, sc.blk_begin, sc.nblk, ctx->stream);
+  check(hipMemcpyAsync(out, va.out, sizeof(float) * pt.n, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, const double* x0, double* x_out,
+                      admm_info* info) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  pgd_options o;
+  pgd_default_options(&o);
+  if (popts) o = *popts;
+  if (!(o.beta > 0 && o.beta < 1) || !(o.gamma > 0 && o.gamma < 1) || o.max_trials < 1 || o.max_iter < 0 ||
+      !(o.obj_rel_tol >= 0) || !std::isfinite(o.alpha))
+    return set_err(ctx, ADMM_E_ARG, "invalid PGD options");
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  const int n = pt.n;
+  float* x = ctx->d_pvec + pt.zvec_base;
+  float* g = ctx->d_pvec2 + pt.zvec_base;
+  float* xt = ctx->d_pvec3 + pt.zvec_base;
+  const float* lb = ctx->d_lb + pt.zvec_base;
+  const float* ub = ctx->d_ub + pt.zvec_base;
+  hipStream_t s = ctx->stream;
+  double alpha = o.alpha;
+  if (!(alpha > 0)) {
+    // largest eigenvalue of H = 2 sum_s A_s^T c_s W A_s by power iteration
+    std::vector<float> v(n, static_cast<float>(1.0 / std::sqrt(static_cast<double>(n))));
+    double lam = 0.0;
+    for (int it = 0; it < 30; ++it) {
+      check(hipMemcpyAsync(xt, v.data(), sizeof(float) * n, hipMemcpyHostToDevice, s), "H2D");
+      PassArgs pa = ctx->pass_args(ctx->mat32);
+      pa.src = ctx->d_pvec3;
+      pa.src_per_scen = 0;
+      pa.objpart = nullptr;
+      launch_pass(PASS_CG, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, s);
+      launch_gsum(ctx->d_scen, ctx->d_pat, ctx->d_pblk, ctx->d_tiles, ctx->d_part, pt.blk_begin, pt.nblk, 2.0f, g, s);
+      check(hipMemcpyAsync(v.data(), g, sizeof(float) * n, hipMemcpyDeviceToHost, s), "D2H");
+      check(hipStreamSynchronize(s), "sync");
+      double nrm = 0.0;
+      for (float e : v) nrm += static_cast<double>(e) * e;
+      nrm = std::sqrt(nrm);
+      lam = nrm;
+      if (!(nrm > 0)) break;
+      for (float& e : v) e = static_cast<float>(e / nrm);
+    }
+    alpha = lam > 0 ? 10.0 / lam : 1.0;
+  }
+  std::vector<double> x0v(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double v = x0 ? x0[j] : 0.0;
+    x0v[j] = std::min(std::max(v, static_cast<double>(ctx->H.lb[pt.zvec_base + j])),
+                      static_cast<double>(ctx->H.ub[pt.zvec_base + j]));
+  }
+  ctx->upload_pvec(patient, x0v.data(), ctx->d_pvec);
+  double f = ctx->objective_dev(patient, g);
+  const int nb = (n + kThreads - 1) / kThreads;
+  int iters = 0;
+  bool converged = false, failed = false;
+  for (int k = 0; k < o.max_iter; ++k) {
+    double t = alpha;
+    bool accepted = false;
+    double ft = 0.0;
+    for (int trial = 0; trial < o.max_trials; ++trial) {
+      launch_pgd_trial(x, g, lb, ub, static_cast<float>(t), xt, n, ctx->d_scratch + 8, s);
+      launch_dot_sum(ctx->d_scratch + 8, nb, ctx->d_scratch + 1, s);
+      PassArgs pa = ctx->pass_args(ctx->mat32);
+      pa.src = ctx->d_pvec3;
+      pa.src_per_scen = 0;
+      pa.part = nullptr;  // objective only
+      launch_pass(PASS_OBJ, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, s);
+      launch_objsum(ctx->d_tiles, ctx->d_objpart, pt.tile_begin, pt.tile_end - pt.tile_begin, ctx->d_scratch, s);
+      check(hipMemcpyAsync(ctx->h_scr, ctx->d_scratch, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+      check(hipStreamSynchronize(s), "sync");
+      ft = ctx->h_scr[0] + pt.fzero;
+      const double gd = ctx->h_scr[1];
+      if (ft <= f + o.beta * gd) {
+        accepted = true;
+        break;
+      }
+      t *= o.gamma;
+    }
+    iters = k + 1;
+    if (!accepted) {
+      failed = true;
+      break;
+    }
+    check(hipMemcpyAsync(x, xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s), "D2D");
+    const double f_old = f;
+    f = ctx->objective_dev(patient, g);
+    if (std::fabs(f_old - f) <= o.obj_rel_tol * std::fabs(f_old)) {
+      converged = true;
+      break;
+    }
+  }
+  if (x_out) {
+    std::vector<float> xv(n);
+    check(hipMemcpy(xv.data(), x, sizeof(float) * n, hipMemcpyDeviceToHost), "D2H");
+    for (int j = 0; j < n; ++j) x_out[j] = xv[j];
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->iter = iters;
+    info->obj = f;
+    info->tau = alpha;
+    info->status = converged ? ADMM_OK : ADMM_MAX_ITER;
+  }
+  (void)failed;
+  return converged ? ADMM_OK : ADMM_MAX_ITER;
+  GUARD_END(ctx)
+}
+
+admm_status admm_get_state(admm_ctx* ctx, int32_t patient, double* z, double* y, double* d, double* scalars) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  const int64_t len = static_cast<int64_t>(pt.num_scen) * pt.n;
+  const int64_t base = ctx->H.scen[pt.scen_begin].vec_base;
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  if (z) {
+    std::vector<float> v(pt.n);
+    check(hipMemcpy(v.data(), ctx->d_z + pt.zvec_base, sizeof(float) * pt.n, hipMemcpyDeviceToHost), "D2H");
+    for (int j = 0; j < pt.n; ++j) z[j] = v[j];
+  }
+  if (y) {
+    std::vector<float> v(len);
+    check(hipMemcpy(v.data(), ctx->d_y + base, sizeof(float) * len, hipMemcpyDeviceToHost), "D2H");
+    for (int64_t j = 0; j < len; ++j) y[j] = v[j];
+  }
+  if (d) check(hipMemcpy(d, ctx->d_dprev + base, sizeof(double) * len, hipMemcpyDeviceToHost), "D2H");
+  if (scalars) {
+    ctx->read_state();
+    const PatState& s = ctx->h_ps[patient];
+    scalars[0] = s.iter;
+    scalars[1] = s.tau;
+    scalars[2] = s.f_prev;
+    scalars[3] = s.pending;
+    scalars[4] = s.stopped;
+    scalars[5] = s.status;
+    scalars[6] = s.rho;
+    scalars[7] = s.cg_total;
+  }
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, const double* y, const double* d,
+                           const double* scalars) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!z || !y || !d || !scalars) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  const Pat& pt = ctx->H.pat[patient];
+  const int64_t len = static_cast<int64_t>(pt.num_scen) * pt.n;
+  for (int64_t j = 0; j < len; ++j)
+    if (!std::isfinite(y[j]) || !std::isfinite(d[j])) return set_err(ctx, ADMM_E_NONFINITE, "state not finite");
+  if (scalars[6] > 0 && scalars[6] != ctx->rho[patient] && ctx->opts.precond)
+    return set_err(ctx, ADMM_E_STATE, "rho differs from the preconditioner's");
+  GUARD_BEGIN
+  const int64_t base = ctx->H.scen[pt.scen_begin].vec_base;
+  std::vector<float> zf(pt.n), yf(len);
+  for (int j = 0; j < pt.n; ++j) zf[j] = static_cast<float>(z[j]);
+  for (int64_t j = 0; j < len; ++j) yf[j] = static_cast<float>(y[j]);
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  check(hipMemcpy(ctx->d_z + pt.zvec_base, zf.data(), sizeof(float) * pt.n, hipMemcpyHostToDevice), "H2D");
+  check(hipMemcpy(ctx->d_y + base, yf.data(), sizeof(float) * len, hipMemcpyHostToDevice), "H2D");
+  check(hipMemcpy(ctx->d_dprev + base, d, sizeof(double) * len, hipMemcpyHostToDevice), "H2D");
+  if (scalars[6] > 0) ctx->rho[patient] = scalars[6];
+  PatState s{};
+  s.iter = static_cast<int32_t>(scalars[0]);
+  s.tau = scalars[1];
+  s.f_prev = scalars[2];
+  s.pending = static_cast<int32_t>(scalars[3]);
+  s.stopped = static_cast<int32_t>(scalars[4]);
+  s.status = static_cast<int32_t>(scalars[5]);
+  s.rho = ctx->rho[patient];
+  s.cg_total = static_cast<int32_t>(scalars[7]);
+  ctx->h_ps[patient] = s;
+  check(hipMemcpy(ctx->d_ps + patient, &s, sizeof(PatState), hipMemcpyHostToDevice), "H2D");
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_get_trace(admm_ctx* ctx, int32_t patient, admm_info* buf, int32_t cap, int32_t* count) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!buf || cap < 0) return set_err(ctx, ADMM_E_ARG, "bad buffer");
+  GUARD_BEGIN
+  ctx->read_state();
+  const int have = std::min(ctx->h_ps[patient].iter, ctx->trace_cap);
+  const int k = std::min(have, cap);
+  std::vector<IterRecord> rec(static_cast<size_t>(std::max(k, 1)));
+  if (k > 0)
+    check(hipMemcpy(rec.data(), ctx->d_trace + static_cast<int64_t>(patient) * ctx->trace_cap,
+                    sizeof(IterRecord) * k, hipMemcpyDeviceToHost),
+          "D2H");
+  for (int i = 0; i < k; ++i) {
+    std::memset(&buf[i], 0, sizeof(admm_info));
+    buf[i].iter = rec[i].iter;
+    buf[i].cg_steps = rec[i].cg_steps;
+    buf[i].obj = rec[i].obj;
+    buf[i].r_prim = rec[i].r_prim;
+    buf[i].r_dual = rec[i].r_dual;
+    buf[i].eps_prim = rec[i].eps_prim;
+    buf[i].eps_dual = rec[i].eps_dual;
+    buf[i].tau = rec[i].tau;
+  }
+  if (count) *count = k;
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+}  // extern "C"

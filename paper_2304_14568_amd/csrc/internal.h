@@ -1,0 +1,181 @@
+// Device-side tables and launch interfaces shared by the host runtime and the
+// gfx950 kernels.  Plain structs only; no torch or HIP types in here except
+// hipStream_t in the launcher declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace admmbb {
+
+constexpr int kThreads = 256;       // threads per workgroup, all kernels
+constexpr int kColBlock = 256;      // columns handled by one block of a vector kernel
+constexpr int kMaxCg = 64;          // CG steps per ADMM iteration, upper limit
+constexpr int kRing = kMaxCg + 2;   // per-scenario CG scalar slots
+constexpr int kRegChunks = 4;       // nonzeros of a row kept in registers per lane
+
+enum PassMode { PASS_GRAD = 0, PASS_CG = 1, PASS_OBJ = 2, PASS_MATVEC = 3, PASS_RMATVEC = 4 };
+enum ValKind { VAL_F32 = 0, VAL_BF16 = 1, VAL_F16 = 2 };
+enum RedMode { RED_HEAD = 0, RED_CG = 1, RED_NORMAL = 2, RED_RMAT = 3 };
+
+// One per (patient, scenario).
+struct Scen {
+  int32_t patient;
+  int32_t n;            // spots of the patient
+  int32_t m;            // voxels of the patient
+  int32_t rows;         // rows holding at least one nonzero (length-sorted)
+  int64_t row_base;     // into per-row arrays (rw, rpres, rorig, rscale)
+  int64_t rp_base;      // into rp (rows + 1 entries per scenario)
+  int64_t nnz_base;     // into col / val arrays
+  int64_t vec_base;     // into the stacked per-scenario n-vectors
+  int32_t blk_begin;    // first scenario column block
+  int32_t nblk;
+  int32_t tile_begin, tile_end;
+  float cw;             // scenario probability c_s (already folded into rw)
+  int32_t pad;
+};
+
+// One per patient.
+struct Pat {
+  int32_t n, m;
+  int32_t num_scen, scen_begin;
+  int32_t blk_begin, nblk;      // patient column blocks (z kernels)
+  int32_t tile_begin, tile_end; // tiles of all its scenarios (contiguous)
+  int64_t zvec_base;            // into per-patient n-vectors (z, lb, ub, dinv-free)
+  double fzero;                 // sum_s c_s sum_{i: row i of A_s empty} w_i p_i^2 (objective of dropped rows)
+};
+
+// A contiguous range of length-sorted rows of one scenario, handled by one
+// workgroup with `lanes` lanes per row.
+struct Tile {
+  int32_t scen;
+  int32_t row_begin, row_end;
+  int32_t lanes;
+  int64_t part_off;   // offset of this tile's n-vector of partial column sums
+};
+
+// Column block of a scenario (owner = scenario) or of a patient (owner = patient).
+struct Blk {
+  int32_t owner;
+  int32_t col0;
+};
+
+// Per-patient scalars living on the device.
+struct PatState {
+  double rho;
+  double tau;          // dual step used by the pending dual update
+  double f_prev;       // objective at the previous z
+  double f_cur;
+  double r_prim, r_dual, eps_prim, eps_dual;
+  double xnorm, znorm;
+  int32_t iter;        // completed ADMM iterations
+  int32_t pending;     // body done: the next head completes the dual update and the stop test
+  int32_t stopped;
+  int32_t status;      // 0 running, 1 converged, 2 diverged (non-finite)
+  int32_t cg_steps;    // CG steps (summed over scenarios) of the last iteration
+  int32_t cg_total;
+};
+
+struct IterRecord {
+  int32_t iter;
+  int32_t cg_steps;
+  double obj, r_prim, r_dual, eps_prim, eps_dual, tau;
+};
+
+struct AlgoParams {
+  double eps_abs, eps_rel, obj_rel_tol;
+  double bb_clamp;
+  double eta_factor, eta_floor;
+  int32_t bb;
+  int32_t z_mode;
+  int32_t stop_enabled;
+  int32_t precond;
+  int32_t trace_cap;
+  int32_t num_pat;
+};
+
+// Matrix storage of all (patient, scenario) pairs, length-sorted rows.
+struct MatDev {
+  const uint32_t* rp;      // row start offsets relative to nnz_base
+  const void* col;         // uint16 (n <= 65535) or int32 column indices
+  const void* val;         // float / bf16 bits / fp16 values
+  const float* rscale;     // per-row scale for low-precision values (nullptr for fp32)
+  const float* rw;         // c_s * w_i per sorted row
+  const float* rpres;      // p_i per sorted row
+  const int32_t* rorig;    // original row index per sorted row
+  int32_t col16;           // 1 when col holds uint16
+  int32_t vkind;           // ValKind
+};
+
+struct PassArgs {
+  const Tile* tiles;
+  const Scen* scen;
+  const Pat* pat;
+  MatDev mat;
+  const float* src;        // multiplied vector: per scenario (src + vec_base) or per patient (src + zvec_base)
+  int32_t src_per_scen;
+  int32_t step;            // CG step (selects the active flag slot)
+  const uint8_t* act;      // [scen * kRing + step], nullptr = all active
+  const PatState* ps;      // skip stopped patients when non-null
+  float* part;             // tile partial column sums
+  double* objpart;         // per-tile objective partial (GRAD / OBJ)
+  const float* tin;        // RMATVEC input (m-vector of the scenario)
+  float* tout;             // MATVEC output (m-vector of the scenario)
+  int32_t nmax;
+  int32_t acc64;           // 1: LDS column accumulators in double
+};
+
+struct VecArgs {
+  const Scen* scen;
+  const Pat* pat;
+  const Blk* blk;           // scenario column blocks
+  const Blk* pblk;          // patient column blocks
+  const Tile* tiles;
+  const float* part;
+  const double* objpart;
+  PatState* ps;
+  int32_t step;
+  uint8_t* act;            // [scen * kRing + k]
+  double* rz;              // [scen * kRing + k]
+  double* tol2;            // [scen]
+  int32_t* cgcount;        // [scen]
+  float* x;
+  float* r;
+  float* v;
+  float* q;
+  float* zp;               // preconditioned residual (== r when no preconditioner)
+  float* y;
+  const float* b;          // A_s^T c_s W p
+  const float* dinv;       // Jacobi inverse diagonal (per scenario), may be null
+  float* z;                // per patient
+  const float* lb;
+  const float* ub;
+  double* dprev;           // d = x - z of the last iteration (stacked, fp64)
+  double* bpart;           // per scenario-block partials [blk * 8 + k]
+  double* bpartp;          // per patient-block partials [pblk * 8 + k]
+  float* out;              // RMAT / NORMAL output vector (n)
+  double rho_out;          // NORMAL: diagonal shift rho/2 * v added when > 0
+  AlgoParams prm;
+  IterRecord* trace;
+};
+
+// ---- launchers (kernels.hip) ----
+void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hipStream_t st);
+void launch_reduce(int mode, const VecArgs& a, int blk_begin, int nblk, hipStream_t st);
+void launch_head_scalars(const VecArgs& a, int nscen, int cg_setup, hipStream_t st);
+void launch_cg_update(const VecArgs& a, int nblk, hipStream_t st);
+void launch_cg_dir(const VecArgs& a, int nblk, hipStream_t st);
+void launch_zres(const VecArgs& a, int npblk, hipStream_t st);
+void launch_body_scalars(const VecArgs& a, hipStream_t st);
+void launch_gsum(const Scen* scen, const Pat* pat, const Blk* pblk, const Tile* tiles, const float* part,
+                 int patient_blk_begin, int nblk, float scale, float* out, hipStream_t st);
+void launch_objsum(const Tile* tiles, const double* objpart, int tile_begin, int tile_count, double* out,
+                   hipStream_t st);
+void launch_pgd_trial(const float* x, const float* g, const float* lb, const float* ub, float t, float* xt,
+                      int n, double* dotpart, hipStream_t st);
+void launch_dot_sum(const double* part, int count, double* out, hipStream_t st);
+void launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
+void launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
+void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st);
+int pass_smem_bytes(int nmax, int acc64);
+
+}  // namespace admmbb

@@ -1,0 +1,690 @@
+// gfx950 kernels for ADMM-BB robust planning.
+//
+// The hot kernel is k_pass: one streaming pass over the length-sorted CSR of
+// every (patient, scenario) dose-influence matrix A_s.  For each row i it forms
+// the row dot a_i . v, turns it into t_i (c_s w_i a_i.v for a CG product,
+// c_s w_i (a_i.v - p_i) for the gradient / objective), and immediately scatters
+// t_i a_i into column accumulators held in LDS.  The row's values and column
+// indices stay in registers between the two uses, so each nonzero is read from
+// HBM once per operator application A_s^T diag(c_s w) A_s v (the x-update
+// system of Appendix A without its rho/2 shift).  Each workgroup writes its
+// column partial sums; a column-blocked reduction kernel adds them in a fixed
+// order.  All scalar reductions are float64 and deterministic (fixed trees).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace admmbb {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+template <int VK>
+struct ValT;
+template <>
+struct ValT<VAL_F32> {
+  using T = float;
+  static __device__ __forceinline__ float f(T v) { return v; }
+};
+template <>
+struct ValT<VAL_BF16> {
+  using T = uint16_t;
+  static __device__ __forceinline__ float f(T v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+};
+template <>
+struct ValT<VAL_F16> {
+  using T = _Float16;
+  static __device__ __forceinline__ float f(T v) { return static_cast<float>(v); }
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// Deterministic block sum of NV doubles; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = (sh[k] + sh[NV + k]) + (sh[2 * NV + k] + sh[3 * NV + k]);
+  }
+  __syncthreads();
+}
+
+// Block sum of a strided list: thread i adds items i, i+256, ... in order,
+// then a fixed tree.  Deterministic for a given count.
+template <class F>
+__device__ __forceinline__ double block_list_sum(int count, F item, double* sh) {
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < count; i += kThreads) v[0] += item(i);
+  block_sum<1>(v, sh);
+  return v[0];
+}
+
+// ---------------------------------------------------------------------------
+// the fused pass
+// ---------------------------------------------------------------------------
+
+template <int VK, bool C16, int L, int MODE>
+__device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, const Scen& sc, float* vsh,
+                                          float* qf, double* qd, bool acc64, bool scatter, double& objacc) {
+  using V = ValT<VK>;
+  using VT = typename V::T;
+  using CT = std::conditional_t<C16, uint16_t, int32_t>;
+  using DACC = std::conditional_t<MODE == PASS_GRAD, double, float>;
+  constexpr int K = kRegChunks;
+  constexpr int G = kThreads / L;
+  const int grp = threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  const uint32_t* __restrict__ rp = a.mat.rp + sc.rp_base;
+  const CT* __restrict__ col = static_cast<const CT*>(a.mat.col) + sc.nnz_base;
+  const VT* __restrict__ val = static_cast<const VT*>(a.mat.val) + sc.nnz_base;
+  const int64_t rb = sc.row_base;
+  const bool given_t = (MODE == PASS_CG) && (a.tin != nullptr);
+
+  for (int r = t.row_begin + grp; r < t.row_end; r += G) {
+    const uint32_t s = rp[r], e = rp[r + 1];
+    float vv[K];
+    int cc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t i = s + lane + k * L;
+      if (i < e) {
+        vv[k] = V::f(val[i]);
+        cc[k] = static_cast<int>(col[i]);
+      } else {
+        vv[k] = 0.0f;
+        cc[k] = 0;
+      }
+    }
+    float tv;
+    if (given_t) {
+      tv = a.tin[a.mat.rorig[rb + r]];
+    } else {
+      DACC dot = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if constexpr (MODE == PASS_GRAD)
+          dot += static_cast<double>(vv[k]) * static_cast<double>(vsh[cc[k]]);
+        else
+          dot = fmaf(vv[k], vsh[cc[k]], dot);
+      }
+      for (uint32_t i = s + lane + K * L; i < e; i += L) {
+        const float av = V::f(val[i]);
+        const float xv = vsh[static_cast<int>(col[i])];
+        if constexpr (MODE == PASS_GRAD)
+          dot += static_cast<double>(av) * static_cast<double>(xv);
+        else
+          dot = fmaf(av, xv, dot);
+      }
+#pragma unroll
+      for (int off = L / 2; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+      if constexpr (MODE == PASS_GRAD) {
+        if (a.tout != nullptr) {
+          if (lane == 0) a.tout[a.mat.rorig[rb + r]] = static_cast<float>(dot);
+          continue;
+        }
+        const double res = dot - static_cast<double>(a.mat.rpres[rb + r]);
+        const double wgt = static_cast<double>(a.mat.rw[rb + r]);
+        if (lane == 0) objacc += wgt * res * res;
+        tv = static_cast<float>(wgt * res);
+      } else {
+        float scl = 1.0f;
+        if (a.mat.rscale != nullptr) scl = a.mat.rscale[rb + r];
+        tv = a.mat.rw[rb + r] * dot * scl * scl;
+      }
+    }
+    if (!scatter) continue;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t i = s + lane + k * L;
+      if (i < e) {
+        const float c = tv * vv[k];
+        if (acc64)
+          atomicAdd(&qd[cc[k]], static_cast<double>(c));
+        else
+          atomicAdd(&qf[cc[k]], c);
+      }
+    }
+    for (uint32_t i = s + lane + K * L; i < e; i += L) {
+      const float c = tv * V::f(val[i]);
+      const int j = static_cast<int>(col[i]);
+      if (acc64)
+        atomicAdd(&qd[j], static_cast<double>(c));
+      else
+        atomicAdd(&qf[j], c);
+    }
+  }
+}
+
+template <int VK, bool C16, int MODE>
+__global__ __launch_bounds__(kThreads) void k_pass(PassArgs a, int tile_begin) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ti = tile_begin + static_cast<int>(blockIdx.x);
+  const Tile t = a.tiles[ti];
+  const Scen sc = a.scen[t.scen];
+  if (a.act != nullptr && !a.act[t.scen * kRing + a.step]) return;
+  if (a.ps != nullptr && a.ps[sc.patient].stopped) return;
+  const int n = sc.n;
+  float* vsh = reinterpret_cast<float*>(smem);
+  const size_t qoff = (static_cast<size_t>(a.nmax) * 4 + 15) & ~static_cast<size_t>(15);
+  float* qf = reinterpret_cast<float*>(smem + qoff);
+  double* qd = reinterpret_cast<double*>(smem + qoff);
+  const bool acc64 = a.acc64 != 0;
+  bool scatter;
+  if constexpr (MODE == PASS_GRAD)
+    scatter = (a.tout == nullptr) && (a.part != nullptr);
+  else
+    scatter = true;
+  const bool given_t = (MODE == PASS_CG) && (a.tin != nullptr);
+
+  if (!given_t) {
+    const float* src = a.src + (a.src_per_scen ? sc.vec_base : a.pat[sc.patient].zvec_base);
+    for (int j = threadIdx.x; j < n; j += kThreads) vsh[j] = src[j];
+  }
+  if (scatter) {
+    if (acc64)
+      for (int j = threadIdx.x; j < n; j += kThreads) qd[j] = 0.0;
+    else
+      for (int j = threadIdx.x; j < n; j += kThreads) qf[j] = 0.0f;
+  }
+  __syncthreads();
+
+  double objacc = 0.0;
+  switch (t.lanes) {
+    case 1: pass_rows<VK, C16, 1, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+    case 2: pass_rows<VK, C16, 2, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+    case 4: pass_rows<VK, C16, 4, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+    case 8: pass_rows<VK, C16, 8, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+    case 16: pass_rows<VK, C16, 16, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+    case 32: pass_rows<VK, C16, 32, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+    default: pass_rows<VK, C16, 64, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+  }
+
+  if (MODE == PASS_GRAD && a.objpart != nullptr) {
+    __shared__ double sh[4];
+    double v[1] = {objacc};
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) a.objpart[ti] = v[0];
+  } else {
+    __syncthreads();
+  }
+  if (scatter) {
+    float* out = a.part + t.part_off;
+    if (acc64)
+      for (int j = threadIdx.x; j < n; j += kThreads) out[j] = static_cast<float>(qd[j]);
+    else
+      for (int j = threadIdx.x; j < n; j += kThreads) out[j] = qf[j];
+  }
+}
+
+int pass_smem_bytes(int nmax, int acc64) {
+  const int qoff = (nmax * 4 + 15) & ~15;
+  return qoff + nmax * (acc64 ? 8 : 4);
+}
+
+template <int VK, bool C16, int MODE>
+static void launch_pass_t(const PassArgs& a, int tile_begin, int tile_count, hipStream_t st) {
+  const int smem = pass_smem_bytes(a.nmax, a.acc64);
+  auto kern = k_pass<VK, C16, MODE>;
+  static bool attr_done = false;
+  if (!attr_done && smem > 65536) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              163840);
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(tile_count), dim3(kThreads), smem, st, a, tile_begin);
+}
+
+void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hipStream_t st) {
+  if (tile_count <= 0) return;
+  const bool c16 = a.mat.col16 != 0;
+  const bool grad = (mode == PASS_GRAD || mode == PASS_OBJ || mode == PASS_MATVEC);
+  if (grad) {
+    if (c16)
+      launch_pass_t<VAL_F32, true, PASS_GRAD>(a, tile_begin, tile_count, st);
+    else
+      launch_pass_t<VAL_F32, false, PASS_GRAD>(a, tile_begin, tile_count, st);
+    return;
+  }
+  switch (a.mat.vkind) {
+    case VAL_BF16:
+      if (c16)
+        launch_pass_t<VAL_BF16, true, PASS_CG>(a, tile_begin, tile_count, st);
+      else
+        launch_pass_t<VAL_BF16, false, PASS_CG>(a, tile_begin, tile_count, st);
+      break;
+    case VAL_F16:
+      if (c16)
+        launch_pass_t<VAL_F16, true, PASS_CG>(a, tile_begin, tile_count, st);
+      else
+        launch_pass_t<VAL_F16, false, PASS_CG>(a, tile_begin, tile_count, st);
+      break;
+    default:
+      if (c16)
+        launch_pass_t<VAL_F32, true, PASS_CG>(a, tile_begin, tile_count, st);
+      else
+        launch_pass_t<VAL_F32, false, PASS_CG>(a, tile_begin, tile_count, st);
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column reduction of the tile partials, fused with the vector work that
+// needs the completed column sums
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, int mode) {
+  __shared__ double sh[4 * 3];
+  const int bi = blk_begin + static_cast<int>(blockIdx.x);
+  const Blk bk = a.blk[bi];
+  const int g = bk.owner;
+  const Scen sc = a.scen[g];
+  const Pat pt = a.pat[sc.patient];
+  PatState* ps = a.ps + sc.patient;
+  if (mode == RED_HEAD || mode == RED_CG) {
+    if (ps->stopped) return;
+    if (mode == RED_CG && !a.act[g * kRing + a.step]) return;
+  }
+  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  double loc[3] = {0.0, 0.0, 0.0};
+  if (j < sc.n) {
+    double s = 0.0;
+    for (int t = sc.tile_begin; t < sc.tile_end; ++t) s += static_cast<double>(a.part[a.tiles[t].part_off + j]);
+    const int64_t vi = sc.vec_base + j;
+    if (mode == RED_HEAD) {
+      const double rho = ps->rho;
+      float yv = a.y[vi];
+      if (ps->pending) {
+        yv = static_cast<float>(static_cast<double>(yv) + ps->tau * a.dprev[vi]);
+        a.y[vi] = yv;
+      }
+      const float zj = a.z[pt.zvec_base + j];
+      // residual of B_s x = c_s at x = z:  c_s - B_s z = -A_s^T c_s W (A_s z - p) - y_s / 2
+      const float rf = static_cast<float>(-s - 0.5 * static_cast<double>(yv));
+      a.r[vi] = rf;
+      a.x[vi] = zj;
+      float zpv = rf;
+      if (a.dinv != nullptr) {
+        zpv = rf * a.dinv[vi];
+        a.zp[vi] = zpv;
+      }
+      a.v[vi] = zpv;
+      const double c = static_cast<double>(a.b[vi]) + 0.5 * rho * zj - 0.5 * static_cast<double>(yv);
+      loc[0] = static_cast<double>(rf) * zpv;
+      loc[1] = c * c;
+      loc[2] = static_cast<double>(yv) * yv;
+    } else if (mode == RED_CG) {
+      const float vj = a.v[vi];
+      const float qj = static_cast<float>(s + 0.5 * ps->rho * vj);
+      a.q[vi] = qj;
+      loc[0] = static_cast<double>(vj) * qj;
+    } else if (mode == RED_NORMAL) {
+      a.out[j] = static_cast<float>(s + 0.5 * a.rho_out * a.v[vi]);
+    } else {
+      a.out[j] = static_cast<float>(s);
+    }
+  }
+  if (mode == RED_HEAD || mode == RED_CG) {
+    block_sum<3>(loc, sh);
+    if (threadIdx.x == 0) {
+      double* bp = a.bpart + static_cast<int64_t>(bi) * 8;
+      bp[0] = loc[0];
+      bp[1] = loc[1];
+      bp[2] = loc[2];
+    }
+  }
+}
+
+void launch_reduce(int mode, const VecArgs& a, int blk_begin, int nblk, hipStream_t st) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(kThreads), 0, st, a, blk_begin, mode);
+}
+
+// ---------------------------------------------------------------------------
+// head scalars: objective at z, completion of the previous iteration
+// (dual-update norm, trace record, stopping test) and CG set-up
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_head_scalars(VecArgs a, int nscen, int cg_setup) {
+  __shared__ double sh[4];
+  const AlgoParams& P = a.prm;
+  for (int p = 0; p < P.num_pat; ++p) {
+    const Pat pt = a.pat[p];
+    PatState* ps = a.ps + p;
+    if (ps->stopped) continue;  // uniform
+    const double f = pt.fzero + block_list_sum(pt.tile_end - pt.tile_begin,
+                                               [&](int i) { return a.objpart[pt.tile_begin + i]; }, sh);
+    const int sb0 = a.scen[pt.scen_begin].blk_begin;
+    const Scen last = a.scen[pt.scen_begin + pt.num_scen - 1];
+    const int sb1 = last.blk_begin + last.nblk;
+    const double yy = block_list_sum(sb1 - sb0, [&](int i) { return a.bpart[(int64_t)(sb0 + i) * 8 + 2]; }, sh);
+    if (threadIdx.x == 0) {
+      ps->f_cur = f;
+      if (ps->pending) {
+        const int N = pt.num_scen;
+        const double base = P.eps_abs * sqrt(static_cast<double>(N) * pt.n);
+        ps->eps_dual = base + P.eps_rel * sqrt(yy);
+        const int k = ps->iter;  // iterations completed, >= 1
+        if (a.trace != nullptr && k - 1 < P.trace_cap) {
+          IterRecord rec;
+          rec.iter = k;
+          rec.cg_steps = ps->cg_steps;
+          rec.obj = f;
+          rec.r_prim = ps->r_prim;
+          rec.r_dual = ps->r_dual;
+          rec.eps_prim = ps->eps_prim;
+          rec.eps_dual = ps->eps_dual;
+          rec.tau = ps->tau;
+          a.trace[static_cast<int64_t>(p) * P.trace_cap + (k - 1)] = rec;
+        }
+        if (!isfinite(f) || !isfinite(ps->r_prim)) {
+          ps->stopped = 1;
+          ps->status = 2;
+        } else if (P.stop_enabled) {
+          bool obj_ok = true;
+          if (P.obj_rel_tol > 0.0) obj_ok = (k >= 2) && fabs(f - ps->f_prev) <= P.obj_rel_tol * fabs(ps->f_prev);
+          if (ps->r_prim <= ps->eps_prim && ps->r_dual <= ps->eps_dual && obj_ok) {
+            ps->stopped = 1;
+            ps->status = 1;
+          }
+        }
+        ps->pending = 0;
+      }
+      ps->f_prev = f;
+    }
+    __syncthreads();
+  }
+  if (!cg_setup) return;
+  // per-scenario CG set-up: one thread per scenario, fixed-order sums over its blocks
+  for (int g = threadIdx.x; g < nscen; g += kThreads) {
+    const Scen sc = a.scen[g];
+    const PatState* ps = a.ps + sc.patient;
+    double rz0 = 0.0, cc = 0.0;
+    for (int b = 0; b < sc.nblk; ++b) {
+      rz0 += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 0];
+      cc += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 1];
+    }
+    double eta = P.eta_factor;
+    if (ps->iter > 0) {
+      const double rel = ps->r_prim / fmax(ps->xnorm, 1e-30);
+      eta = fmax(P.eta_floor, P.eta_factor * fmin(1.0, rel));
+    }
+    const double tol2 = eta * eta * cc;
+    a.tol2[g] = tol2;
+    a.rz[g * kRing + 0] = rz0;
+    a.act[g * kRing + 0] = (!ps->stopped && rz0 > tol2 && rz0 > 0.0) ? 1 : 0;
+    a.cgcount[g] = 0;
+  }
+}
+
+void launch_head_scalars(const VecArgs& a, int nscen, int cg_setup, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_scalars, dim3(1), dim3(kThreads), 0, st, a, nscen, cg_setup);
+}
+
+// ---------------------------------------------------------------------------
+// CG vector steps
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_cg_update(VecArgs a) {
+  __shared__ double sh[4];
+  const int bi = static_cast<int>(blockIdx.x);
+  const Blk bk = a.blk[bi];
+  const int g = bk.owner;
+  const Scen sc = a.scen[g];
+  if (!a.act[g * kRing + a.step]) return;
+  double vq = 0.0;
+  for (int b = 0; b < sc.nblk; ++b) vq += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 0];
+  const double rz = a.rz[g * kRing + a.step];
+  const float alpha = (vq > 0.0) ? static_cast<float>(rz / vq) : 0.0f;
+  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  double loc[1] = {0.0};
+  if (j < sc.n) {
+    const int64_t vi = sc.vec_base + j;
+    const float vj = a.v[vi];
+    a.x[vi] = fmaf(alpha, vj, a.x[vi]);
+    const float rj = fmaf(-alpha, a.q[vi], a.r[vi]);
+    a.r[vi] = rj;
+    float zpv = rj;
+    if (a.dinv != nullptr) {
+      zpv = rj * a.dinv[vi];
+      a.zp[vi] = zpv;
+    }
+    loc[0] = static_cast<double>(rj) * zpv;
+  }
+  block_sum<1>(loc, sh);
+  if (threadIdx.x == 0) a.bpart[(int64_t)bi * 8 + 3] = loc[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_dir(VecArgs a) {
+  const int bi = static_cast<int>(blockIdx.x);
+  const Blk bk = a.blk[bi];
+  const int g = bk.owner;
+  const Scen sc = a.scen[g];
+  const int k = a.step;
+  if (!a.act[g * kRing + k]) {
+    if (threadIdx.x == 0) a.act[g * kRing + k + 1] = 0;
+    return;
+  }
+  double rz1 = 0.0;
+  for (int b = 0; b < sc.nblk; ++b) rz1 += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 3];
+  const double rz0 = a.rz[g * kRing + k];
+  const float beta = (rz0 > 0.0) ? static_cast<float>(rz1 / rz0) : 0.0f;
+  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  if (j < sc.n) {
+    const int64_t vi = sc.vec_base + j;
+    const float zpv = (a.dinv != nullptr) ? a.zp[vi] : a.r[vi];
+    a.v[vi] = fmaf(beta, a.v[vi], zpv);
+  }
+  if (threadIdx.x == 0) {
+    // every block of the scenario writes the same values
+    a.rz[g * kRing + k + 1] = rz1;
+    a.act[g * kRing + k + 1] = (rz1 > a.tol2[g] && rz1 > 0.0) ? 1 : 0;
+    if (bk.col0 == 0) a.cgcount[g] += 1;
+  }
+}
+
+void launch_cg_update(const VecArgs& a, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kThreads), 0, st, a);
+}
+void launch_cg_dir(const VecArgs& a, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(nblk), dim3(kThreads), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// z-update and residual / BB partial sums, one patient column block per
+// workgroup (every quantity is columnwise until the final sums)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
+  __shared__ double sh[4 * 6];
+  const int bi = static_cast<int>(blockIdx.x);
+  const Blk bk = a.pblk[bi];
+  const int p = bk.owner;
+  const Pat pt = a.pat[p];
+  const PatState* ps = a.ps + p;
+  if (ps->stopped) return;
+  const double rho = ps->rho;
+  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  double loc[6] = {0, 0, 0, 0, 0, 0};  // ||dz||^2, ||z||^2, ||d||^2, <dd,d_prev>, ||dd||^2, ||x||^2
+  if (j < pt.n) {
+    double acc = 0.0;
+    for (int s = 0; s < pt.num_scen; ++s) {
+      const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
+      acc += static_cast<double>(a.x[vi]);
+      if (a.prm.z_mode == 0) acc += static_cast<double>(a.y[vi]) / rho;
+    }
+    const int64_t zi = pt.zvec_base + j;
+    double zn = acc / pt.num_scen;
+    zn = fmin(fmax(zn, static_cast<double>(a.lb[zi])), static_cast<double>(a.ub[zi]));
+    const float znf = static_cast<float>(zn);
+    const double dz = static_cast<double>(znf) - static_cast<double>(a.z[zi]);
+    a.z[zi] = znf;
+    loc[0] = dz * dz;
+    loc[1] = static_cast<double>(znf) * znf;
+    for (int s = 0; s < pt.num_scen; ++s) {
+      const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
+      const double xv = static_cast<double>(a.x[vi]);
+      const double d = xv - static_cast<double>(znf);
+      const double dp = a.dprev[vi];
+      const double dd = d - dp;
+      loc[2] += d * d;
+      loc[3] += dd * dp;
+      loc[4] += dd * dd;
+      loc[5] += xv * xv;
+      a.dprev[vi] = d;
+    }
+  }
+  block_sum<6>(loc, sh);
+  if (threadIdx.x == 0) {
+    double* bp = a.bpartp + static_cast<int64_t>(bi) * 8;
+    for (int k = 0; k < 6; ++k) bp[k] = loc[k];
+  }
+}
+
+void launch_zres(const VecArgs& a, int npblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_zres, dim3(npblk), dim3(kThreads), 0, st, a);
+}
+
+// Residual norms, tolerances and the Barzilai-Borwein dual step per patient.
+__global__ __launch_bounds__(kThreads) void k_body_scalars(VecArgs a) {
+  __shared__ double sh[4 * 6];
+  const AlgoParams& P = a.prm;
+  for (int p = 0; p < P.num_pat; ++p) {
+    const Pat pt = a.pat[p];
+    PatState* ps = a.ps + p;
+    if (ps->stopped) continue;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < pt.nblk; b += kThreads)
+      for (int k = 0; k < 6; ++k) v[k] += a.bpartp[(int64_t)(pt.blk_begin + b) * 8 + k];
+    block_sum<6>(v, sh);
+    int cg = 0;
+    if (threadIdx.x == 0) {
+      for (int s = 0; s < pt.num_scen; ++s) cg += a.cgcount[pt.scen_begin + s];
+      const int N = pt.num_scen;
+      const double rho = ps->rho;
+      const double rp = sqrt(v[2]);
+      const double rd = sqrt(static_cast<double>(N)) * rho * sqrt(v[0]);
+      double tau = rho;
+      if (P.bb && ps->iter >= 1 && v[4] > 0.0) {
+        // dy = y^k - y^{k-1} = tau_{k-1} d^k, so <dd, dy> = tau_{k-1} <dd, d^k>
+        const double beta = -ps->tau * v[3] / v[4];
+        if (isfinite(beta) && beta > 0.0) tau = beta;
+      }
+      if (P.bb_clamp > 0.0) tau = fmin(fmax(tau, rho / P.bb_clamp), rho * P.bb_clamp);
+      const double base = P.eps_abs * sqrt(static_cast<double>(N) * pt.n);
+      ps->xnorm = sqrt(v[5]);
+      ps->znorm = sqrt(v[1]);
+      ps->eps_prim = base + P.eps_rel * fmax(ps->xnorm, sqrt(static_cast<double>(N)) * ps->znorm);
+      ps->r_prim = rp;
+      ps->r_dual = rd;
+      ps->tau = tau;
+      ps->cg_steps = cg;
+      ps->cg_total += cg;
+      ps->iter += 1;
+      ps->pending = 1;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_body_scalars(const VecArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_body_scalars, dim3(1), dim3(kThreads), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// small helpers: cross-scenario gradient sum, objective sum, PGD trial step
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_gsum(const Scen* scen, const Pat* pat, const Blk* pblk,
+                                                   const Tile* tiles, const float* part, int blk_begin,
+                                                   float scale, float* out) {
+  const Blk bk = pblk[blk_begin + blockIdx.x];
+  const Pat pt = pat[bk.owner];
+  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  if (j >= pt.n) return;
+  double s = 0.0;
+  for (int t = pt.tile_begin; t < pt.tile_end; ++t) s += static_cast<double>(part[tiles[t].part_off + j]);
+  out[j] = static_cast<float>(scale * s);
+}
+
+void launch_gsum(const Scen* scen, const Pat* pat, const Blk* pblk, const Tile* tiles, const float* part,
+                 int patient_blk_begin, int nblk, float scale, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gsum, dim3(nblk), dim3(kThreads), 0, st, scen, pat, pblk, tiles, part, patient_blk_begin,
+                     scale, out);
+}
+
+__global__ __launch_bounds__(kThreads) void k_objsum(const double* objpart, int tile_begin, int count, double* out) {
+  __shared__ double sh[4];
+  const double f = block_list_sum(count, [&](int i) { return objpart[tile_begin + i]; }, sh);
+  if (threadIdx.x == 0) *out = f;
+}
+
+void launch_objsum(const Tile*, const double* objpart, int tile_begin, int tile_count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_objsum, dim3(1), dim3(kThreads), 0, st, objpart, tile_begin, tile_count, out);
+}
+
+__global__ __launch_bounds__(kThreads) void k_pgd_trial(const float* x, const float* g, const float* lb,
+                                                        const float* ub, float t, float* xt, int n,
+                                                        double* dotpart) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x * kThreads + threadIdx.x;
+  double loc[1] = {0.0};
+  if (j < n) {
+    const float v = fminf(fmaxf(x[j] - t * g[j], lb[j]), ub[j]);
+    xt[j] = v;
+    loc[0] = static_cast<double>(g[j]) * (static_cast<double>(v) - static_cast<double>(x[j]));
+  }
+  block_sum<1>(loc, sh);
+  if (threadIdx.x == 0) dotpart[blockIdx.x] = loc[0];
+}
+
+void launch_pgd_trial(const float* x, const float* g, const float* lb, const float* ub, float t, float* xt, int n,
+                      double* dotpart, hipStream_t st) {
+  const int nb = (n + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_pgd_trial, dim3(nb), dim3(kThreads), 0, st, x, g, lb, ub, t, xt, n, dotpart);
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot_sum(const double* part, int count, double* out) {
+  __shared__ double sh[4];
+  const double f = block_list_sum(count, [&](int i) { return part[i]; }, sh);
+  if (threadIdx.x == 0) *out = f;
+}
+
+void launch_dot_sum(const double* part, int count, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot_sum, dim3(1), dim3(kThreads), 0, st, part, count, out);
+}
+
+template <class T>
+__global__ void k_fill(T* p, T v, int64_t count) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+template <class T>
+static void fill(T* p, T v, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
+  int64_t nb = (count + kThreads - 1) / kThreads;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_fill<T>, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, st, p, v, count);
+}
+
+void launch_fill_f32(float* p, float v, int64_t count, hipStream_t st) { fill<float>(p, v, count, st); }
+void launch_fill_f64(double* p, double v, int64_t count, hipStream_t st) { fill<double>(p, v, count, st); }
+void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st) { fill<uint8_t>(p, v, count, st); }
+
+}  // namespace admmbb

@@ -1,0 +1,95 @@
+// Host-side validation of admm_problem (no device calls; usable without a GPU).
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "../../include/admmbb.h"
+#include "host.h"
+
+namespace admmbb {
+
+static admm_status fail(std::string* msg, admm_status st, const char* fmt, long long a = 0, long long b = 0,
+                        long long c = 0) {
+  if (msg) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), fmt, a, b, c);
+    *msg = buf;
+  }
+  return st;
+}
+
+admm_status validate_problem(const admm_problem* p, std::string* msg) {
+  if (!p) return fail(msg, ADMM_E_ARG, "problem is NULL");
+  if (p->m <= 0 || p->n <= 0 || p->num_scen <= 0)
+    return fail(msg, ADMM_E_ARG, "sizes must be positive (m=%lld n=%lld num_scen=%lld)", p->m, p->n, p->num_scen);
+  if (p->n > 1 << 24) return fail(msg, ADMM_E_ARG, "n=%lld exceeds the supported 2^24 spots", p->n);
+  if (!p->A || !p->struct_id || !p->struct_weight || !p->presc)
+    return fail(msg, ADMM_E_ARG, "NULL array in problem (A, struct_id, struct_weight or presc)");
+  if (p->num_struct <= 0 || p->num_struct > 256) return fail(msg, ADMM_E_ARG, "num_struct=%lld not in 1..256", p->num_struct);
+  for (int k = 0; k < p->num_struct; ++k) {
+    const double w = p->struct_weight[k];
+    if (!std::isfinite(w)) return fail(msg, ADMM_E_NONFINITE, "struct_weight[%lld] is not finite", k);
+    if (w < 0) return fail(msg, ADMM_E_NEGATIVE, "struct_weight[%lld] < 0", k);
+  }
+  for (int i = 0; i < p->m; ++i) {
+    if (p->struct_id[i] >= p->num_struct)
+      return fail(msg, ADMM_E_ARG, "struct_id[%lld]=%lld >= num_struct", i, p->struct_id[i]);
+    const double v = p->presc[i];
+    if (!std::isfinite(v)) return fail(msg, ADMM_E_NONFINITE, "presc[%lld] is not finite", i);
+    if (v < 0) return fail(msg, ADMM_E_NEGATIVE, "presc[%lld] < 0", i);
+  }
+  for (int j = 0; j < p->n; ++j) {
+    const double lo = p->lb ? p->lb[j] : 0.0;
+    const double hi = p->ub ? p->ub[j] : INFINITY;
+    if (std::isnan(lo) || std::isnan(hi) || std::isinf(lo))
+      return fail(msg, ADMM_E_NONFINITE, "bound of spot %lld is NaN or lb is infinite", j);
+    if (lo > hi) return fail(msg, ADMM_E_ARG, "lb > ub at spot %lld", j);
+  }
+  for (int s = 0; s < p->num_scen; ++s) {
+    const admm_csr& A = p->A[s];
+    if (!A.row_ptr || (A.nnz > 0 && (!A.col || !A.val)))
+      return fail(msg, ADMM_E_ARG, "scenario %lld: NULL CSR array", s);
+    if (A.nnz < 0 || A.nnz > (int64_t)0xFFFFFFFFLL)
+      return fail(msg, ADMM_E_CSR, "scenario %lld: nnz=%lld outside 0..2^32-1", s, A.nnz);
+    if (!std::isfinite(A.prob)) return fail(msg, ADMM_E_NONFINITE, "scenario %lld: probability not finite", s);
+    if (A.prob < 0) return fail(msg, ADMM_E_NEGATIVE, "scenario %lld: probability < 0", s);
+    if (A.row_ptr[0] != 0) return fail(msg, ADMM_E_CSR, "scenario %lld: row_ptr[0] != 0", s);
+    if (A.row_ptr[p->m] != A.nnz)
+      return fail(msg, ADMM_E_CSR, "scenario %lld: row_ptr[m]=%lld != nnz=%lld", s, A.row_ptr[p->m], A.nnz);
+    for (int i = 0; i < p->m; ++i) {
+      const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
+      if (e < b) return fail(msg, ADMM_E_CSR, "scenario %lld: row_ptr decreases at row %lld", s, i);
+      if (e - b > p->n) return fail(msg, ADMM_E_CSR, "scenario %lld: row %lld has more than n entries", s, i);
+      int32_t prev = -1;
+      for (int64_t k = b; k < e; ++k) {
+        const int32_t c = A.col[k];
+        if (c < 0 || c >= p->n) return fail(msg, ADMM_E_CSR, "scenario %lld: column %lld out of range at row %lld", s, c, i);
+        if (c <= prev) return fail(msg, ADMM_E_CSR, "scenario %lld: columns not increasing in row %lld", s, i);
+        prev = c;
+        const float v = A.val[k];
+        if (!std::isfinite(v)) return fail(msg, ADMM_E_NONFINITE, "scenario %lld: non-finite value at row %lld", s, i);
+        if (v < 0) return fail(msg, ADMM_E_NEGATIVE, "scenario %lld: negative value at row %lld", s, i);
+      }
+    }
+  }
+  return ADMM_OK;
+}
+
+admm_status validate_options(const admm_options* o, std::string* msg) {
+  if (!o) return ADMM_OK;
+  if (!(o->eps_abs >= 0) || !(o->eps_rel >= 0) || !(o->obj_rel_tol >= 0) || !(o->bb_clamp >= 0) ||
+      !std::isfinite(o->rho))
+    return fail(msg, ADMM_E_ARG, "tolerances, bb_clamp must be >= 0 and rho finite");
+  if (o->max_iter < 0) return fail(msg, ADMM_E_ARG, "max_iter < 0");
+  if (o->cg_max < 1 || o->cg_max > kMaxCg) return fail(msg, ADMM_E_ARG, "cg_max=%lld not in 1..64", o->cg_max);
+  if (!(o->cg_eta >= 0) || !(o->cg_eta_floor >= 0)) return fail(msg, ADMM_E_ARG, "cg_eta must be >= 0");
+  if (o->precision < ADMM_PREC_FP32 || o->precision > ADMM_PREC_FP16)
+    return fail(msg, ADMM_E_ARG, "unknown precision %lld", o->precision);
+  if (o->z_mode < 0 || o->z_mode > 1) return fail(msg, ADMM_E_ARG, "z_mode must be 0 or 1");
+  if (o->check_every < 1) return fail(msg, ADMM_E_ARG, "check_every must be >= 1");
+  if (o->lds_fp64 < -1 || o->lds_fp64 > 1) return fail(msg, ADMM_E_ARG, "lds_fp64 must be -1, 0 or 1");
+  if (o->tile_nnz < 0) return fail(msg, ADMM_E_ARG, "tile_nnz < 0");
+  return ADMM_OK;
+}
+
+}  // namespace admmbb

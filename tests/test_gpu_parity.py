@@ -1,0 +1,126 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C-ABI).
+
+Tolerances:
+  SpMV-type products (fp32 values, fp32/fp64 accumulation): per entry
+      |y_gpu - y_ref| <= 1e-6 * (|A| |v|)_i      (y_ref = fp64 product of the same fp32 inputs)
+  final objective: |f_gpu - f*| <= 1e-5 f*
+  spot intensities: ||z - x*|| / ||x*|| <= 1e-4 (only where the oracle's
+      Hessian is well enough conditioned for the intensities to be identifiable;
+      otherwise the objective tolerance is the criterion)
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import exact, wls
+
+pytestmark = pytest.mark.gpu
+
+SPMV_TOL = 1e-6
+
+
+def _solver(P, **kw):
+    import paper_2304_14568_amd as A
+    return A.Solver(P, **kw)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    P = synth.make_tiny(0)
+    W = wls.from_problem(P)
+    Hm, g0, const = wls.quadratic_form(W)
+    xs, info = exact.active_set(W, H=Hm, g0=g0)
+    return P, W, xs, wls.objective(W, xs)
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = synth.hn_small(1)
+    W = wls.from_problem(P)
+    Hm, g0, const = wls.quadratic_form(W)
+    xs, info = exact.active_set(W, H=Hm, g0=g0)
+    return P, W, xs, wls.objective(W, xs)
+
+
+def _spmv_check(got, ref, scale, tol=SPMV_TOL):
+    err = np.abs(got.astype(np.float64) - ref)
+    bound = tol * scale + 1e-30
+    bad = np.nonzero(err > bound)[0]
+    assert bad.size == 0, f"{bad.size} entries over bound; worst ratio {np.max(err / bound):.3g}"
+
+
+@pytest.mark.parametrize("tile_nnz", [0, 4096])
+def test_matvec_rmatvec_parity(tiny, small, tile_nnz):
+    rng = np.random.default_rng(7)
+    for P, W in ((tiny[0], tiny[1]), (small[0], small[1])):
+        with _solver(P, tile_nnz=tile_nnz) as S:
+            for s in range(P.num_scen):
+                v = rng.uniform(0, 1, P.n).astype(np.float32)
+                _spmv_check(S.matvec(v, s), wls.matvec(W, s, v), wls.matvec_abs(W, s, v))
+                t = rng.normal(size=P.m).astype(np.float32)
+                _spmv_check(S.rmatvec(t, s), wls.rmatvec(W, s, t), wls.rmatvec_abs(W, s, t))
+
+
+@pytest.mark.parametrize("lds_fp64", [0, 1])
+def test_normal_apply_parity(small, lds_fp64):
+    P, W, _, _ = small
+    rng = np.random.default_rng(8)
+    with _solver(P, lds_fp64=lds_fp64, tile_nnz=20000) as S:
+        rho = S.rho()
+        for s in (0, 5, P.num_scen - 1):
+            v = rng.normal(size=P.n).astype(np.float32)
+            got = S.normal_apply(v, s)
+            ref = wls.normal_apply(W, s, v, rho)
+            _spmv_check(got, ref, wls.normal_apply_abs(W, s, v, rho))
+
+
+def test_gradient_objective_parity(tiny, small):
+    rng = np.random.default_rng(9)
+    for P, W, xs, _ in (tiny, small):
+        with _solver(P) as S:
+            for x in (xs, rng.uniform(0, 0.5, P.n)):
+                x32 = x.astype(np.float32).astype(np.float64)
+                g, f = S.gradient(x32)
+                gr = wls.gradient(W, x32)
+                scale = np.zeros(P.n)
+                for s in range(W.N):
+                    r_abs = np.abs(W.A[s]) @ x32 + W.p
+                    scale += 2 * W.c[s] * (abs(W.A[s]).T @ (W.w * r_abs))
+                _spmv_check(g, gr, scale)
+                fr = wls.objective(W, x32)
+                assert abs(f - fr) <= 1e-6 * fr
+                assert abs(S.objective(x32) - fr) <= 1e-6 * fr
+
+
+def test_admm_solve_tiny(tiny):
+    P, W, xs, fs = tiny
+    with _solver(P, max_iter=3000) as S:
+        zs, info, st = S.solve()
+        z = zs[0]
+        assert st == 0, info
+        f = wls.objective(W, z)
+        assert abs(f - fs) <= 1e-5 * fs
+        assert abs(info[0]["obj"] - f) <= 1e-6 * fs
+        assert S.kkt(z) <= 1e-3
+
+
+def test_admm_solve_hn_small(small):
+    P, W, xs, fs = small
+    with _solver(P, max_iter=3000) as S:
+        zs, info, st = S.solve()
+        z = zs[0]
+        assert st == 0, info
+        f = wls.objective(W, z)
+        assert abs(f - fs) <= 1e-5 * fs, (f, fs)
+        assert np.linalg.norm(z - xs) / np.linalg.norm(xs) <= 1e-2
+
+
+def test_pgd_gpu(tiny):
+    P, W, xs, fs = tiny
+    with _solver(P) as S:
+        x, info, st = S.pgd(0, obj_rel_tol=1e-9, max_iter=5000)
+        f = wls.objective(W, x)
+        assert f >= fs * (1 - 1e-7)
+        assert abs(f - fs) <= 1e-4 * fs
