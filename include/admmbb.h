@@ -107,8 +107,12 @@ typedef struct {
   int32_t precond;     /* 1: Jacobi-preconditioned CG; default 0 */
   int32_t use_graph;   /* 1: capture one iteration in a HIP graph and replay it (default) */
   int32_t check_every; /* host reads the stop flags every k iterations; default 1 */
-  int32_t lds_fp64;    /* column accumulators in LDS: -1 auto (fp64 when max n <= 4096), 0 fp32, 1 fp64 */
+  int32_t lds_acc;     /* column accumulators of the fused pass in LDS: 0 fp32 atomics, 1 fp64 atomics,
+                          2 64-bit fixed point (integer atomics: exact, order-independent sums);
+                          -1 = chosen by the set-up autotuner among 1 and 2 */
   int32_t tile_nnz;    /* target nonzeros per workgroup tile; 0 = automatic */
+  int32_t pass_threads; /* fused-pass workgroup size 256 or 512; 0 = chosen by the set-up autotuner */
+  int32_t pass_unroll;  /* reserved: rows per lane group in flight, 0 or 1 */
   void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
 } admm_options;
 
@@ -197,6 +201,16 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
 
 /* Per-iteration records of the last solve / iterate calls (up to cap). */
 admm_status admm_get_trace(admm_ctx* ctx, int32_t patient, admm_info* buf, int32_t cap, int32_t* count);
+
+/* Fused-pass configuration in use (picked by the set-up autotuner unless fixed
+ * in the options): workgroup size, rows in flight per lane group, LDS
+ * accumulator kind, and the measured average pass time in ms of the chosen one
+ * (all scenarios, fp32 or the CG value precision). */
+admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms);
+
+/* CG steps performed per scenario of a patient since its last reset
+ * (num_scen int64 entries): the number of fused CG-pass applications of A_s. */
+admm_status admm_get_cg_counts(admm_ctx* ctx, int32_t patient, int64_t* counts);
 
 /* Sizes: num_patients; per patient n, m, num_scen, total nonzeros. */
 admm_status admm_get_sizes(const admm_ctx* ctx, int32_t patient, int32_t* n, int32_t* m, int32_t* num_scen,

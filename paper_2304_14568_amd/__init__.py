@@ -25,7 +25,7 @@ EXPORTS = [
     "admm_default_options", "pgd_default_options", "admm_setup", "admm_setup_batch", "admm_warm_start",
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
-    "admm_set_state", "admm_get_trace", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
+    "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
     "admm_last_error", "admm_destroy", "admm_validate",
 ]
 
@@ -54,7 +54,8 @@ class OptionsC(ctypes.Structure):
                 ("z_mode", ctypes.c_int32), ("bb_clamp", ctypes.c_double), ("cg_max", ctypes.c_int32),
                 ("cg_eta", ctypes.c_double), ("cg_eta_floor", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("lds_fp64", ctypes.c_int32), ("tile_nnz", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("lds_acc", ctypes.c_int32), ("tile_nnz", ctypes.c_int32), ("pass_threads", ctypes.c_int32),
+                ("pass_unroll", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class InfoC(ctypes.Structure):
@@ -100,6 +101,8 @@ def _load():
         "admm_get_state": [P, i32, P, P, P, P],
         "admm_set_state": [P, i32, P, P, P, P],
         "admm_get_trace": [P, i32, P, i32, P],
+        "admm_get_cg_counts": [P, i32, P],
+        "admm_get_tuning": [P, P, P, P, P],
         "admm_get_sizes": [P, i32, P, P, P, P],
         "admm_enable_timing": [P, i32],
         "admm_get_timing": [P, P, P, P],
@@ -320,6 +323,18 @@ class Solver:
         cnt = ctypes.c_int32()
         _check(self.ctx, lib.admm_get_trace(self.ctx, patient, buf, cap, ctypes.byref(cnt)))
         return [buf[i].as_dict() for i in range(cnt.value)]
+
+    def tuning(self):
+        t, u, a = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        _check(self.ctx, lib.admm_get_tuning(self.ctx, ctypes.byref(t), ctypes.byref(u), ctypes.byref(a),
+                                             ctypes.byref(ms)))
+        return dict(threads=t.value, unroll=u.value, lds_acc=a.value, pass_ms=ms.value)
+
+    def cg_counts(self, patient: int = 0):
+        c = np.zeros(self.num_scen[patient], dtype=np.int64)
+        _check(self.ctx, lib.admm_get_cg_counts(self.ctx, patient, c.ctypes.data))
+        return c
 
     def sizes(self, patient: int = 0):
         n, m, N = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -57,6 +57,7 @@ struct admm_ctx {
   uint8_t* d_act = nullptr;
   double *d_rz = nullptr, *d_tol2 = nullptr;
   int32_t* d_cgcount = nullptr;
+  int64_t* d_cgtotal = nullptr;
   PatState* d_ps = nullptr;
   IterRecord* d_trace = nullptr;
   int trace_cap = 0;
@@ -64,7 +65,9 @@ struct admm_ctx {
   double* h_scr = nullptr;   // pinned scratch
   hipGraphExec_t g_solve = nullptr, g_iter = nullptr;
   hipGraph_t gr_solve = nullptr, gr_iter = nullptr;
-  bool acc64 = false;
+  int acc = ACC_F64;
+  int pass_threads = 512, pass_unroll = 1;
+  double tuned_ms = 0.0;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs around the CG passes inside the captured iteration
@@ -111,7 +114,9 @@ struct admm_ctx {
     a.part = d_part;
     a.objpart = d_objpart;
     a.nmax = H.nmax;
-    a.acc64 = acc64 ? 1 : 0;
+    a.acc = acc;
+    a.threads = pass_threads;
+    a.unroll = pass_unroll;
     return a;
   }
 
@@ -129,6 +134,7 @@ struct admm_ctx {
     a.rz = d_rz;
     a.tol2 = d_tol2;
     a.cgcount = d_cgcount;
+    a.cgtotal = d_cgtotal;
     a.x = d_x;
     a.r = d_r;
     a.v = d_v;
@@ -211,7 +217,9 @@ struct admm_ctx {
   }
 
   void one_iteration(int stop_enabled) {
-    if (opts.use_graph) {
+    // timed runs launch directly: events recorded around each pass launch must
+    // be readable after every iteration, which graph-captured events are not
+    if (opts.use_graph && !timing) {
       hipGraphExec_t& ge = stop_enabled ? g_solve : g_iter;
       hipGraph_t& gr = stop_enabled ? gr_solve : gr_iter;
       if (!ge) capture(stop_enabled, &gr, &ge);
@@ -287,6 +295,53 @@ struct admm_ctx {
     }
   }
 
+  // Time the fused CG pass over every tile for each candidate configuration
+  // and keep the fastest (values of the multiplied vector do not change the work).
+  void autotune() {
+    const MatDev& m = (opts.precision == ADMM_PREC_FP32) ? mat32 : matlp;
+    std::vector<int> th = {256, 512}, un = {1}, ac = {ACC_FIX64, ACC_F64};
+    if (opts.pass_threads) th = {opts.pass_threads};
+    if (opts.pass_unroll) un = {opts.pass_unroll};
+    if (opts.lds_acc >= 0) ac = {opts.lds_acc};
+    if (pass_smem_bytes(H.nmax, ac[0]) > 65536) return;
+    hipEvent_t e0, e1;
+    check(hipEventCreate(&e0), "hipEventCreate");
+    check(hipEventCreate(&e1), "hipEventCreate");
+    double best = 1e30;
+    int bt = th[0], bu = un[0], ba = ac[0];
+    const int reps = 3;
+    for (int a64 : ac)
+      for (int t : th)
+        for (int u : un) {
+          acc = a64;
+          pass_threads = t;
+          pass_unroll = u;
+          PassArgs pa = pass_args(m);
+          pa.src = d_v;
+          pa.src_per_scen = 1;
+          pa.objpart = nullptr;
+          launch_pass(PASS_CG, pa, 0, T, stream);
+          check(hipEventRecord(e0, stream), "hipEventRecord");
+          for (int r = 0; r < reps; ++r) launch_pass(PASS_CG, pa, 0, T, stream);
+          check(hipEventRecord(e1, stream), "hipEventRecord");
+          check(hipEventSynchronize(e1), "hipEventSynchronize");
+          float ms = 0.0f;
+          check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+          if (ms / reps < best) {
+            best = ms / reps;
+            bt = t;
+            bu = u;
+            ba = a64;
+          }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    acc = ba;
+    pass_threads = bt;
+    pass_unroll = bu;
+    tuned_ms = best < 1e30 ? best : 0.0;
+  }
+
   void reset_patient(int p, const double* z0, double new_rho) {
     const Pat& pt = H.pat[p];
     std::vector<float> z(pt.n);
@@ -301,6 +356,7 @@ struct admm_ctx {
     launch_fill_f32(d_y + s0.vec_base, 0.0f, len, stream);
     launch_fill_f32(d_x + s0.vec_base, 0.0f, len, stream);
     launch_fill_f64(d_dprev + s0.vec_base, 0.0, len, stream);
+    check(hipMemsetAsync(d_cgtotal + pt.scen_begin, 0, sizeof(int64_t) * pt.num_scen, stream), "memset");
     if (new_rho > 0) rho[p] = new_rho;
     PatState st{};
     st.rho = rho[p];
@@ -324,8 +380,7 @@ struct admm_ctx {
     PassArgs pa = pass_args(mat32);
     pa.src = d_pvec;
     pa.src_per_scen = 0;
-    if (!grad_dev) pa.part = nullptr;
-    launch_pass(PASS_GRAD, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, stream);
+    launch_pass(grad_dev ? PASS_GRAD : PASS_OBJ, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, stream);
     if (grad_dev)
       launch_gsum(d_scen, d_pat, d_pblk, d_tiles, d_part, pt.blk_begin, pt.nblk, 2.0f, grad_dev, stream);
     launch_objsum(d_tiles, d_objpart, pt.tile_begin, pt.tile_end - pt.tile_begin, d_scratch, stream);
@@ -391,8 +446,10 @@ admm_status admm_default_options(admm_options* o) {
   o->precond = 0;
   o->use_graph = 1;
   o->check_every = 1;
-  o->lds_fp64 = -1;
+  o->lds_acc = -1;
   o->tile_nnz = 0;
+  o->pass_threads = 0;
+  o->pass_unroll = 0;
   o->stream = nullptr;
   return ADMM_OK;
 }
@@ -455,7 +512,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->T = static_cast<int>(H.tiles.size());
     c->NB = static_cast<int>(H.blk.size());
     c->NPB = static_cast<int>(H.pblk.size());
-    c->acc64 = o.lds_fp64 == 1 || (o.lds_fp64 == -1 && H.nmax <= 4096);
+    c->acc = o.lds_acc >= 0 ? o.lds_acc : ACC_FIX64;
     if (o.stream) {
       c->stream = static_cast<hipStream_t>(o.stream);
     } else {
@@ -515,6 +572,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->d_rz = c->alloc<double>(static_cast<size_t>(c->G) * kRing);
     c->d_tol2 = c->alloc<double>(c->G);
     c->d_cgcount = c->alloc<int32_t>(c->G);
+    c->d_cgtotal = c->alloc<int64_t>(c->G);
     c->d_ps = c->alloc<PatState>(c->P);
     c->d_trace = c->alloc<IterRecord>(static_cast<size_t>(c->P) * c->trace_cap);
     check(hipHostMalloc(reinterpret_cast<void**>(&c->h_ps), sizeof(PatState) * c->P, hipHostMallocDefault),
@@ -527,6 +585,9 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     launch_fill_u8(c->d_act, 0, static_cast<int64_t>(c->G) * kRing, c->stream);
     launch_fill_f64(c->d_rz, 0.0, static_cast<int64_t>(c->G) * kRing, c->stream);
     for (int p = 0; p < num_patients; ++p) c->reset_patient(p, nullptr, 0.0);
+    if (o.pass_threads) c->pass_threads = o.pass_threads;
+    if (o.pass_unroll) c->pass_unroll = o.pass_unroll;
+    c->autotune();
     check(hipEventCreate(&c->ev_a), "hipEventCreate");
     check(hipEventCreate(&c->ev_b), "hipEventCreate");
     check(hipStreamSynchronize(c->stream), "setup sync");
@@ -665,12 +726,7 @@ admm_status admm_get_sizes(const admm_ctx* ctx, int32_t patient, int32_t* n, int
   if (num_scen) *num_scen = pt.num_scen;
   if (nnz) {
     int64_t t = 0;
-    for (int s = 0; s < pt.num_scen; ++s) {
-      const Scen& sc = ctx->H.scen[pt.scen_begin + s];
-      const int64_t next = (pt.scen_begin + s + 1 < ctx->G) ? ctx->H.scen[pt.scen_begin + s + 1].nnz_base
-                                                           : ctx->H.nnz_total;
-      t += next - sc.nnz_base;
-    }
+    for (int s = 0; s < pt.num_scen; ++s) t += ctx->H.scen_nnz[pt.scen_begin + s];
     *nnz = t;
   }
   return ADMM_OK;
@@ -977,6 +1033,28 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
   s.cg_total = static_cast<int32_t>(scalars[7]);
   ctx->h_ps[patient] = s;
   check(hipMemcpy(ctx->d_ps + patient, &s, sizeof(PatState), hipMemcpyHostToDevice), "H2D");
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms) {
+  if (!ctx) return ADMM_E_ARG;
+  if (threads) *threads = ctx->pass_threads;
+  if (unroll) *unroll = ctx->pass_unroll;
+  if (lds_acc) *lds_acc = ctx->acc;
+  if (ms) *ms = ctx->tuned_ms;
+  return ADMM_OK;
+}
+
+admm_status admm_get_cg_counts(admm_ctx* ctx, int32_t patient, int64_t* counts) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!counts) return set_err(ctx, ADMM_E_ARG, "counts is NULL");
+  GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  check(hipMemcpy(counts, ctx->d_cgtotal + pt.scen_begin, sizeof(int64_t) * pt.num_scen, hipMemcpyDeviceToHost),
+        "D2H");
   return ADMM_OK;
   GUARD_END(ctx)
 }

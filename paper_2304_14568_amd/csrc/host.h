@@ -16,6 +16,7 @@ admm_status validate_options(const admm_options* o, std::string* msg);
 // Host-side image of everything that goes to the device.
 struct Packed {
   std::vector<Scen> scen;
+  std::vector<int64_t> scen_nnz;  // nonzeros of each A_s as given (before chunk padding)
   std::vector<Pat> pat;
   std::vector<Tile> tiles;
   std::vector<Blk> blk, pblk;

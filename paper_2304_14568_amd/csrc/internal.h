@@ -11,11 +11,14 @@ constexpr int kThreads = 256;       // threads per workgroup, all kernels
 constexpr int kColBlock = 256;      // columns handled by one block of a vector kernel
 constexpr int kMaxCg = 64;          // CG steps per ADMM iteration, upper limit
 constexpr int kRing = kMaxCg + 2;   // per-scenario CG scalar slots
-constexpr int kRegChunks = 4;       // nonzeros of a row kept in registers per lane
+constexpr int kRegChunks = 4;       // 4-element chunks of a row kept in registers per lane
 
 enum PassMode { PASS_GRAD = 0, PASS_CG = 1, PASS_OBJ = 2, PASS_MATVEC = 3, PASS_RMATVEC = 4 };
 enum ValKind { VAL_F32 = 0, VAL_BF16 = 1, VAL_F16 = 2 };
 enum RedMode { RED_HEAD = 0, RED_CG = 1, RED_NORMAL = 2, RED_RMAT = 3 };
+// LDS column accumulators of the fused pass: float atomics, double atomics, or
+// 64-bit fixed point (integer atomics, exact and order-independent sums).
+enum AccKind { ACC_F32 = 0, ACC_F64 = 1, ACC_FIX64 = 2 };
 
 // One per (patient, scenario).
 struct Scen {
@@ -51,6 +54,11 @@ struct Tile {
   int32_t row_begin, row_end;
   int32_t lanes;
   int64_t part_off;   // offset of this tile's n-vector of partial column sums
+  // bounds for the fixed-point column accumulators (rounded up):
+  float wmax;         // max over the tile's rows of c_s w_i sum_j |a_ij|
+  float pmax;         // max over the tile's rows of c_s w_i p_i
+  float cmax;         // max over columns of sum over the tile's rows of |a_ij|
+  int32_t pad;
 };
 
 // Column block of a scenario (owner = scenario) or of a patient (owner = patient).
@@ -95,7 +103,7 @@ struct AlgoParams {
 
 // Matrix storage of all (patient, scenario) pairs, length-sorted rows.
 struct MatDev {
-  const uint32_t* rp;      // row start offsets relative to nnz_base
+  const uint32_t* rp;      // row starts in 4-element chunks relative to nnz_base (rows padded to whole chunks)
   const void* col;         // uint16 (n <= 65535) or int32 column indices
   const void* val;         // float / bf16 bits / fp16 values
   const float* rscale;     // per-row scale for low-precision values (nullptr for fp32)
@@ -121,7 +129,9 @@ struct PassArgs {
   const float* tin;        // RMATVEC input (m-vector of the scenario)
   float* tout;             // MATVEC output (m-vector of the scenario)
   int32_t nmax;
-  int32_t acc64;           // 1: LDS column accumulators in double
+  int32_t acc;             // LDS column accumulators: ACC_F32, ACC_F64 or ACC_FIX64
+  int32_t threads;         // workgroup size of the pass: 256 or 512
+  int32_t unroll;          // rows per lane group in flight: 1, 2 or 4
 };
 
 struct VecArgs {
@@ -137,7 +147,8 @@ struct VecArgs {
   uint8_t* act;            // [scen * kRing + k]
   double* rz;              // [scen * kRing + k]
   double* tol2;            // [scen]
-  int32_t* cgcount;        // [scen]
+  int32_t* cgcount;        // [scen], CG steps of the current iteration
+  int64_t* cgtotal;        // [scen], CG steps since the last reset
   float* x;
   float* r;
   float* v;
@@ -176,6 +187,6 @@ void launch_dot_sum(const double* part, int count, double* out, hipStream_t st);
 void launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st);
-int pass_smem_bytes(int nmax, int acc64);
+int pass_smem_bytes(int nmax, int acc);
 
 }  // namespace admmbb

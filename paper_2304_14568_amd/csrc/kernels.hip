@@ -46,9 +46,10 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-// Deterministic block sum of NV doubles; result valid in thread 0.
-template <int NV>
+// Deterministic block sum of NV doubles over NT threads; result valid in thread 0.
+template <int NV, int NT = kThreads>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+  constexpr int NW = NT / 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
@@ -60,7 +61,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = (sh[k] + sh[NV + k]) + (sh[2 * NV + k] + sh[3 * NV + k]);
+    for (int k = 0; k < NV; ++k) {
+      double acc = 0.0;
+      for (int w = 0; w < NW; ++w) acc += sh[w * NV + k];
+      v[k] = acc;
+    }
   }
   __syncthreads();
 }
@@ -79,101 +84,214 @@ __device__ __forceinline__ double block_list_sum(int count, F item, double* sh) 
 // the fused pass
 // ---------------------------------------------------------------------------
 
-template <int VK, bool C16, int L, int MODE>
-__device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, const Scen& sc, float* vsh,
-                                          float* qf, double* qd, bool acc64, bool scatter, double& objacc) {
-  using V = ValT<VK>;
-  using VT = typename V::T;
+// Round a scaled contribution (|d| < 2^61) to a two's-complement 64-bit
+// integer: d = hi * 2^32 + lo with lo in [0, 2^32), all steps exact except
+// the final truncation of lo (an error below one fixed-point unit).
+__device__ __forceinline__ unsigned long long to_fixed(double d) {
+  const double h = floor(d * 0x1p-32);
+  const double l = fma(h, -0x1p32, d);
+  const uint32_t lo = static_cast<uint32_t>(l);
+  const uint32_t hi = static_cast<uint32_t>(static_cast<int32_t>(h));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// 4-element chunk types: values (fp32: one 16-byte load; bf16 / fp16: 8 bytes)
+// and column indices (uint16: 8 bytes; int32: 16 bytes).
+template <int VK>
+struct VChunk;
+template <>
+struct VChunk<VAL_F32> {
+  using T = float4;
+  static __device__ __forceinline__ void unpack(const T& c, float (&o)[4]) {
+    o[0] = c.x;
+    o[1] = c.y;
+    o[2] = c.z;
+    o[3] = c.w;
+  }
+};
+template <>
+struct VChunk<VAL_BF16> {
+  using T = uint2;
+  static __device__ __forceinline__ void unpack(const T& c, float (&o)[4]) {
+    o[0] = __uint_as_float(c.x << 16);
+    o[1] = __uint_as_float(c.x & 0xffff0000u);
+    o[2] = __uint_as_float(c.y << 16);
+    o[3] = __uint_as_float(c.y & 0xffff0000u);
+  }
+};
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+template <>
+struct VChunk<VAL_F16> {
+  using T = uint2;
+  static __device__ __forceinline__ void unpack(const T& c, float (&o)[4]) {
+    const half2v a = __builtin_bit_cast(half2v, c.x);
+    const half2v b = __builtin_bit_cast(half2v, c.y);
+    o[0] = static_cast<float>(a[0]);
+    o[1] = static_cast<float>(a[1]);
+    o[2] = static_cast<float>(b[0]);
+    o[3] = static_cast<float>(b[1]);
+  }
+};
+template <bool C16>
+struct CChunk;
+template <>
+struct CChunk<true> {
+  using T = uint2;
+  static __device__ __forceinline__ int get(const T& c, int e) {
+    const uint32_t w = (e < 2) ? c.x : c.y;
+    return static_cast<int>((e & 1) ? (w >> 16) : (w & 0xffffu));
+  }
+};
+template <>
+struct CChunk<false> {
+  using T = int4;
+  static __device__ __forceinline__ int get(const T& c, int e) {
+    return e == 0 ? c.x : (e == 1 ? c.y : (e == 2 ? c.z : c.w));
+  }
+};
+
+// Rows of one tile with L lanes per row.  Rows are stored padded to whole
+// 4-element chunks (zero values); lane l of a row loads chunks l, l+L, ... with
+// one wide load per chunk and keeps up to kRegChunks of them in registers
+// between the row dot product and the scatter.  Rows longer than that (only in
+// the 64-lane bin) stream their tail twice.  The next row's offsets are loaded
+// while the current row computes.
+//
+// MODE  PASS_GRAD     t_i = c_s w_i (a_i.v - p_i) (fp64 dot), objective partial, scatter
+//       PASS_OBJ      objective partial only
+//       PASS_MATVEC   (a_i.v) written to tout[row] (fp64 dot)
+//       PASS_CG       t_i = c_s w_i a_i.v (fp32 dot), scatter
+//       PASS_RMATVEC  t_i = tin[row], scatter
+// ACC   LDS column accumulators (AccKind)
+template <int VK, bool C16, int L, int MODE, int ACC, int NT>
+__device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, const Scen& sc, const float* vsh,
+                                          void* qacc, double fscale, double& objacc) {
+  using VC = typename VChunk<VK>::T;
+  using CCk = typename CChunk<C16>::T;
+  using VT = typename ValT<VK>::T;
   using CT = std::conditional_t<C16, uint16_t, int32_t>;
-  using DACC = std::conditional_t<MODE == PASS_GRAD, double, float>;
+  constexpr bool kDot = MODE != PASS_RMATVEC;
+  constexpr bool kScatter = MODE == PASS_GRAD || MODE == PASS_CG || MODE == PASS_RMATVEC;
+  constexpr bool kDot64 = MODE == PASS_GRAD || MODE == PASS_OBJ || MODE == PASS_MATVEC;
+  using DACC = std::conditional_t<kDot64, double, float>;
   constexpr int K = kRegChunks;
-  constexpr int G = kThreads / L;
+  constexpr int G = NT / L;
   const int grp = threadIdx.x / L;
   const int lane = threadIdx.x % L;
   const uint32_t* __restrict__ rp = a.mat.rp + sc.rp_base;
-  const CT* __restrict__ col = static_cast<const CT*>(a.mat.col) + sc.nnz_base;
-  const VT* __restrict__ val = static_cast<const VT*>(a.mat.val) + sc.nnz_base;
+  const VC* __restrict__ valc = reinterpret_cast<const VC*>(static_cast<const VT*>(a.mat.val) + sc.nnz_base);
+  const CCk* __restrict__ colc = reinterpret_cast<const CCk*>(static_cast<const CT*>(a.mat.col) + sc.nnz_base);
   const int64_t rb = sc.row_base;
-  const bool given_t = (MODE == PASS_CG) && (a.tin != nullptr);
+  const int rend = t.row_end;
+  float* __restrict__ qf = static_cast<float*>(qacc);
+  double* __restrict__ qd = static_cast<double*>(qacc);
+  unsigned long long* __restrict__ qi = static_cast<unsigned long long*>(qacc);
 
-  for (int r = t.row_begin + grp; r < t.row_end; r += G) {
-    const uint32_t s = rp[r], e = rp[r + 1];
-    float vv[K];
-    int cc[K];
+  auto scatter4 = [&](const CCk& c4, const float (&v4)[4], float tv, double td) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = CChunk<C16>::get(c4, q);
+      if constexpr (ACC == ACC_FIX64)
+        atomicAdd(&qi[j], to_fixed(td * static_cast<double>(v4[q])));
+      else if constexpr (ACC == ACC_F64)
+        atomicAdd(&qd[j], static_cast<double>(tv * v4[q]));
+      else
+        atomicAdd(&qf[j], tv * v4[q]);
+    }
+  };
+  auto dot4 = [&](const CCk& c4, const float (&v4)[4], DACC& dot) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float xv = vsh[CChunk<C16>::get(c4, q)];
+      if constexpr (kDot64)
+        dot += static_cast<double>(v4[q]) * static_cast<double>(xv);
+      else
+        dot = fmaf(v4[q], xv, dot);
+    }
+  };
+
+  int r = t.row_begin + grp;
+  uint32_t s = r < rend ? rp[r] : 0u;
+  uint32_t e = r < rend ? rp[r + 1] : 0u;
+  for (; r < rend; r += G) {
+    float vv[K][4];
+    CCk cc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const uint32_t i = s + lane + k * L;
-      if (i < e) {
-        vv[k] = V::f(val[i]);
-        cc[k] = static_cast<int>(col[i]);
+      const uint32_t c = s + lane + k * L;
+      if (c < e) {
+        VChunk<VK>::unpack(valc[c], vv[k]);
+        cc[k] = colc[c];
       } else {
-        vv[k] = 0.0f;
-        cc[k] = 0;
+        vv[k][0] = vv[k][1] = vv[k][2] = vv[k][3] = 0.0f;
+        cc[k] = CCk{};
       }
     }
-    float tv;
-    if (given_t) {
-      tv = a.tin[a.mat.rorig[rb + r]];
+    float rw;
+    float aux = 0.0f;
+    if constexpr (MODE == PASS_RMATVEC) {
+      rw = a.tin[a.mat.rorig[rb + r]];
+    } else if constexpr (MODE == PASS_MATVEC) {
+      rw = 0.0f;
     } else {
+      rw = a.mat.rw[rb + r];
+      if constexpr (kDot64)
+        aux = a.mat.rpres[rb + r];
+      else if (a.mat.rscale != nullptr)
+        aux = a.mat.rscale[rb + r];
+      else
+        aux = 1.0f;
+    }
+    // next row's offsets, in flight while this row computes
+    const int rn = r + G;
+    const uint32_t sn = rn < rend ? rp[rn] : 0u;
+    const uint32_t en = rn < rend ? rp[rn + 1] : 0u;
+
+    float tv = rw;
+    if constexpr (kDot) {
       DACC dot = 0;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if constexpr (MODE == PASS_GRAD)
-          dot += static_cast<double>(vv[k]) * static_cast<double>(vsh[cc[k]]);
-        else
-          dot = fmaf(vv[k], vsh[cc[k]], dot);
-      }
-      for (uint32_t i = s + lane + K * L; i < e; i += L) {
-        const float av = V::f(val[i]);
-        const float xv = vsh[static_cast<int>(col[i])];
-        if constexpr (MODE == PASS_GRAD)
-          dot += static_cast<double>(av) * static_cast<double>(xv);
-        else
-          dot = fmaf(av, xv, dot);
+      for (int k = 0; k < K; ++k) dot4(cc[k], vv[k], dot);
+      for (uint32_t c = s + lane + K * L; c < e; c += L) {
+        float v4[4];
+        VChunk<VK>::unpack(valc[c], v4);
+        dot4(colc[c], v4, dot);
       }
 #pragma unroll
       for (int off = L / 2; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
-      if constexpr (MODE == PASS_GRAD) {
-        if (a.tout != nullptr) {
-          if (lane == 0) a.tout[a.mat.rorig[rb + r]] = static_cast<float>(dot);
-          continue;
-        }
-        const double res = dot - static_cast<double>(a.mat.rpres[rb + r]);
-        const double wgt = static_cast<double>(a.mat.rw[rb + r]);
+      if constexpr (MODE == PASS_MATVEC) {
+        if (lane == 0) a.tout[a.mat.rorig[rb + r]] = static_cast<float>(dot);
+      } else if constexpr (kDot64) {
+        const double res = dot - static_cast<double>(aux);
+        const double wgt = static_cast<double>(rw);
         if (lane == 0) objacc += wgt * res * res;
         tv = static_cast<float>(wgt * res);
       } else {
-        float scl = 1.0f;
-        if (a.mat.rscale != nullptr) scl = a.mat.rscale[rb + r];
-        tv = a.mat.rw[rb + r] * dot * scl * scl;
+        tv = rw * dot * aux * aux;
       }
     }
-    if (!scatter) continue;
+    if constexpr (kScatter) {
+      const double td = static_cast<double>(tv) * fscale;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const uint32_t i = s + lane + k * L;
-      if (i < e) {
-        const float c = tv * vv[k];
-        if (acc64)
-          atomicAdd(&qd[cc[k]], static_cast<double>(c));
-        else
-          atomicAdd(&qf[cc[k]], c);
+      for (int k = 0; k < K; ++k) {
+        if (s + lane + k * L < e) scatter4(cc[k], vv[k], tv, td);
+      }
+      for (uint32_t c = s + lane + K * L; c < e; c += L) {
+        float v4[4];
+        VChunk<VK>::unpack(valc[c], v4);
+        scatter4(colc[c], v4, tv, td);
       }
     }
-    for (uint32_t i = s + lane + K * L; i < e; i += L) {
-      const float c = tv * V::f(val[i]);
-      const int j = static_cast<int>(col[i]);
-      if (acc64)
-        atomicAdd(&qd[j], static_cast<double>(c));
-      else
-        atomicAdd(&qf[j], c);
-    }
+    s = sn;
+    e = en;
   }
 }
 
-template <int VK, bool C16, int MODE>
-__global__ __launch_bounds__(kThreads) void k_pass(PassArgs a, int tile_begin) {
+template <int VK, bool C16, int MODE, int ACC, int NT>
+__global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float vmax_sh[NT / 64];
+  constexpr bool kScatter = MODE == PASS_GRAD || MODE == PASS_CG || MODE == PASS_RMATVEC;
   const int ti = tile_begin + static_cast<int>(blockIdx.x);
   const Tile t = a.tiles[ti];
   const Scen sc = a.scen[t.scen];
@@ -182,105 +300,143 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a, int tile_begin) {
   const int n = sc.n;
   float* vsh = reinterpret_cast<float*>(smem);
   const size_t qoff = (static_cast<size_t>(a.nmax) * 4 + 15) & ~static_cast<size_t>(15);
-  float* qf = reinterpret_cast<float*>(smem + qoff);
-  double* qd = reinterpret_cast<double*>(smem + qoff);
-  const bool acc64 = a.acc64 != 0;
-  bool scatter;
-  if constexpr (MODE == PASS_GRAD)
-    scatter = (a.tout == nullptr) && (a.part != nullptr);
-  else
-    scatter = true;
-  const bool given_t = (MODE == PASS_CG) && (a.tin != nullptr);
+  void* qacc = static_cast<void*>(smem + qoff);
 
-  if (!given_t) {
+  float vmax = 0.0f;
+  if constexpr (MODE != PASS_RMATVEC) {
     const float* src = a.src + (a.src_per_scen ? sc.vec_base : a.pat[sc.patient].zvec_base);
-    for (int j = threadIdx.x; j < n; j += kThreads) vsh[j] = src[j];
+    for (int j = threadIdx.x; j < n; j += NT) {
+      const float x = src[j];
+      vsh[j] = x;
+      vmax = fmaxf(vmax, fabsf(x));
+    }
   }
-  if (scatter) {
-    if (acc64)
-      for (int j = threadIdx.x; j < n; j += kThreads) qd[j] = 0.0;
+  if constexpr (kScatter) {
+    if constexpr (ACC == ACC_F32)
+      for (int j = threadIdx.x; j < n; j += NT) static_cast<float*>(qacc)[j] = 0.0f;
     else
-      for (int j = threadIdx.x; j < n; j += kThreads) qf[j] = 0.0f;
+      for (int j = threadIdx.x; j < n; j += NT) static_cast<unsigned long long*>(qacc)[j] = 0ull;
+  }
+  // fixed-point scale: every partial column sum of this tile is below
+  // cmax * (wmax * max|v| + pmax) < 2^61 / 2^F
+  double fscale = 1.0, funscale = 1.0;
+  if constexpr (kScatter && ACC == ACC_FIX64) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+    if ((threadIdx.x & 63) == 0) vmax_sh[threadIdx.x >> 6] = vmax;
+    __syncthreads();
+    float vm = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) vm = fmaxf(vm, vmax_sh[w]);
+    const double tb = static_cast<double>(t.wmax) * vm + (MODE == PASS_GRAD ? static_cast<double>(t.pmax) : 0.0);
+    const double bound = 1.0625 * tb * static_cast<double>(t.cmax);
+    if (bound > 0.0 && isfinite(bound)) {
+      const int F = 60 - ilogb(bound);
+      fscale = ldexp(1.0, F);
+      funscale = ldexp(1.0, -F);
+    }
   }
   __syncthreads();
 
   double objacc = 0.0;
   switch (t.lanes) {
-    case 1: pass_rows<VK, C16, 1, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
-    case 2: pass_rows<VK, C16, 2, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
-    case 4: pass_rows<VK, C16, 4, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
-    case 8: pass_rows<VK, C16, 8, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
-    case 16: pass_rows<VK, C16, 16, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
-    case 32: pass_rows<VK, C16, 32, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
-    default: pass_rows<VK, C16, 64, MODE>(a, t, sc, vsh, qf, qd, acc64, scatter, objacc); break;
+    case 1: pass_rows<VK, C16, 1, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 2: pass_rows<VK, C16, 2, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 4: pass_rows<VK, C16, 4, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 8: pass_rows<VK, C16, 8, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 16: pass_rows<VK, C16, 16, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 32: pass_rows<VK, C16, 32, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    default: pass_rows<VK, C16, 64, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
   }
 
-  if (MODE == PASS_GRAD && a.objpart != nullptr) {
-    __shared__ double sh[4];
+  if constexpr (MODE == PASS_GRAD || MODE == PASS_OBJ) {
+    __shared__ double sh[NT / 64];
     double v[1] = {objacc};
-    block_sum<1>(v, sh);
-    if (threadIdx.x == 0) a.objpart[ti] = v[0];
+    block_sum<1, NT>(v, sh);
+    if (threadIdx.x == 0 && a.objpart != nullptr) a.objpart[ti] = v[0];
   } else {
     __syncthreads();
   }
-  if (scatter) {
+  if constexpr (kScatter) {
     float* out = a.part + t.part_off;
-    if (acc64)
-      for (int j = threadIdx.x; j < n; j += kThreads) out[j] = static_cast<float>(qd[j]);
-    else
-      for (int j = threadIdx.x; j < n; j += kThreads) out[j] = qf[j];
+    if constexpr (ACC == ACC_FIX64) {
+      const long long* qi = static_cast<const long long*>(qacc);
+      for (int j = threadIdx.x; j < n; j += NT) out[j] = static_cast<float>(static_cast<double>(qi[j]) * funscale);
+    } else if constexpr (ACC == ACC_F64) {
+      const double* qd = static_cast<const double*>(qacc);
+      for (int j = threadIdx.x; j < n; j += NT) out[j] = static_cast<float>(qd[j]);
+    } else {
+      const float* qf = static_cast<const float*>(qacc);
+      for (int j = threadIdx.x; j < n; j += NT) out[j] = qf[j];
+    }
   }
 }
 
-int pass_smem_bytes(int nmax, int acc64) {
+int pass_smem_bytes(int nmax, int acc) {
   const int qoff = (nmax * 4 + 15) & ~15;
-  return qoff + nmax * (acc64 ? 8 : 4);
+  return qoff + nmax * (acc == ACC_F32 ? 4 : 8);
 }
 
-template <int VK, bool C16, int MODE>
-static void launch_pass_t(const PassArgs& a, int tile_begin, int tile_count, hipStream_t st) {
-  const int smem = pass_smem_bytes(a.nmax, a.acc64);
-  auto kern = k_pass<VK, C16, MODE>;
+template <int VK, bool C16, int MODE, int ACC, int NT>
+static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStream_t st) {
+  const int smem = pass_smem_bytes(a.nmax, ACC);
+  auto kern = k_pass<VK, C16, MODE, ACC, NT>;
   static bool attr_done = false;
   if (!attr_done && smem > 65536) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                               163840);
     attr_done = true;
   }
-  hipLaunchKernelGGL(kern, dim3(tile_count), dim3(kThreads), smem, st, a, tile_begin);
+  hipLaunchKernelGGL(kern, dim3(tile_count), dim3(NT), smem, st, a, tile_begin);
+}
+
+template <int VK, bool C16, int MODE, int ACC>
+static void launch_nt(const PassArgs& a, int tb, int tc, hipStream_t st) {
+  if (a.threads == 256)
+    launch_k<VK, C16, MODE, ACC, 256>(a, tb, tc, st);
+  else
+    launch_k<VK, C16, MODE, ACC, 512>(a, tb, tc, st);
+}
+
+template <int VK, bool C16, int MODE>
+static void launch_acc(const PassArgs& a, int tb, int tc, hipStream_t st) {
+  if constexpr (MODE == PASS_OBJ || MODE == PASS_MATVEC) {
+    launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st);  // no column accumulators
+  } else if constexpr (MODE == PASS_RMATVEC) {
+    launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st);  // no bound on the given t
+  } else {
+    if (a.acc == ACC_FIX64)
+      launch_nt<VK, C16, MODE, ACC_FIX64>(a, tb, tc, st);
+    else if (a.acc == ACC_F32 && MODE == PASS_CG)
+      launch_nt<VK, C16, MODE, ACC_F32>(a, tb, tc, st);
+    else
+      launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st);
+  }
+}
+
+template <bool C16>
+static void launch_mode(int mode, const PassArgs& a, int tb, int tc, hipStream_t st) {
+  switch (mode) {
+    case PASS_GRAD: launch_acc<VAL_F32, C16, PASS_GRAD>(a, tb, tc, st); break;
+    case PASS_OBJ: launch_acc<VAL_F32, C16, PASS_OBJ>(a, tb, tc, st); break;
+    case PASS_MATVEC: launch_acc<VAL_F32, C16, PASS_MATVEC>(a, tb, tc, st); break;
+    case PASS_RMATVEC: launch_acc<VAL_F32, C16, PASS_RMATVEC>(a, tb, tc, st); break;
+    default:
+      if (a.mat.vkind == VAL_BF16)
+        launch_acc<VAL_BF16, C16, PASS_CG>(a, tb, tc, st);
+      else if (a.mat.vkind == VAL_F16)
+        launch_acc<VAL_F16, C16, PASS_CG>(a, tb, tc, st);
+      else
+        launch_acc<VAL_F32, C16, PASS_CG>(a, tb, tc, st);
+  }
 }
 
 void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hipStream_t st) {
   if (tile_count <= 0) return;
-  const bool c16 = a.mat.col16 != 0;
-  const bool grad = (mode == PASS_GRAD || mode == PASS_OBJ || mode == PASS_MATVEC);
-  if (grad) {
-    if (c16)
-      launch_pass_t<VAL_F32, true, PASS_GRAD>(a, tile_begin, tile_count, st);
-    else
-      launch_pass_t<VAL_F32, false, PASS_GRAD>(a, tile_begin, tile_count, st);
-    return;
-  }
-  switch (a.mat.vkind) {
-    case VAL_BF16:
-      if (c16)
-        launch_pass_t<VAL_BF16, true, PASS_CG>(a, tile_begin, tile_count, st);
-      else
-        launch_pass_t<VAL_BF16, false, PASS_CG>(a, tile_begin, tile_count, st);
-      break;
-    case VAL_F16:
-      if (c16)
-        launch_pass_t<VAL_F16, true, PASS_CG>(a, tile_begin, tile_count, st);
-      else
-        launch_pass_t<VAL_F16, false, PASS_CG>(a, tile_begin, tile_count, st);
-      break;
-    default:
-      if (c16)
-        launch_pass_t<VAL_F32, true, PASS_CG>(a, tile_begin, tile_count, st);
-      else
-        launch_pass_t<VAL_F32, false, PASS_CG>(a, tile_begin, tile_count, st);
-      break;
-  }
+  if (a.mat.col16)
+    launch_mode<true>(mode, a, tile_begin, tile_count, st);
+  else
+    launch_mode<false>(mode, a, tile_begin, tile_count, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,7 +650,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir(VecArgs a) {
     // every block of the scenario writes the same values
     a.rz[g * kRing + k + 1] = rz1;
     a.act[g * kRing + k + 1] = (rz1 > a.tol2[g] && rz1 > 0.0) ? 1 : 0;
-    if (bk.col0 == 0) a.cgcount[g] += 1;
+    if (bk.col0 == 0) {
+      a.cgcount[g] += 1;
+      a.cgtotal[g] += 1;
+    }
   }
 }
 

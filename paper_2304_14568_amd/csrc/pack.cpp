@@ -30,9 +30,11 @@ uint16_t to_f16_bits(float v) {
   return b;
 }
 
-static int lanes_for(int64_t len) {
+// lanes per row for a row of `chunks` 4-element chunks: each lane holds up to
+// kRegChunks chunks in registers
+static int lanes_for(int64_t chunks) {
   int L = 1;
-  while (L < 64 && static_cast<int64_t>(L) * kRegChunks < len) L <<= 1;
+  while (L < 64 && static_cast<int64_t>(L) * kRegChunks < chunks) L <<= 1;
   return L;
 }
 
@@ -42,8 +44,9 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
   int64_t nnz_all = 0;
   for (int p = 0; p < num_patients; ++p)
     for (int s = 0; s < probs[p].num_scen; ++s) nnz_all += probs[p].A[s].nnz;
-  int64_t tile_nnz = o.tile_nnz > 0 ? o.tile_nnz : nnz_all / (256 * 4);
+  int64_t tile_nnz = o.tile_nnz > 0 ? o.tile_nnz : nnz_all / (256 * 8);
   tile_nnz = std::max<int64_t>(8192, std::min<int64_t>(tile_nnz, 1 << 22));
+  const int64_t tile_chunks = std::max<int64_t>(1, tile_nnz / 4);
 
   P.col16_used = true;
   for (int p = 0; p < num_patients; ++p) {
@@ -53,12 +56,13 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
   }
   const bool lp = o.precision != ADMM_PREC_FP32;
   try {
-    P.val.reserve(static_cast<size_t>(nnz_all));
+    const size_t cap = static_cast<size_t>(nnz_all + nnz_all / 16 + 1024);
+    P.val.reserve(cap);
     if (P.col16_used)
-      P.col16.reserve(static_cast<size_t>(nnz_all));
+      P.col16.reserve(cap);
     else
-      P.col32.reserve(static_cast<size_t>(nnz_all));
-    if (lp) P.val_lp.reserve(static_cast<size_t>(nnz_all));
+      P.col32.reserve(cap);
+    if (lp) P.val_lp.reserve(cap);
   } catch (const std::bad_alloc&) {
     if (msg) *msg = "host allocation failed while packing";
     return ADMM_E_OOM;
@@ -140,11 +144,16 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         uint32_t off = 0;
         P.rp.push_back(0);
         std::vector<double> bs(n, 0.0);
+        std::vector<double> row_w(static_cast<size_t>(rows)), row_p(static_cast<size_t>(rows));
         for (int64_t r = 0; r < rows; ++r) {
           const int i = order[static_cast<size_t>(r)];
           const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
           const double cwi = c * w[i];
           float rmax = 0.0f;
+          double rsum = 0.0;
+          for (int64_t k = b; k < e; ++k) rsum += A.val[k];
+          row_w[static_cast<size_t>(r)] = cwi * rsum;
+          row_p[static_cast<size_t>(r)] = cwi * pr.presc[i];
           for (int64_t k = b; k < e; ++k) {
             const int32_t j = A.col[k];
             const float v = A.val[k];
@@ -165,10 +174,21 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
               P.val_lp.push_back(o.precision == ADMM_PREC_BF16 ? to_bf16_bits(q) : to_f16_bits(q));
             }
           }
+          // pad the row to whole 4-element chunks: value 0, column = the row's last column
+          const int64_t len = e - b, len4 = (len + 3) & ~int64_t(3);
+          for (int64_t k = len; k < len4; ++k) {
+            const int32_t j = A.col[e - 1];
+            if (P.col16_used)
+              P.col16.push_back(static_cast<uint16_t>(j));
+            else
+              P.col32.push_back(j);
+            P.val.push_back(0.0f);
+            if (lp) P.val_lp.push_back(0);
+          }
           P.rw.push_back(static_cast<float>(cwi));
           P.rpres.push_back(static_cast<float>(pr.presc[i]));
           P.rorig.push_back(i);
-          off += static_cast<uint32_t>(e - b);
+          off += static_cast<uint32_t>(len4 / 4);
           P.rp.push_back(off);
         }
         for (int j = 0; j < n; ++j) {
@@ -181,11 +201,14 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         sc.tile_begin = static_cast<int32_t>(P.tiles.size());
         int64_t r = 0;
         const uint32_t* rpp = P.rp.data() + rp_base;
+        std::vector<double> colsum(n, 0.0);
+        std::vector<int32_t> touched;
+        auto round_up = [](double x) { return static_cast<float>(x * (1.0 + 1e-6)) ; };
         while (r < rows) {
           const int L = lanes_for(rpp[r + 1] - rpp[r]);
           int64_t r1 = r;
           int64_t nz = 0;
-          while (r1 < rows && lanes_for(rpp[r1 + 1] - rpp[r1]) == L && (nz < tile_nnz || r1 == r)) {
+          while (r1 < rows && lanes_for(rpp[r1 + 1] - rpp[r1]) == L && (nz < tile_chunks || r1 == r)) {
             nz += rpp[r1 + 1] - rpp[r1];
             ++r1;
           }
@@ -194,6 +217,24 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
           t.row_begin = static_cast<int32_t>(r);
           t.row_end = static_cast<int32_t>(r1);
           t.lanes = L;
+          double wm = 0.0, pm = 0.0, cm = 0.0;
+          for (int64_t rr = r; rr < r1; ++rr) {
+            wm = std::max(wm, row_w[static_cast<size_t>(rr)]);
+            pm = std::max(pm, row_p[static_cast<size_t>(rr)]);
+            for (int64_t k = nnz_base + 4 * static_cast<int64_t>(rpp[rr]); k < nnz_base + 4 * static_cast<int64_t>(rpp[rr + 1]); ++k) {
+              const int32_t j = P.col16_used ? P.col16[static_cast<size_t>(k)] : P.col32[static_cast<size_t>(k)];
+              if (colsum[j] == 0.0) touched.push_back(j);
+              colsum[j] += P.val[static_cast<size_t>(k)];
+            }
+          }
+          for (int32_t j : touched) {
+            cm = std::max(cm, colsum[j]);
+            colsum[j] = 0.0;
+          }
+          touched.clear();
+          t.wmax = round_up(wm);
+          t.pmax = round_up(pm);
+          t.cmax = round_up(cm);
           t.part_off = P.part_total;
           P.part_total += n;
           P.tiles.push_back(t);
@@ -201,7 +242,8 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         }
         sc.tile_end = static_cast<int32_t>(P.tiles.size());
         P.scen.push_back(sc);
-        nnz_base += A.nnz;
+        P.scen_nnz.push_back(A.nnz);
+        nnz_base += static_cast<int64_t>(off) * 4;
         row_base += rows;
         rp_base += rows + 1;
         P.vec_total += n;
@@ -228,6 +270,15 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
   } catch (const std::bad_alloc&) {
     if (msg) *msg = "host allocation failed while packing";
     return ADMM_E_OOM;
+  }
+  // trailing zero chunks so that no chunk load can leave the arrays
+  for (int k = 0; k < 256; ++k) {
+    P.val.push_back(0.0f);
+    if (P.col16_used)
+      P.col16.push_back(0);
+    else
+      P.col32.push_back(0);
+    if (lp) P.val_lp.push_back(0);
   }
   P.nnz_total = nnz_base;
   P.rows_total = row_base;

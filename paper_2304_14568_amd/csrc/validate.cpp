@@ -87,8 +87,12 @@ admm_status validate_options(const admm_options* o, std::string* msg) {
     return fail(msg, ADMM_E_ARG, "unknown precision %lld", o->precision);
   if (o->z_mode < 0 || o->z_mode > 1) return fail(msg, ADMM_E_ARG, "z_mode must be 0 or 1");
   if (o->check_every < 1) return fail(msg, ADMM_E_ARG, "check_every must be >= 1");
-  if (o->lds_fp64 < -1 || o->lds_fp64 > 1) return fail(msg, ADMM_E_ARG, "lds_fp64 must be -1, 0 or 1");
+  if (o->lds_acc < -1 || o->lds_acc > 2) return fail(msg, ADMM_E_ARG, "lds_acc must be -1, 0, 1 or 2");
   if (o->tile_nnz < 0) return fail(msg, ADMM_E_ARG, "tile_nnz < 0");
+  if (o->pass_threads != 0 && o->pass_threads != 256 && o->pass_threads != 512)
+    return fail(msg, ADMM_E_ARG, "pass_threads must be 0, 256 or 512");
+  if (o->pass_unroll != 0 && o->pass_unroll != 1)
+    return fail(msg, ADMM_E_ARG, "pass_unroll must be 0 or 1");
   return ADMM_OK;
 }
 
