@@ -8,7 +8,7 @@
 namespace admmbb {
 
 constexpr int kThreads = 256;       // threads per workgroup, all kernels
-constexpr int kColBlock = 256;      // columns handled by one block of a vector kernel
+constexpr int kColBlock = 64;       // columns handled by one block of a vector kernel (one wave)
 constexpr int kMaxCg = 64;          // CG steps per ADMM iteration, upper limit
 constexpr int kRing = kMaxCg + 2;   // per-scenario CG scalar slots
 constexpr int kRegChunks = 4;       // 4-element chunks of a row kept in registers per lane

@@ -46,6 +46,16 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// Sum of p[b * 8] for b < count by one wave: lane l adds entries l, l+64, ...
+// then a fixed butterfly; every lane returns the same total.
+__device__ __forceinline__ double wave_strided_sum(const double* p, int count) {
+  double s = 0.0;
+  for (int b = threadIdx.x & 63; b < count; b += 64) s += p[static_cast<int64_t>(b) * 8];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
 // Deterministic block sum of NV doubles over NT threads; result valid in thread 0.
 template <int NV, int NT = kThreads>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
@@ -444,8 +454,31 @@ void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hi
 // needs the completed column sums
 // ---------------------------------------------------------------------------
 
+// Sum of the partial column sums of tiles [0, ntiles) (tile t's partials at
+// part[t * n + j]) for column j: the four waves of the block take every fourth
+// tile, four loads in flight each, then wave 0 adds the four results in a
+// fixed order.  Returns the total in wave 0 (lane = column offset).
+__device__ __forceinline__ double tile_column_sum(const float* __restrict__ part, int ntiles, int n, int j,
+                                                  double (*red)[64]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (j < n) {
+    int t = w;
+    for (; t + 12 < ntiles; t += 16) {
+      s0 += static_cast<double>(part[static_cast<int64_t>(t) * n + j]);
+      s1 += static_cast<double>(part[static_cast<int64_t>(t + 4) * n + j]);
+      s2 += static_cast<double>(part[static_cast<int64_t>(t + 8) * n + j]);
+      s3 += static_cast<double>(part[static_cast<int64_t>(t + 12) * n + j]);
+    }
+    for (; t < ntiles; t += 4) s0 += static_cast<double>(part[static_cast<int64_t>(t) * n + j]);
+  }
+  red[w][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  return (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, int mode) {
-  __shared__ double sh[4 * 3];
+  __shared__ double red[4][64];
   const int bi = blk_begin + static_cast<int>(blockIdx.x);
   const Blk bk = a.blk[bi];
   const int g = bk.owner;
@@ -456,11 +489,12 @@ __global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, i
     if (ps->stopped) return;
     if (mode == RED_CG && !a.act[g * kRing + a.step]) return;
   }
-  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  const int j = bk.col0 + static_cast<int>(threadIdx.x & 63);
+  const float* part = a.part + a.tiles[sc.tile_begin].part_off;
+  const double s = tile_column_sum(part, sc.tile_end - sc.tile_begin, sc.n, j, red);
+  if (threadIdx.x >= 64) return;
   double loc[3] = {0.0, 0.0, 0.0};
   if (j < sc.n) {
-    double s = 0.0;
-    for (int t = sc.tile_begin; t < sc.tile_end; ++t) s += static_cast<double>(a.part[a.tiles[t].part_off + j]);
     const int64_t vi = sc.vec_base + j;
     if (mode == RED_HEAD) {
       const double rho = ps->rho;
@@ -496,7 +530,8 @@ __global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, i
     }
   }
   if (mode == RED_HEAD || mode == RED_CG) {
-    block_sum<3>(loc, sh);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) loc[k] = wave_sum(loc[k]);
     if (threadIdx.x == 0) {
       double* bp = a.bpart + static_cast<int64_t>(bi) * 8;
       bp[0] = loc[0];
@@ -596,15 +631,13 @@ void launch_head_scalars(const VecArgs& a, int nscen, int cg_setup, hipStream_t 
 // CG vector steps
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_cg_update(VecArgs a) {
-  __shared__ double sh[4];
+__global__ __launch_bounds__(kColBlock) void k_cg_update(VecArgs a) {
   const int bi = static_cast<int>(blockIdx.x);
   const Blk bk = a.blk[bi];
   const int g = bk.owner;
   const Scen sc = a.scen[g];
   if (!a.act[g * kRing + a.step]) return;
-  double vq = 0.0;
-  for (int b = 0; b < sc.nblk; ++b) vq += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 0];
+  const double vq = wave_strided_sum(a.bpart + static_cast<int64_t>(sc.blk_begin) * 8 + 0, sc.nblk);
   const double rz = a.rz[g * kRing + a.step];
   const float alpha = (vq > 0.0) ? static_cast<float>(rz / vq) : 0.0f;
   const int j = bk.col0 + static_cast<int>(threadIdx.x);
@@ -622,11 +655,11 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(VecArgs a) {
     }
     loc[0] = static_cast<double>(rj) * zpv;
   }
-  block_sum<1>(loc, sh);
+  loc[0] = wave_sum(loc[0]);
   if (threadIdx.x == 0) a.bpart[(int64_t)bi * 8 + 3] = loc[0];
 }
 
-__global__ __launch_bounds__(kThreads) void k_cg_dir(VecArgs a) {
+__global__ __launch_bounds__(kColBlock) void k_cg_dir(VecArgs a) {
   const int bi = static_cast<int>(blockIdx.x);
   const Blk bk = a.blk[bi];
   const int g = bk.owner;
@@ -636,8 +669,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir(VecArgs a) {
     if (threadIdx.x == 0) a.act[g * kRing + k + 1] = 0;
     return;
   }
-  double rz1 = 0.0;
-  for (int b = 0; b < sc.nblk; ++b) rz1 += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 3];
+  const double rz1 = wave_strided_sum(a.bpart + static_cast<int64_t>(sc.blk_begin) * 8 + 3, sc.nblk);
   const double rz0 = a.rz[g * kRing + k];
   const float beta = (rz0 > 0.0) ? static_cast<float>(rz1 / rz0) : 0.0f;
   const int j = bk.col0 + static_cast<int>(threadIdx.x);
@@ -658,10 +690,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_dir(VecArgs a) {
 }
 
 void launch_cg_update(const VecArgs& a, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kColBlock), 0, st, a);
 }
 void launch_cg_dir(const VecArgs& a, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_dir, dim3(nblk), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(k_cg_dir, dim3(nblk), dim3(kColBlock), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -669,8 +701,7 @@ void launch_cg_dir(const VecArgs& a, int nblk, hipStream_t st) {
 // workgroup (every quantity is columnwise until the final sums)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
-  __shared__ double sh[4 * 6];
+__global__ __launch_bounds__(kColBlock) void k_zres(VecArgs a) {
   const int bi = static_cast<int>(blockIdx.x);
   const Blk bk = a.pblk[bi];
   const int p = bk.owner;
@@ -708,7 +739,8 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
       a.dprev[vi] = d;
     }
   }
-  block_sum<6>(loc, sh);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) loc[k] = wave_sum(loc[k]);
   if (threadIdx.x == 0) {
     double* bp = a.bpartp + static_cast<int64_t>(bi) * 8;
     for (int k = 0; k < 6; ++k) bp[k] = loc[k];
@@ -716,7 +748,7 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
 }
 
 void launch_zres(const VecArgs& a, int npblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_zres, dim3(npblk), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(k_zres, dim3(npblk), dim3(kColBlock), 0, st, a);
 }
 
 // Residual norms, tolerances and the Barzilai-Borwein dual step per patient.
@@ -772,13 +804,12 @@ void launch_body_scalars(const VecArgs& a, hipStream_t st) {
 __global__ __launch_bounds__(kThreads) void k_gsum(const Scen* scen, const Pat* pat, const Blk* pblk,
                                                    const Tile* tiles, const float* part, int blk_begin,
                                                    float scale, float* out) {
+  __shared__ double red[4][64];
   const Blk bk = pblk[blk_begin + blockIdx.x];
   const Pat pt = pat[bk.owner];
-  const int j = bk.col0 + static_cast<int>(threadIdx.x);
-  if (j >= pt.n) return;
-  double s = 0.0;
-  for (int t = pt.tile_begin; t < pt.tile_end; ++t) s += static_cast<double>(part[tiles[t].part_off + j]);
-  out[j] = static_cast<float>(scale * s);
+  const int j = bk.col0 + static_cast<int>(threadIdx.x & 63);
+  const double s = tile_column_sum(part + tiles[pt.tile_begin].part_off, pt.tile_end - pt.tile_begin, pt.n, j, red);
+  if (threadIdx.x < 64 && j < pt.n) out[j] = static_cast<float>(scale * s);
 }
 
 void launch_gsum(const Scen* scen, const Pat* pat, const Blk* pblk, const Tile* tiles, const float* part,

@@ -280,6 +280,13 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       P.col32.push_back(0);
     if (lp) P.val_lp.push_back(0);
   }
+  // the column reductions address tile t's partials as first_tile_offset + (t - first) * n
+  for (const Pat& pt : P.pat)
+    for (int t = pt.tile_begin; t < pt.tile_end; ++t)
+      if (P.tiles[t].part_off != P.tiles[pt.tile_begin].part_off + static_cast<int64_t>(t - pt.tile_begin) * pt.n) {
+        if (msg) *msg = "internal: tile partials are not contiguous";
+        return ADMM_E_STATE;
+      }
   P.nnz_total = nnz_base;
   P.rows_total = row_base;
   return ADMM_OK;
