@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance measurement")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a reference kernel for HBM byte counters)")
     ap.add_argument("--graph", action="store_true",
                     help="replay each iteration from a captured HIP graph in the throughput region "
                          "(the instrumented region always launches directly)")
@@ -105,6 +107,13 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
+
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     t0 = time.perf_counter()
     P = synth.hn_full(args.seed)

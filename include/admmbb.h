@@ -100,7 +100,7 @@ typedef struct {
   int32_t z_mode;      /* 0: z = P(mean(x_s + y_s/rho)) (default); 1: z = P(mean x_s) as printed in Sec. 2.2 */
   double bb_clamp;     /* 0: none (default); c > 0: tau clamped to [rho/c, rho*c] */
   int32_t cg_max;      /* CG steps per ADMM iteration, 1..64; default 8 */
-  double cg_eta;       /* CG stops at ||r|| <= eta ||c_s||, eta = max(eta_floor, cg_eta*min(1, r_prim/||x||)); default 0.1 */
+  double cg_eta;       /* CG stops at ||r|| <= eta ||c_s||, eta = max(eta_floor, cg_eta*min(1, r_prim/||x||)); default 0.01 */
   double cg_eta_floor; /* default 1e-6 */
   int32_t precision;   /* ADMM_PREC_*: value type of A_s inside CG; the objective and the
                           per-iteration residual always use the fp32 matrix; default FP32 */
@@ -112,7 +112,8 @@ typedef struct {
                           -1 = chosen by the set-up autotuner among 1 and 2 */
   int32_t tile_nnz;    /* target nonzeros per workgroup tile; 0 = automatic */
   int32_t pass_threads; /* fused-pass workgroup size 256 or 512; 0 = chosen by the set-up autotuner */
-  int32_t pass_unroll;  /* reserved: rows per lane group in flight, 0 or 1 */
+  int32_t pass_unroll;  /* 1: row data loaded when the row starts; 2: next row's data in flight during the
+                           current row (software pipelined); 0 = chosen by the autotuner */
   void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
 } admm_options;
 

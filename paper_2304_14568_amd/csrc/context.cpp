@@ -189,9 +189,10 @@ struct admm_ctx {
       pa.act = d_act;
       pa.ps = d_ps;
       pa.objpart = nullptr;
-      if (with_events) check(hipEventRecord(ev[2 * k], stream), "hipEventRecord");
-      launch_pass(PASS_CG, pa, 0, T, stream);
-      if (with_events) check(hipEventRecord(ev[2 * k + 1], stream), "hipEventRecord");
+      if (with_events)
+        launch_pass(PASS_CG, pa, 0, T, stream, ev[2 * k], ev[2 * k + 1]);
+      else
+        launch_pass(PASS_CG, pa, 0, T, stream);
       va.step = k;
       launch_reduce(RED_CG, va, 0, NB, stream);
       launch_cg_update(va, NB, stream);
@@ -299,7 +300,7 @@ struct admm_ctx {
   // and keep the fastest (values of the multiplied vector do not change the work).
   void autotune() {
     const MatDev& m = (opts.precision == ADMM_PREC_FP32) ? mat32 : matlp;
-    std::vector<int> th = {256, 512}, un = {1}, ac = {ACC_FIX64, ACC_F64};
+    std::vector<int> th = {256, 512}, un = {1, 2}, ac = {ACC_FIX64, ACC_F64};
     if (opts.pass_threads) th = {opts.pass_threads};
     if (opts.pass_unroll) un = {opts.pass_unroll};
     if (opts.lds_acc >= 0) ac = {opts.lds_acc};
@@ -440,7 +441,7 @@ admm_status admm_default_options(admm_options* o) {
   o->z_mode = 0;
   o->bb_clamp = 0.0;
   o->cg_max = 8;
-  o->cg_eta = 0.1;
+  o->cg_eta = 0.01;
   o->cg_eta_floor = 1e-6;
   o->precision = ADMM_PREC_FP32;
   o->precond = 0;

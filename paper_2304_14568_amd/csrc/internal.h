@@ -170,7 +170,9 @@ struct VecArgs {
 };
 
 // ---- launchers (kernels.hip) ----
-void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hipStream_t st);
+// e0 / e1 (optional): events stamped at the start and end of the kernel itself
+void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hipStream_t st,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_reduce(int mode, const VecArgs& a, int blk_begin, int nblk, hipStream_t st);
 void launch_head_scalars(const VecArgs& a, int nscen, int cg_setup, hipStream_t st);
 void launch_cg_update(const VecArgs& a, int nblk, hipStream_t st);

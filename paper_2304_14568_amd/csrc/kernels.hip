@@ -10,6 +10,7 @@
 // system of Appendix A without its rho/2 shift).  Each workgroup writes its
 // column partial sums; a column-blocked reduction kernel adds them in a fixed
 // order.  All scalar reductions are float64 and deterministic (fixed trees).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -94,15 +95,13 @@ __device__ __forceinline__ double block_list_sum(int count, F item, double* sh) 
 // the fused pass
 // ---------------------------------------------------------------------------
 
-// Round a scaled contribution (|d| < 2^61) to a two's-complement 64-bit
-// integer: d = hi * 2^32 + lo with lo in [0, 2^32), all steps exact except
-// the final truncation of lo (an error below one fixed-point unit).
+// Round a scaled contribution d (|d| < 2^50) to the nearest integer, as a
+// two's-complement 64-bit value: adding 1.5 * 2^52 moves the rounded integer
+// into the low mantissa bits (exact for |d| < 2^51); subtracting the bit
+// pattern of 1.5 * 2^52, whose low word is zero, leaves the integer.
 __device__ __forceinline__ unsigned long long to_fixed(double d) {
-  const double h = floor(d * 0x1p-32);
-  const double l = fma(h, -0x1p32, d);
-  const uint32_t lo = static_cast<uint32_t>(l);
-  const uint32_t hi = static_cast<uint32_t>(static_cast<int32_t>(h));
-  return (static_cast<unsigned long long>(hi) << 32) | lo;
+  const double r = d + 0x1.8p52;
+  return static_cast<unsigned long long>(__double_as_longlong(r)) - 0x4338000000000000ull;
 }
 
 // 4-element chunk types: values (fp32: one 16-byte load; bf16 / fp16: 8 bytes)
@@ -173,7 +172,7 @@ struct CChunk<false> {
 //       PASS_CG       t_i = c_s w_i a_i.v (fp32 dot), scatter
 //       PASS_RMATVEC  t_i = tin[row], scatter
 // ACC   LDS column accumulators (AccKind)
-template <int VK, bool C16, int L, int MODE, int ACC, int NT>
+template <int VK, bool C16, int L, int MODE, int ACC, int NT, bool PIPE>
 __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, const Scen& sc, const float* vsh,
                                           void* qacc, double fscale, double& objacc) {
   using VC = typename VChunk<VK>::T;
@@ -220,16 +219,12 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
     }
   };
 
-  int r = t.row_begin + grp;
-  uint32_t s = r < rend ? rp[r] : 0u;
-  uint32_t e = r < rend ? rp[r + 1] : 0u;
-  for (; r < rend; r += G) {
-    float vv[K][4];
-    CCk cc[K];
+  // chunks of the row a lane handles next are loaded while the current row computes
+  auto load_row = [&](uint32_t s0, uint32_t e0, float (&vv)[K][4], CCk (&cc)[K]) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const uint32_t c = s + lane + k * L;
-      if (c < e) {
+      const uint32_t c = s0 + lane + k * L;
+      if (c < e0) {
         VChunk<VK>::unpack(valc[c], vv[k]);
         cc[k] = colc[c];
       } else {
@@ -237,6 +232,16 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
         cc[k] = CCk{};
       }
     }
+  };
+
+  int r = t.row_begin + grp;
+  uint32_t s = r < rend ? rp[r] : 0u;
+  uint32_t e = r < rend ? rp[r + 1] : 0u;
+  float vv[K][4];
+  CCk cc[K];
+  if constexpr (PIPE) load_row(s, e, vv, cc);
+  for (; r < rend; r += G) {
+    if constexpr (!PIPE) load_row(s, e, vv, cc);
     float rw;
     float aux = 0.0f;
     if constexpr (MODE == PASS_RMATVEC) {
@@ -252,10 +257,13 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
       else
         aux = 1.0f;
     }
-    // next row's offsets, in flight while this row computes
+    // next row: offsets and (when pipelined) its register chunks, in flight while this row computes
     const int rn = r + G;
     const uint32_t sn = rn < rend ? rp[rn] : 0u;
     const uint32_t en = rn < rend ? rp[rn + 1] : 0u;
+    float vn[K][4];
+    CCk cn[K];
+    if constexpr (PIPE) load_row(sn, en, vn, cn);
 
     float tv = rw;
     if constexpr (kDot) {
@@ -294,10 +302,18 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
     }
     s = sn;
     e = en;
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        cc[k] = cn[k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vv[k][q] = vn[k][q];
+      }
+    }
   }
 }
 
-template <int VK, bool C16, int MODE, int ACC, int NT>
+template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE>
 __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float vmax_sh[NT / 64];
@@ -327,8 +343,8 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
     else
       for (int j = threadIdx.x; j < n; j += NT) static_cast<unsigned long long*>(qacc)[j] = 0ull;
   }
-  // fixed-point scale: every partial column sum of this tile is below
-  // cmax * (wmax * max|v| + pmax) < 2^61 / 2^F
+  // fixed-point scale: every partial column sum of this tile, and every single
+  // contribution, is below cmax * (wmax * max|v| + pmax) < 2^50 / 2^F
   double fscale = 1.0, funscale = 1.0;
   if constexpr (kScatter && ACC == ACC_FIX64) {
 #pragma unroll
@@ -341,7 +357,7 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
     const double tb = static_cast<double>(t.wmax) * vm + (MODE == PASS_GRAD ? static_cast<double>(t.pmax) : 0.0);
     const double bound = 1.0625 * tb * static_cast<double>(t.cmax);
     if (bound > 0.0 && isfinite(bound)) {
-      const int F = 60 - ilogb(bound);
+      const int F = 49 - ilogb(bound);
       fscale = ldexp(1.0, F);
       funscale = ldexp(1.0, -F);
     }
@@ -350,13 +366,13 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
 
   double objacc = 0.0;
   switch (t.lanes) {
-    case 1: pass_rows<VK, C16, 1, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 2: pass_rows<VK, C16, 2, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 4: pass_rows<VK, C16, 4, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 8: pass_rows<VK, C16, 8, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 16: pass_rows<VK, C16, 16, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 32: pass_rows<VK, C16, 32, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    default: pass_rows<VK, C16, 64, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 1: pass_rows<VK, C16, 1, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 2: pass_rows<VK, C16, 2, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 4: pass_rows<VK, C16, 4, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 8: pass_rows<VK, C16, 8, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 16: pass_rows<VK, C16, 16, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    case 32: pass_rows<VK, C16, 32, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    default: pass_rows<VK, C16, 64, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
   }
 
   if constexpr (MODE == PASS_GRAD || MODE == PASS_OBJ) {
@@ -387,66 +403,80 @@ int pass_smem_bytes(int nmax, int acc) {
   return qoff + nmax * (acc == ACC_F32 ? 4 : 8);
 }
 
-template <int VK, bool C16, int MODE, int ACC, int NT>
-static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStream_t st) {
+template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE>
+static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStream_t st, hipEvent_t e0,
+                     hipEvent_t e1) {
   const int smem = pass_smem_bytes(a.nmax, ACC);
-  auto kern = k_pass<VK, C16, MODE, ACC, NT>;
+  auto kern = k_pass<VK, C16, MODE, ACC, NT, PIPE>;
   static bool attr_done = false;
   if (!attr_done && smem > 65536) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                               163840);
     attr_done = true;
   }
-  hipLaunchKernelGGL(kern, dim3(tile_count), dim3(NT), smem, st, a, tile_begin);
+  if (e0 != nullptr)
+    // events stamped by the dispatch itself: kernel start and end
+    hipExtLaunchKernelGGL(kern, dim3(tile_count), dim3(NT), smem, st, e0, e1, 0, a, tile_begin);
+  else
+    hipLaunchKernelGGL(kern, dim3(tile_count), dim3(NT), smem, st, a, tile_begin);
 }
 
 template <int VK, bool C16, int MODE, int ACC>
-static void launch_nt(const PassArgs& a, int tb, int tc, hipStream_t st) {
-  if (a.threads == 256)
-    launch_k<VK, C16, MODE, ACC, 256>(a, tb, tc, st);
-  else
-    launch_k<VK, C16, MODE, ACC, 512>(a, tb, tc, st);
+static void launch_nt(const PassArgs& a, int tb, int tc, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  const bool pipe = a.unroll == 2;
+  if (a.threads == 256) {
+    if (pipe)
+      launch_k<VK, C16, MODE, ACC, 256, true>(a, tb, tc, st, e0, e1);
+    else
+      launch_k<VK, C16, MODE, ACC, 256, false>(a, tb, tc, st, e0, e1);
+  } else {
+    if (pipe)
+      launch_k<VK, C16, MODE, ACC, 512, true>(a, tb, tc, st, e0, e1);
+    else
+      launch_k<VK, C16, MODE, ACC, 512, false>(a, tb, tc, st, e0, e1);
+  }
 }
 
 template <int VK, bool C16, int MODE>
-static void launch_acc(const PassArgs& a, int tb, int tc, hipStream_t st) {
+static void launch_acc(const PassArgs& a, int tb, int tc, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (MODE == PASS_OBJ || MODE == PASS_MATVEC) {
-    launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st);  // no column accumulators
+    launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st, e0, e1);  // no column accumulators
   } else if constexpr (MODE == PASS_RMATVEC) {
-    launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st);  // no bound on the given t
+    launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st, e0, e1);  // no bound on the given t
   } else {
     if (a.acc == ACC_FIX64)
-      launch_nt<VK, C16, MODE, ACC_FIX64>(a, tb, tc, st);
+      launch_nt<VK, C16, MODE, ACC_FIX64>(a, tb, tc, st, e0, e1);
     else if (a.acc == ACC_F32 && MODE == PASS_CG)
-      launch_nt<VK, C16, MODE, ACC_F32>(a, tb, tc, st);
+      launch_nt<VK, C16, MODE, ACC_F32>(a, tb, tc, st, e0, e1);
     else
-      launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st);
+      launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st, e0, e1);
   }
 }
 
 template <bool C16>
-static void launch_mode(int mode, const PassArgs& a, int tb, int tc, hipStream_t st) {
+static void launch_mode(int mode, const PassArgs& a, int tb, int tc, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   switch (mode) {
-    case PASS_GRAD: launch_acc<VAL_F32, C16, PASS_GRAD>(a, tb, tc, st); break;
-    case PASS_OBJ: launch_acc<VAL_F32, C16, PASS_OBJ>(a, tb, tc, st); break;
-    case PASS_MATVEC: launch_acc<VAL_F32, C16, PASS_MATVEC>(a, tb, tc, st); break;
-    case PASS_RMATVEC: launch_acc<VAL_F32, C16, PASS_RMATVEC>(a, tb, tc, st); break;
+    case PASS_GRAD: launch_acc<VAL_F32, C16, PASS_GRAD>(a, tb, tc, st, e0, e1); break;
+    case PASS_OBJ: launch_acc<VAL_F32, C16, PASS_OBJ>(a, tb, tc, st, e0, e1); break;
+    case PASS_MATVEC: launch_acc<VAL_F32, C16, PASS_MATVEC>(a, tb, tc, st, e0, e1); break;
+    case PASS_RMATVEC: launch_acc<VAL_F32, C16, PASS_RMATVEC>(a, tb, tc, st, e0, e1); break;
     default:
       if (a.mat.vkind == VAL_BF16)
-        launch_acc<VAL_BF16, C16, PASS_CG>(a, tb, tc, st);
+        launch_acc<VAL_BF16, C16, PASS_CG>(a, tb, tc, st, e0, e1);
       else if (a.mat.vkind == VAL_F16)
-        launch_acc<VAL_F16, C16, PASS_CG>(a, tb, tc, st);
+        launch_acc<VAL_F16, C16, PASS_CG>(a, tb, tc, st, e0, e1);
       else
-        launch_acc<VAL_F32, C16, PASS_CG>(a, tb, tc, st);
+        launch_acc<VAL_F32, C16, PASS_CG>(a, tb, tc, st, e0, e1);
   }
 }
 
-void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hipStream_t st) {
+void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hipStream_t st, hipEvent_t e0,
+                 hipEvent_t e1) {
   if (tile_count <= 0) return;
   if (a.mat.col16)
-    launch_mode<true>(mode, a, tile_begin, tile_count, st);
+    launch_mode<true>(mode, a, tile_begin, tile_count, st, e0, e1);
   else
-    launch_mode<false>(mode, a, tile_begin, tile_count, st);
+    launch_mode<false>(mode, a, tile_begin, tile_count, st, e0, e1);
 }
 
 // ---------------------------------------------------------------------------

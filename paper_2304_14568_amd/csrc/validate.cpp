@@ -91,8 +91,8 @@ admm_status validate_options(const admm_options* o, std::string* msg) {
   if (o->tile_nnz < 0) return fail(msg, ADMM_E_ARG, "tile_nnz < 0");
   if (o->pass_threads != 0 && o->pass_threads != 256 && o->pass_threads != 512)
     return fail(msg, ADMM_E_ARG, "pass_threads must be 0, 256 or 512");
-  if (o->pass_unroll != 0 && o->pass_unroll != 1)
-    return fail(msg, ADMM_E_ARG, "pass_unroll must be 0 or 1");
+  if (o->pass_unroll != 0 && o->pass_unroll != 1 && o->pass_unroll != 2)
+    return fail(msg, ADMM_E_ARG, "pass_unroll must be 0, 1 or 2");
   return ADMM_OK;
 }
 
