@@ -150,9 +150,13 @@ admm_status admm_setup(const admm_problem* prob, const admm_options* opts, admm_
 admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, const admm_options* opts,
                              admm_ctx** out);
 
-/* Reset every patient to z = P(z0) (z0 NULL: 0), y = 0, iteration 0.
- * rho > 0 replaces the penalty of that patient (rho <= 0 keeps it). */
-admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, double rho);
+/* Restart one patient from z = P(z0) (z0 NULL: 0), iteration 0.
+ * rho > 0 replaces the penalty of that patient (rho <= 0 keeps it).
+ * dual_init = 0: y_s = 0.  dual_init = 1: y_s = -grad f_s(z) for every scenario,
+ * the duals for which x_s = z solves every x-update subproblem exactly (from the
+ * optimality condition of the subproblem of Sec. 2.2), computed on the GPU. */
+admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, double rho, int32_t dual_init);
+/* Restart every patient from z = P(0), y = 0, iteration 0. */
 admm_status admm_reset(admm_ctx* ctx);
 
 /* Run exactly k ADMM iterations for every patient, without the stopping test.
@@ -186,6 +190,18 @@ admm_status admm_matvec(admm_ctx* ctx, int32_t patient, int32_t scen, const floa
 admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const float* t, float* out);
 admm_status admm_normal_apply(admm_ctx* ctx, int32_t patient, int32_t scen, int32_t precision, const float* v,
                               float* out);
+
+/* Dose-derived per-spot features for the learned warm start, computed on the GPU
+ * from A_s^T applied to voxel indicator vectors.  voxel_class[m]: 0 other,
+ * 1 target, 2 organ at risk.  feat: n x ADMM_NUM_DOSE_FEATURES floats, row-major:
+ *   0..2  mean / min / max over scenarios of the target share of the spot's dose
+ *         (sum_{i in targets} a_ij / sum_i a_ij)
+ *   3..4  mean / max over scenarios of the organ-at-risk share
+ *   5     log(1 + mean over scenarios of sum_i a_ij)
+ *   6     sum_s (A_s^T c_s W p)_j / sum_s (A_s^T c_s W A_s)_jj, the intensity that
+ *         would minimise f if spot j acted alone */
+#define ADMM_NUM_DOSE_FEATURES 7
+admm_status admm_spot_features(admm_ctx* ctx, int32_t patient, const uint8_t* voxel_class, float* feat);
 
 /* Penalty rho in use for a patient. */
 admm_status admm_get_rho(const admm_ctx* ctx, int32_t patient, double* rho);
@@ -233,6 +249,35 @@ void admm_destroy(admm_ctx* ctx);
 
 /* Host-only validation of a problem (the checks admm_setup performs first). */
 admm_status admm_validate(const admm_problem* prob);
+
+/* ---- Learned warm start: a small network trained and run on the GPU ----
+ * Not part of the paper's method.  For the spots of one patient (rows of X,
+ * rows x nin, row-major float32):
+ *   h1 = relu(X W1^T + b1), h2 = relu(h1 W2^T + b2), y = softplus(h2 . w3 + b3)
+ * predicts the spot intensities z0 (>= 0), and lr = mean_rows(h2) . wr + br the
+ * log of the penalty scale rho / rho_default.  Loss for training:
+ *   L = mean_rows (y - target)^2 + lam (lr - target_log_rho)^2.
+ * Parameters (float32, flat): W1[hidden x nin], b1[hidden], W2[hidden x hidden],
+ * b2[hidden], w3[hidden], b3, wr[hidden], br. */
+typedef struct admm_mlp admm_mlp;
+/* He-uniform weights from a splitmix64 stream seeded with `seed`, zero biases. */
+admm_status mlp_create(int32_t nin, int32_t hidden, uint64_t seed, void* stream, admm_mlp** out);
+void mlp_destroy(admm_mlp* net);
+int64_t mlp_num_params(const admm_mlp* net);
+admm_status mlp_get_params(admm_mlp* net, float* out);
+/* Also clears the Adam moments and step count. */
+admm_status mlp_set_params(admm_mlp* net, const float* in);
+/* precision: ADMM_PREC_FP32, or ADMM_PREC_BF16 (hidden activations rounded to
+ * bf16, fp32 accumulation).  y_out: rows floats (may be NULL). */
+admm_status mlp_forward(admm_mlp* net, const float* X, int32_t rows, int32_t precision, float* y_out,
+                        float* log_rho_out);
+/* Loss and its gradient with respect to every parameter (grad_out: num_params
+ * floats, may be NULL); the gradient is kept for mlp_adam_step. */
+admm_status mlp_loss_grad(admm_mlp* net, const float* X, const float* target, int32_t rows, float target_log_rho,
+                          float lam, double* loss_out, float* grad_out);
+/* One Adam update with the last gradient. */
+admm_status mlp_adam_step(admm_mlp* net, float lr, float beta1, float beta2, float eps);
+const char* mlp_last_error(void);
 
 #ifdef __cplusplus
 }

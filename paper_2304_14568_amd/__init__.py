@@ -26,8 +26,11 @@ EXPORTS = [
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
     "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
-    "admm_last_error", "admm_destroy", "admm_validate",
+    "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features",
+    "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
+    "mlp_loss_grad", "mlp_adam_step", "mlp_last_error",
 ]
+NUM_DOSE_FEATURES = 7
 
 
 class AdmmError(RuntimeError):
@@ -85,7 +88,14 @@ def _load():
         "pgd_default_options": [ctypes.POINTER(PgdOptionsC)],
         "admm_setup": [ctypes.POINTER(ProblemC), ctypes.POINTER(OptionsC), ctypes.POINTER(P)],
         "admm_setup_batch": [ctypes.POINTER(ProblemC), i32, ctypes.POINTER(OptionsC), ctypes.POINTER(P)],
-        "admm_warm_start": [P, i32, P, dbl],
+        "admm_warm_start": [P, i32, P, dbl, i32],
+        "admm_spot_features": [P, i32, P, P],
+        "mlp_create": [i32, i32, ctypes.c_uint64, P, ctypes.POINTER(P)],
+        "mlp_get_params": [P, P],
+        "mlp_set_params": [P, P],
+        "mlp_forward": [P, P, i32, i32, P, P],
+        "mlp_loss_grad": [P, P, P, i32, ctypes.c_float, ctypes.c_float, P, P],
+        "mlp_adam_step": [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
         "admm_reset": [P],
         "admm_iterate": [P, i32, P],
         "admm_solve": [P, P, P],
@@ -116,6 +126,12 @@ def _load():
     lib.admm_last_error.restype = ctypes.c_char_p
     lib.admm_destroy.argtypes = [P]
     lib.admm_destroy.restype = None
+    lib.mlp_destroy.argtypes = [P]
+    lib.mlp_destroy.restype = None
+    lib.mlp_num_params.argtypes = [P]
+    lib.mlp_num_params.restype = ctypes.c_int64
+    lib.mlp_last_error.argtypes = []
+    lib.mlp_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -240,9 +256,16 @@ class Solver:
     def reset(self):
         _check(self.ctx, lib.admm_reset(self.ctx))
 
-    def warm_start(self, patient: int, z0: Optional[np.ndarray] = None, rho: float = 0.0):
+    def warm_start(self, patient: int, z0: Optional[np.ndarray] = None, rho: float = 0.0, dual_init: bool = False):
         z = None if z0 is None else np.ascontiguousarray(z0, dtype=np.float64)
-        _check(self.ctx, lib.admm_warm_start(self.ctx, patient, _ptr(z), float(rho)))
+        _check(self.ctx, lib.admm_warm_start(self.ctx, patient, _ptr(z), float(rho), 1 if dual_init else 0))
+
+    def spot_features(self, voxel_class, patient: int = 0):
+        """Dose-derived per-spot features (n x NUM_DOSE_FEATURES), computed on the GPU."""
+        vc = np.ascontiguousarray(voxel_class, dtype=np.uint8)
+        out = np.zeros((self.n[patient], NUM_DOSE_FEATURES), dtype=np.float32)
+        _check(self.ctx, lib.admm_spot_features(self.ctx, patient, vc.ctypes.data, out.ctypes.data))
+        return out
 
     def pgd(self, patient: int = 0, x0: Optional[np.ndarray] = None, **kw):
         o = PgdOptionsC()
@@ -351,3 +374,63 @@ class Solver:
         c = ctypes.c_int32()
         _check(self.ctx, lib.admm_get_timing(self.ctx, ctypes.byref(t), ctypes.byref(p), ctypes.byref(c)))
         return dict(total_ms=t.value, pass_ms=p.value, pass_launches=c.value)
+
+
+def _mlp_check(code: int):
+    if code < 0:
+        raise AdmmError(code, lib.mlp_last_error().decode(errors="replace"))
+    return code
+
+
+class Mlp:
+    """The warm-start network of the library (training and inference on the GPU)."""
+
+    def __init__(self, nin: int, hidden: int = 128, seed: int = 0, stream=None):
+        st = None if stream is None else int(getattr(stream, "cuda_stream", stream))
+        h = ctypes.c_void_p()
+        _mlp_check(lib.mlp_create(int(nin), int(hidden), ctypes.c_uint64(seed), st, ctypes.byref(h)))
+        self.h = h
+        self.nin, self.hidden = int(nin), int(hidden)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def num_params(self) -> int:
+        return int(lib.mlp_num_params(self.h))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, dtype=np.float32)
+        _mlp_check(lib.mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, theta) -> None:
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.shape[0] != self.num_params:
+            raise ValueError("parameter count mismatch")
+        _mlp_check(lib.mlp_set_params(self.h, t.ctypes.data))
+
+    def forward(self, X, precision="fp32"):
+        Xa = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.zeros(Xa.shape[0], dtype=np.float32)
+        lr = ctypes.c_float()
+        pr = PREC[precision] if isinstance(precision, str) else int(precision)
+        _mlp_check(lib.mlp_forward(self.h, Xa.ctypes.data, Xa.shape[0], pr, y.ctypes.data, ctypes.byref(lr)))
+        return y, lr.value
+
+    def loss_grad(self, X, target, target_log_rho: float = 0.0, lam: float = 0.0, want_grad: bool = True):
+        Xa = np.ascontiguousarray(X, dtype=np.float32)
+        ta = np.ascontiguousarray(target, dtype=np.float32)
+        loss = ctypes.c_double()
+        g = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
+        _mlp_check(lib.mlp_loss_grad(self.h, Xa.ctypes.data, ta.ctypes.data, Xa.shape[0], float(target_log_rho),
+                                     float(lam), ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        _mlp_check(lib.mlp_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps)))

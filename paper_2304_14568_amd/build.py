@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadmmbb.so")
-SOURCES = ["kernels.hip", "context.cpp", "pack.cpp", "validate.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "context.cpp", "pack.cpp", "validate.cpp"]
 ARCH = os.environ.get("ADMMBB_ARCH", "gfx950")
 
 

@@ -635,7 +635,7 @@ admm_status admm_get_timing(const admm_ctx* ctx, double* total_ms, double* pass_
   return ADMM_OK;
 }
 
-admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, double rho) {
+admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, double rho, int32_t dual_init) {
   admm_status st = check_patient(ctx, patient);
   if (st != ADMM_OK) return st;
   if (!std::isfinite(rho)) return set_err(ctx, ADMM_E_ARG, "rho not finite");
@@ -644,8 +644,94 @@ admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, do
       if (!std::isfinite(z0[j])) return set_err(ctx, ADMM_E_NONFINITE, "z0 has a non-finite entry");
   if (rho > 0 && ctx->opts.precond)
     return set_err(ctx, ADMM_E_STATE, "changing rho is not supported with the Jacobi preconditioner");
+  if (dual_init != 0 && dual_init != 1) return set_err(ctx, ADMM_E_ARG, "dual_init must be 0 or 1");
   GUARD_BEGIN
   ctx->reset_patient(patient, z0, rho);
+  if (dual_init) {
+    // y_s = -grad f_s(z): one gradient pass at z over this patient's tiles
+    const Pat& pt = ctx->H.pat[patient];
+    PassArgs pa = ctx->pass_args(ctx->mat32);
+    pa.src = ctx->d_z;
+    pa.src_per_scen = 0;
+    launch_pass(PASS_GRAD, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, ctx->stream);
+    VecArgs va = ctx->vec_args(0);
+    const Scen& s0 = ctx->H.scen[pt.scen_begin];
+    const Scen& s1 = ctx->H.scen[pt.scen_begin + pt.num_scen - 1];
+    launch_reduce(RED_DUALINIT, va, s0.blk_begin, s1.blk_begin + s1.nblk - s0.blk_begin, ctx->stream);
+    check(hipStreamSynchronize(ctx->stream), "sync");
+  }
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_spot_features(admm_ctx* ctx, int32_t patient, const uint8_t* voxel_class, float* feat) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!voxel_class || !feat) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  const Pat& pt = ctx->H.pat[patient];
+  for (int i = 0; i < pt.m; ++i)
+    if (voxel_class[i] > 2) return set_err(ctx, ADMM_E_ARG, "voxel_class entries must be 0, 1 or 2");
+  GUARD_BEGIN
+  const int n = pt.n, m = pt.m, N = pt.num_scen;
+  // indicator vectors of targets, organs at risk and all voxels
+  std::vector<float> ind(static_cast<size_t>(3) * m);
+  for (int i = 0; i < m; ++i) {
+    ind[i] = voxel_class[i] == 1 ? 1.0f : 0.0f;
+    ind[static_cast<size_t>(m) + i] = voxel_class[i] == 2 ? 1.0f : 0.0f;
+    ind[static_cast<size_t>(2) * m + i] = 1.0f;
+  }
+  float* d_ind = nullptr;
+  check(hipMalloc(reinterpret_cast<void**>(&d_ind), sizeof(float) * ind.size()), "hipMalloc");
+  std::vector<float> col(static_cast<size_t>(3) * N * n);
+  try {
+    check(hipMemcpy(d_ind, ind.data(), sizeof(float) * ind.size(), hipMemcpyHostToDevice), "H2D");
+    for (int s = 0; s < N; ++s) {
+      const Scen& sc = ctx->H.scen[pt.scen_begin + s];
+      for (int c = 0; c < 3; ++c) {
+        PassArgs pa = ctx->pass_args(ctx->mat32);
+        pa.tin = d_ind + static_cast<size_t>(c) * m;
+        pa.objpart = nullptr;
+        launch_pass(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+        VecArgs va = ctx->vec_args(0);
+        va.out = ctx->d_pvec2 + pt.zvec_base;
+        launch_reduce(RED_RMAT, va, sc.blk_begin, sc.nblk, ctx->stream);
+        check(hipMemcpyAsync(col.data() + (static_cast<size_t>(c) * N + s) * n, va.out, sizeof(float) * n,
+                             hipMemcpyDeviceToHost, ctx->stream),
+              "D2H");
+      }
+    }
+    check(hipStreamSynchronize(ctx->stream), "sync");
+  } catch (...) {
+    (void)hipFree(d_ind);
+    throw;
+  }
+  (void)hipFree(d_ind);
+  const int64_t vb = ctx->H.scen[pt.scen_begin].vec_base;
+  for (int j = 0; j < n; ++j) {
+    double ft_sum = 0, ft_min = 1e300, ft_max = -1e300, fo_sum = 0, fo_max = -1e300, mass_sum = 0, bsum = 0, gsum = 0;
+    for (int s = 0; s < N; ++s) {
+      const double T = col[(static_cast<size_t>(0) * N + s) * n + j];
+      const double O = col[(static_cast<size_t>(1) * N + s) * n + j];
+      const double M = col[(static_cast<size_t>(2) * N + s) * n + j];
+      const double ft = M > 0 ? T / M : 0.0, fo = M > 0 ? O / M : 0.0;
+      ft_sum += ft;
+      ft_min = std::min(ft_min, ft);
+      ft_max = std::max(ft_max, ft);
+      fo_sum += fo;
+      fo_max = std::max(fo_max, fo);
+      mass_sum += M;
+      bsum += ctx->H.b[vb + static_cast<int64_t>(s) * n + j];
+      gsum += ctx->H.gdiag[vb + static_cast<int64_t>(s) * n + j];
+    }
+    float* f = feat + static_cast<size_t>(j) * ADMM_NUM_DOSE_FEATURES;
+    f[0] = static_cast<float>(ft_sum / N);
+    f[1] = static_cast<float>(ft_min);
+    f[2] = static_cast<float>(ft_max);
+    f[3] = static_cast<float>(fo_sum / N);
+    f[4] = static_cast<float>(fo_max);
+    f[5] = static_cast<float>(std::log1p(mass_sum / N));
+    f[6] = static_cast<float>(gsum > 0 ? bsum / gsum : 0.0);
+  }
   return ADMM_OK;
   GUARD_END(ctx)
 }

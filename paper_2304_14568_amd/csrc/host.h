@@ -30,6 +30,7 @@ struct Packed {
   std::vector<int32_t> rorig;
   std::vector<float> b;           // A_s^T c_s W p per scenario (stacked)
   std::vector<float> dinv;        // Jacobi inverse diagonal (stacked), filled when requested
+  std::vector<float> gdiag;       // (A_s^T c_s W A_s)_jj per scenario (stacked)
   std::vector<double> gdiag_mean; // per patient: mean over scenarios and spots of (A_s^T c_s W A_s)_jj
   std::vector<std::vector<double>> g0;  // per patient: 2 sum_s b_s
   std::vector<float> lb, ub;      // per patient stacked

@@ -15,7 +15,7 @@ constexpr int kRegChunks = 4;       // 4-element chunks of a row kept in registe
 
 enum PassMode { PASS_GRAD = 0, PASS_CG = 1, PASS_OBJ = 2, PASS_MATVEC = 3, PASS_RMATVEC = 4 };
 enum ValKind { VAL_F32 = 0, VAL_BF16 = 1, VAL_F16 = 2 };
-enum RedMode { RED_HEAD = 0, RED_CG = 1, RED_NORMAL = 2, RED_RMAT = 3 };
+enum RedMode { RED_HEAD = 0, RED_CG = 1, RED_NORMAL = 2, RED_RMAT = 3, RED_DUALINIT = 4 };
 // LDS column accumulators of the fused pass: float atomics, double atomics, or
 // 64-bit fixed point (integer atomics, exact and order-independent sums).
 enum AccKind { ACC_F32 = 0, ACC_F64 = 1, ACC_FIX64 = 2 };

@@ -555,6 +555,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, i
       loc[0] = static_cast<double>(vj) * qj;
     } else if (mode == RED_NORMAL) {
       a.out[j] = static_cast<float>(s + 0.5 * a.rho_out * a.v[vi]);
+    } else if (mode == RED_DUALINIT) {
+      // s = A_s^T c_s W (A_s z - p) = grad f_s(z) / 2
+      a.y[vi] = static_cast<float>(-2.0 * s);
     } else {
       a.out[j] = static_cast<float>(s);
     }

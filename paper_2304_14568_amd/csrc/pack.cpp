@@ -192,6 +192,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
           P.rp.push_back(off);
         }
         for (int j = 0; j < n; ++j) {
+          P.gdiag.push_back(static_cast<float>(gdiag[s][j]));
           P.b.push_back(static_cast<float>(bs[j]));
           g0[j] += 2.0 * bs[j];
           gsum += gdiag[s][j];
