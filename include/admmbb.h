@@ -191,6 +191,22 @@ admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const flo
 admm_status admm_normal_apply(admm_ctx* ctx, int32_t patient, int32_t scen, int32_t precision, const float* v,
                               float* out);
 
+/* Dose statistics of a plan x (n doubles, host) for dose-volume evaluation
+ * (Sec. 3: dose-volume histograms and D98 / Dmax / D3 / Dmean metrics).
+ * Voxel i belongs to group voxel_group[i] < num_groups (<= 256), for example
+ * its structure.  For every scenario s and group g, with d = A_s x (fp32
+ * matrix, fp64 row sums rounded to fp32) and bin width w = dmax / nbins:
+ *   counts[(s*G + g)*nbins + k] = #{i in g : k w <= d_i < (k+1) w}; doses below
+ *                                 0 count in bin 0, doses >= dmax in bin nbins-1
+ *   sums[s*G + g]  = sum of d_i over the group (fp64)
+ *   maxes[s*G + g] = max of d_i over the group (-inf for an empty group)
+ * dose_out (may be NULL): the N*m doses, scenario-major, original voxel order.
+ * Requires 12 G + 4 G nbins <= 65536 (the per-block histograms live in LDS).
+ * Counts and maxima are exact; sums are order-dependent in the last bits. */
+admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, const uint8_t* voxel_group,
+                            int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
+                            float* maxes, float* dose_out);
+
 /* Dose-derived per-spot features for the learned warm start, computed on the GPU
  * from A_s^T applied to voxel indicator vectors.  voxel_class[m]: 0 other,
  * 1 target, 2 organ at risk.  feat: n x ADMM_NUM_DOSE_FEATURES floats, row-major:

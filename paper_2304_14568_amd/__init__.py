@@ -26,7 +26,7 @@ EXPORTS = [
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
     "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
-    "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features",
+    "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
     "mlp_loss_grad", "mlp_adam_step", "mlp_last_error",
 ]
@@ -90,6 +90,7 @@ def _load():
         "admm_setup_batch": [ctypes.POINTER(ProblemC), i32, ctypes.POINTER(OptionsC), ctypes.POINTER(P)],
         "admm_warm_start": [P, i32, P, dbl, i32],
         "admm_spot_features": [P, i32, P, P],
+        "admm_dose_stats": [P, i32, P, P, i32, i32, dbl, P, P, P, P],
         "mlp_create": [i32, i32, ctypes.c_uint64, P, ctypes.POINTER(P)],
         "mlp_get_params": [P, P],
         "mlp_set_params": [P, P],
@@ -266,6 +267,22 @@ class Solver:
         out = np.zeros((self.n[patient], NUM_DOSE_FEATURES), dtype=np.float32)
         _check(self.ctx, lib.admm_spot_features(self.ctx, patient, vc.ctypes.data, out.ctypes.data))
         return out
+
+    def dose_stats(self, x, voxel_group, num_groups: int, nbins: int, dmax: float, patient: int = 0,
+                   want_dose: bool = False):
+        """Per-scenario, per-group dose histograms, sums and maxima of plan x
+        (computed on the GPU); returns (counts[N,G,nbins], sums[N,G], maxes[N,G], doses[N,m] or None)."""
+        N, m = self.num_scen[patient], self.m[patient]
+        xa = np.ascontiguousarray(x, dtype=np.float64)
+        grp = np.ascontiguousarray(voxel_group, dtype=np.uint8)
+        counts = np.zeros((N, num_groups, nbins), dtype=np.uint32)
+        sums = np.zeros((N, num_groups))
+        maxes = np.zeros((N, num_groups), dtype=np.float32)
+        dose = np.zeros((N, m), dtype=np.float32) if want_dose else None
+        _check(self.ctx, lib.admm_dose_stats(self.ctx, patient, xa.ctypes.data, grp.ctypes.data, int(num_groups),
+                                             int(nbins), float(dmax), counts.ctypes.data, sums.ctypes.data,
+                                             maxes.ctypes.data, _ptr(dose)))
+        return counts, sums, maxes, dose
 
     def pgd(self, patient: int = 0, x0: Optional[np.ndarray] = None, **kw):
         o = PgdOptionsC()

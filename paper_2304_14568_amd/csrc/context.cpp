@@ -896,6 +896,86 @@ admm_status admm_matvec(admm_ctx* ctx, int32_t patient, int32_t scen, const floa
   GUARD_END(ctx)
 }
 
+admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, const uint8_t* voxel_group,
+                            int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
+                            float* maxes, float* dose_out) {
+  admm_status st = check_patient(ctx, patient);
+  if (st != ADMM_OK) return st;
+  if (!x || !voxel_group || !counts || !sums || !maxes) return set_err(ctx, ADMM_E_ARG, "NULL argument");
+  if (num_groups < 1 || num_groups > 256 || nbins < 1 || !(dmax > 0) || !std::isfinite(dmax) ||
+      dose_hist_smem_bytes(num_groups, nbins) > 65536)
+    return set_err(ctx, ADMM_E_ARG, "need 1 <= num_groups <= 256, nbins >= 1, 12 G + 4 G nbins <= 65536, dmax > 0");
+  const Pat& pt = ctx->H.pat[patient];
+  for (int i = 0; i < pt.m; ++i)
+    if (voxel_group[i] >= num_groups) return set_err(ctx, ADMM_E_ARG, "voxel_group entry >= num_groups");
+  for (int j = 0; j < pt.n; ++j)
+    if (!std::isfinite(x[j])) return set_err(ctx, ADMM_E_NONFINITE, "x is not finite");
+  GUARD_BEGIN
+  const int N = pt.num_scen, m = pt.m, G = num_groups;
+  const size_t per = static_cast<size_t>(G) * nbins;
+  uint8_t* d_grp = nullptr;
+  uint32_t* d_cnt = nullptr;
+  uint32_t* d_key = nullptr;
+  double* d_sum = nullptr;
+  auto release = [&]() {
+    if (d_grp) (void)hipFree(d_grp);
+    if (d_cnt) (void)hipFree(d_cnt);
+    if (d_key) (void)hipFree(d_key);
+    if (d_sum) (void)hipFree(d_sum);
+  };
+  std::vector<uint32_t> keys(static_cast<size_t>(N) * G);
+  try {
+    check(hipMalloc(reinterpret_cast<void**>(&d_grp), m), "hipMalloc");
+    check(hipMalloc(reinterpret_cast<void**>(&d_cnt), sizeof(uint32_t) * per * N), "hipMalloc");
+    check(hipMalloc(reinterpret_cast<void**>(&d_key), sizeof(uint32_t) * G * N), "hipMalloc");
+    check(hipMalloc(reinterpret_cast<void**>(&d_sum), sizeof(double) * G * N), "hipMalloc");
+    check(hipMemcpyAsync(d_grp, voxel_group, m, hipMemcpyHostToDevice, ctx->stream), "H2D");
+    check(hipMemsetAsync(d_cnt, 0, sizeof(uint32_t) * per * N, ctx->stream), "memset");
+    check(hipMemsetAsync(d_key, 0, sizeof(uint32_t) * G * N, ctx->stream), "memset");
+    launch_fill_f64(d_sum, 0.0, static_cast<int64_t>(G) * N, ctx->stream);
+    ctx->upload_pvec(patient, x, ctx->d_pvec);
+    const float inv_w = static_cast<float>(nbins / dmax);
+    for (int s = 0; s < N; ++s) {
+      const Scen& sc = ctx->H.scen[pt.scen_begin + s];
+      launch_fill_f32(ctx->d_mvec, 0.0f, m, ctx->stream);
+      PassArgs pa = ctx->pass_args(ctx->mat32);
+      pa.src = ctx->d_pvec;
+      pa.src_per_scen = 0;
+      pa.tout = ctx->d_mvec;
+      pa.objpart = nullptr;
+      launch_pass(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+      launch_dose_hist(ctx->d_mvec, d_grp, m, G, nbins, inv_w, d_cnt + per * s, d_sum + static_cast<size_t>(G) * s,
+                       d_key + static_cast<size_t>(G) * s, ctx->stream);
+      if (dose_out)
+        check(hipMemcpyAsync(dose_out + static_cast<size_t>(s) * m, ctx->d_mvec, sizeof(float) * m,
+                             hipMemcpyDeviceToHost, ctx->stream),
+              "D2H");
+    }
+    check(hipGetLastError(), "launch");
+    check(hipMemcpyAsync(counts, d_cnt, sizeof(uint32_t) * per * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    check(hipMemcpyAsync(sums, d_sum, sizeof(double) * G * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    check(hipMemcpyAsync(keys.data(), d_key, sizeof(uint32_t) * G * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    check(hipStreamSynchronize(ctx->stream), "sync");
+  } catch (...) {
+    release();
+    throw;
+  }
+  release();
+  for (size_t k = 0; k < keys.size(); ++k) {
+    const uint32_t key = keys[k];
+    if (key == 0u) {
+      maxes[k] = -INFINITY;  // empty group
+      continue;
+    }
+    const uint32_t u = (key & 0x80000000u) ? (key & 0x7fffffffu) : ~key;
+    float f;
+    std::memcpy(&f, &u, sizeof(f));
+    maxes[k] = f;
+  }
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
 admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const float* t, float* out) {
   int g = 0;
   admm_status st = scen_index(ctx, patient, scen, &g);

@@ -190,5 +190,8 @@ void launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
 void launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st);
 int pass_smem_bytes(int nmax, int acc);
+int dose_hist_smem_bytes(int G, int nbins);
+void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
+                      double* sums, uint32_t* maxkey, hipStream_t st);
 
 }  // namespace admmbb
