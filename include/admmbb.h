@@ -90,6 +90,8 @@ typedef struct {
   const double* ub;
 } admm_problem;
 
+enum { ADMM_XUPDATE_AUTO = -1, ADMM_XUPDATE_CG = 0, ADMM_XUPDATE_DENSE = 1 };
+
 typedef struct {
   double rho;          /* penalty; <= 0 selects 2 * mean_s mean_j (A_s^T c_s W A_s)_jj */
   double eps_abs;      /* stopping tolerances of Sec. 2.2; default 1e-6 (Sec. 2.3) */
@@ -114,6 +116,15 @@ typedef struct {
   int32_t pass_threads; /* fused-pass workgroup size 256 or 512; 0 = chosen by the set-up autotuner */
   int32_t pass_unroll;  /* 1: row data loaded when the row starts; 2: next row's data in flight during the
                            current row (software pipelined); 0 = chosen by the autotuner */
+  int32_t xupdate;     /* x-update of every scenario subproblem:
+                          ADMM_XUPDATE_CG: warm-started CG steps with the sparse A_s (cg_max, cg_eta);
+                          ADMM_XUPDATE_DENSE: exact solve with a cached inverse of
+                            A_s^T c_s W A_s + rho/2 I (fp64 Gram matrix and block Gauss-Jordan sweep at
+                            set-up and on every change of rho, fp32 inverse, one GEMV per iteration;
+                            the cached-factor solver of Appendix A); needs n <= 8128 and
+                            about 20 N n^2 bytes of device memory per patient;
+                          ADMM_XUPDATE_AUTO (default): DENSE when every patient has n <= 8128 and the
+                            matrices take at most a quarter of the free device memory, else CG */
   void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
 } admm_options;
 
@@ -149,6 +160,11 @@ admm_status admm_setup(const admm_problem* prob, const admm_options* opts, admm_
  * of them (one launch per phase per iteration). */
 admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, const admm_options* opts,
                              admm_ctx** out);
+
+/* The x-update the context uses (ADMM_XUPDATE_CG or ADMM_XUPDATE_DENSE) and, for
+ * DENSE, the device time in ms of the last set-up of the cached inverses
+ * (Gram matrices and sweeps of all patients). */
+admm_status admm_get_xupdate(const admm_ctx* ctx, int32_t* mode, double* setup_ms);
 
 /* Restart one patient from z = P(z0) (z0 NULL: 0), iteration 0.
  * rho > 0 replaces the penalty of that patient (rho <= 0 keeps it).
@@ -227,7 +243,12 @@ admm_status admm_get_z(admm_ctx* ctx, int32_t patient, double* z);
 
 /* Checkpoint / resume.  The state that determines the next iterations is
  * z (n), y (N*n, scenario-major), d = x - z of the last iteration (N*n) and
- * 8 scalars {iter, tau, f_prev, pending, stopped, status, rho, cg_total}. */
+ * ADMM_STATE_SCALARS scalars {iter, tau, f_prev, pending, stopped, status, rho,
+ * cg_total, f_cur, r_prim, r_dual, eps_prim, eps_dual, ||x||, ||z||, cg_steps}.
+ * Resuming from a saved state in the same or a fresh context with the same
+ * problem and options reproduces the following iterations bit for bit when the
+ * column sums are exact (lds_acc = 2 or the dense x-update). */
+#define ADMM_STATE_SCALARS 16
 admm_status admm_get_state(admm_ctx* ctx, int32_t patient, double* z, double* y, double* d, double* scalars);
 admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, const double* y, const double* d,
                            const double* scalars);

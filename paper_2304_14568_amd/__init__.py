@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libadmmbb.so")
 OK, MAX_ITER = 0, 1
 E_ARG, E_CSR, E_NEGATIVE, E_NONFINITE, E_OOM, E_HIP, E_DIVERGED, E_STATE = -1, -2, -3, -4, -5, -6, -7, -8
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
+XUPDATE = {"auto": -1, "cg": 0, "dense": 1}
 
 # every symbol include/admmbb.h declares
 EXPORTS = [
@@ -26,7 +27,7 @@ EXPORTS = [
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
     "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
-    "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats",
+    "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
     "mlp_loss_grad", "mlp_adam_step", "mlp_last_error",
 ]
@@ -58,7 +59,7 @@ class OptionsC(ctypes.Structure):
                 ("cg_eta", ctypes.c_double), ("cg_eta_floor", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("lds_acc", ctypes.c_int32), ("tile_nnz", ctypes.c_int32), ("pass_threads", ctypes.c_int32),
-                ("pass_unroll", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("pass_unroll", ctypes.c_int32), ("xupdate", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class InfoC(ctypes.Structure):
@@ -91,6 +92,7 @@ def _load():
         "admm_warm_start": [P, i32, P, dbl, i32],
         "admm_spot_features": [P, i32, P, P],
         "admm_dose_stats": [P, i32, P, P, i32, i32, dbl, P, P, P, P],
+        "admm_get_xupdate": [P, P, P],
         "mlp_create": [i32, i32, ctypes.c_uint64, P, ctypes.POINTER(P)],
         "mlp_get_params": [P, P],
         "mlp_set_params": [P, P],
@@ -182,6 +184,8 @@ def default_options(**kw) -> OptionsC:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = PREC[v]
+        if k == "xupdate" and isinstance(v, str):
+            v = XUPDATE[v]
         if k == "stream" and v is not None and not isinstance(v, int):
             v = int(getattr(v, "cuda_stream", v))  # torch.cuda.Stream -> hipStream_t
         if not hasattr(o, k):
@@ -349,7 +353,7 @@ class Solver:
         z = np.zeros(n)
         y = np.zeros(N * n)
         d = np.zeros(N * n)
-        sc = np.zeros(8)
+        sc = np.zeros(16)
         _check(self.ctx, lib.admm_get_state(self.ctx, patient, z.ctypes.data, y.ctypes.data, d.ctypes.data,
                                             sc.ctypes.data))
         return dict(z=z, y=y, d=d, scalars=sc)
@@ -382,6 +386,12 @@ class Solver:
         _check(self.ctx, lib.admm_get_sizes(self.ctx, patient, ctypes.byref(n), ctypes.byref(m), ctypes.byref(N),
                                             ctypes.byref(nnz)))
         return dict(n=n.value, m=m.value, num_scen=N.value, nnz=nnz.value)
+
+    def xupdate(self):
+        """('cg' or 'dense', device ms of the last cached-inverse set-up)."""
+        mode, ms = ctypes.c_int32(), ctypes.c_double()
+        _check(self.ctx, lib.admm_get_xupdate(self.ctx, ctypes.byref(mode), ctypes.byref(ms)))
+        return ("dense" if mode.value == 1 else "cg"), ms.value
 
     def enable_timing(self, on: bool = True):
         _check(self.ctx, lib.admm_enable_timing(self.ctx, 1 if on else 0))

@@ -28,8 +28,14 @@ def _dv_from_hist(counts_desc_cum, K, v, w):
     return (k + 0.5) * w
 
 
-def evaluate(S, P, x, patient: int = 0, nbins: int = 4096, dmax=None) -> dict:
+def max_bins(num_groups: int) -> int:
+    """Largest histogram the GPU kernel holds in LDS for this many groups (12 G + 4 G nbins <= 64 KiB)."""
+    return (65536 - 12 * num_groups) // (4 * num_groups)
+
+
+def evaluate(S, P, x, patient: int = 0, nbins=None, dmax=None) -> dict:
     G = int(len(P.struct_weight))
+    nbins = min(4096, max_bins(G)) if nbins is None else int(nbins)
     presc = np.asarray(P.presc, dtype=np.float64)
     dmax = float(dmax) if dmax else 2.0 * max(1e-12, presc.max())
     counts, sums, maxes, _ = S.dose_stats(x, P.struct_id, G, nbins, dmax, patient)

@@ -74,6 +74,16 @@ struct admm_ctx {
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   double total_ms = 0.0, pass_ms_sum = 0.0;
   int64_t pass_count = 0;
+  // dense x-update (cached inverses)
+  bool dense = false;
+  double *d_G = nullptr, *d_Aw = nullptr, *d_Gsum = nullptr, *d_g0 = nullptr;
+  double *d_Pb = nullptr, *d_U = nullptr, *d_R = nullptr, *d_fpart = nullptr;
+  float* d_M = nullptr;
+  double* d_rw64 = nullptr;
+  XJob *d_xjobs = nullptr, *d_fjobs = nullptr;
+  int n_xjobs = 0, n_fjobs = 0, ld_max = 0;
+  std::vector<double> factored_rho;  // per patient: penalty of the cached inverse
+  double factor_ms = 0.0;            // time of the last set-up of the cached inverses
 
   template <class T>
   T* alloc(size_t count) {
@@ -162,12 +172,62 @@ struct admm_ctx {
     a.prm.precond = opts.precond;
     a.prm.trace_cap = trace_cap;
     a.prm.num_pat = P;
+    a.fpart = dense ? d_fpart : nullptr;
     return a;
+  }
+
+  FactorArgs fargs() const {
+    FactorArgs f{};
+    f.scen = d_scen;
+    f.pat = d_pat;
+    f.ps = d_ps;
+    f.G = d_G;
+    f.A = d_Aw;
+    f.M = d_M;
+    f.Gsum = d_Gsum;
+    f.g0 = d_g0;
+    f.P = d_Pb;
+    f.U = d_U;
+    f.R = d_R;
+    f.xjobs = d_xjobs;
+    f.fjobs = d_fjobs;
+    f.fpart = d_fpart;
+    f.npmax = ld_max;
+    return f;
+  }
+
+  // (Re)build the cached inverses of patient p at its current penalty: the
+  // Gram matrices (when form_gram), then B_s = G_s + rho/2 I swept in place.
+  void factorize(int p, bool form_gram) {
+    const Pat& pt = H.pat[p];
+    const int npad = pt.npad;
+    const int64_t nn = static_cast<int64_t>(npad) * npad;
+    const Scen& s0 = H.scen[pt.scen_begin];
+    FactorArgs f = fargs();
+    if (form_gram) {
+      launch_fill_f64(d_G + s0.fmat_off, 0.0, nn * pt.num_scen, stream);
+      for (int s = 0; s < pt.num_scen; ++s) {
+        const Scen& sc = H.scen[pt.scen_begin + s];
+        launch_gram(mat32, d_rw64, sc, d_G + sc.fmat_off, npad, stream);
+      }
+    }
+    launch_gram_finish(f, p, pt.num_scen, npad, pt.n, rho[p], stream);
+    for (int k0 = 0; k0 < npad; k0 += 64) launch_sweep_step(f, pt.scen_begin, pt.num_scen, npad, k0, stream);
+    launch_sweep_store(f, pt.scen_begin, pt.num_scen, npad, stream);
+    check(hipGetLastError(), "factor launch");
+    factored_rho[p] = rho[p];
   }
 
   // head: gradient pass at z (objective + residual of the x-update system at x = z),
   // completion of the previous iteration, CG set-up
   void launch_head(int stop_enabled, int cg_setup) {
+    if (dense) {
+      VecArgs va = vec_args(stop_enabled);
+      launch_fhead(va, NB, stream);
+      launch_fobj(fargs(), d_z, n_fjobs, ld_max, stream);
+      launch_head_scalars(va, G, 0, stream);
+      return;
+    }
     PassArgs pa = pass_args(mat32);
     pa.src = d_z;
     pa.src_per_scen = 0;
@@ -181,6 +241,15 @@ struct admm_ctx {
   void launch_body(int stop_enabled, bool with_events) {
     const MatDev& m = (opts.precision == ADMM_PREC_FP32) ? mat32 : matlp;
     VecArgs va = vec_args(stop_enabled);
+    if (dense) {
+      if (with_events)
+        launch_xgemv(fargs(), d_r, d_x, n_xjobs, ld_max, stream, ev[0], ev[1]);
+      else
+        launch_xgemv(fargs(), d_r, d_x, n_xjobs, ld_max, stream);
+      launch_zres(va, NPB, stream);
+      launch_body_scalars(va, stream);
+      return;
+    }
     for (int k = 0; k < opts.cg_max; ++k) {
       PassArgs pa = pass_args(m);
       pa.src = d_v;
@@ -233,7 +302,8 @@ struct admm_ctx {
 
   void accumulate_pass_times() {
     if (!timing) return;
-    for (int k = 0; k < opts.cg_max; ++k) {
+    const int nev = dense ? 1 : opts.cg_max;
+    for (int k = 0; k < nev; ++k) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess) {
         pass_ms_sum += ms;
@@ -359,6 +429,7 @@ struct admm_ctx {
     launch_fill_f64(d_dprev + s0.vec_base, 0.0, len, stream);
     check(hipMemsetAsync(d_cgtotal + pt.scen_begin, 0, sizeof(int64_t) * pt.num_scen, stream), "memset");
     if (new_rho > 0) rho[p] = new_rho;
+    if (dense && factored_rho[p] != rho[p]) factorize(p, false);
     PatState st{};
     st.rho = rho[p];
     st.tau = rho[p];
@@ -406,7 +477,11 @@ admm_status from_hip(admm_ctx* c, const HipError& e) {
   return set_err(c, e.code == hipErrorOutOfMemory ? ADMM_E_OOM : ADMM_E_HIP, m);
 }
 
-#define GUARD_BEGIN try {
+// every entry reports only its own HIP errors: a stale last-error left by an
+// earlier call of the thread is cleared first
+#define GUARD_BEGIN      \
+  (void)hipGetLastError(); \
+  try {
 #define GUARD_END(ctx)                                              \
   }                                                                 \
   catch (const HipError& e) {                                       \
@@ -451,6 +526,7 @@ admm_status admm_default_options(admm_options* o) {
   o->tile_nnz = 0;
   o->pass_threads = 0;
   o->pass_unroll = 0;
+  o->xupdate = ADMM_XUPDATE_CG;
   o->stream = nullptr;
   return ADMM_OK;
 }
@@ -505,6 +581,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
   if (st != ADMM_OK) return set_err(nullptr, st, msg);
   try {
     int ndev = 0;
+    (void)hipGetLastError();  // report only this call's errors
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
       return set_err(nullptr, ADMM_E_HIP, "no HIP device available");
     Packed& H = c->H;
@@ -524,6 +601,65 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     for (int p = 0; p < num_patients; ++p) c->rho[p] = o.rho > 0 ? o.rho : 2.0 * H.gdiag_mean[p];
     c->trace_cap = std::max(1, o.max_iter + 2);
 
+    // dense x-update: sizes, offsets and work lists (before the tables go to the device)
+    std::vector<XJob> xjobs, fjobs;
+    {
+      int64_t need = 0;
+      bool fits_n = true;
+      for (const Pat& pt : H.pat) {
+        const int64_t npad = (pt.n + 63) / 64 * 64;
+        fits_n = fits_n && pt.n <= 8128;
+        need += npad * npad * (20 * static_cast<int64_t>(pt.num_scen) + 8) + 2 * 8 * 64 * npad * pt.num_scen;
+      }
+      size_t free_b = 0, total_b = 0;
+      check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+      if (o.xupdate == ADMM_XUPDATE_DENSE) {
+        if (!fits_n) return set_err(nullptr, ADMM_E_ARG, "dense x-update needs n <= 8128 for every patient");
+        if (static_cast<size_t>(need) > free_b)
+          return set_err(nullptr, ADMM_E_OOM, "dense x-update matrices do not fit in device memory");
+        c->dense = true;
+      } else if (o.xupdate == ADMM_XUPDATE_AUTO) {
+        c->dense = fits_n && static_cast<size_t>(need) <= free_b / 4;
+      }
+    }
+    if (c->dense) {
+      int64_t off = 0, goff = 0;
+      for (int p = 0; p < num_patients; ++p) {
+        Pat& pt = H.pat[p];
+        pt.npad = (pt.n + 63) / 64 * 64;
+        c->ld_max = std::max(c->ld_max, pt.npad);
+        const int64_t nn = static_cast<int64_t>(pt.npad) * pt.npad;
+        pt.gsum_off = goff;
+        goff += nn;
+        pt.fobj_begin = static_cast<int32_t>(fjobs.size());
+        for (int r = 0; r < pt.n; r += kXRows) fjobs.push_back(XJob{p, r});
+        pt.fobj_end = static_cast<int32_t>(fjobs.size());
+        for (int s = 0; s < pt.num_scen; ++s) {
+          Scen& sc = H.scen[pt.scen_begin + s];
+          sc.fmat_off = off;
+          off += nn;
+          for (int r = 0; r < pt.n; r += kXRows) xjobs.push_back(XJob{pt.scen_begin + s, r});
+        }
+      }
+      c->n_xjobs = static_cast<int>(xjobs.size());
+      c->n_fjobs = static_cast<int>(fjobs.size());
+      c->d_G = c->alloc<double>(static_cast<size_t>(off));
+      c->d_Aw = c->alloc<double>(static_cast<size_t>(off));
+      c->d_M = c->alloc<float>(static_cast<size_t>(off));
+      c->d_Gsum = c->alloc<double>(static_cast<size_t>(goff));
+      c->d_Pb = c->alloc<double>(static_cast<size_t>(c->G) * 64 * 64);
+      c->d_U = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
+      c->d_R = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
+      c->d_fpart = c->alloc<double>(fjobs.size());
+      c->d_xjobs = c->upload(xjobs);
+      c->d_fjobs = c->upload(fjobs);
+      std::vector<double> g0all(static_cast<size_t>(H.zvec_total));
+      for (int p = 0; p < num_patients; ++p)
+        std::copy(H.g0[p].begin(), H.g0[p].end(), g0all.begin() + H.pat[p].zvec_base);
+      c->d_g0 = c->upload(g0all);
+      c->d_rw64 = c->upload(H.rw64);
+      c->factored_rho.assign(num_patients, 0.0);
+    }
     c->d_scen = c->upload(H.scen);
     c->d_pat = c->upload(H.pat);
     c->d_tiles = c->upload(H.tiles);
@@ -546,6 +682,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     std::vector<uint16_t>().swap(H.col16);
     std::vector<int32_t>().swap(H.col32);
     std::vector<uint32_t>().swap(H.rp);
+    std::vector<double>().swap(H.rw64);
 
     const size_t V = static_cast<size_t>(H.vec_total);
     c->d_x = c->alloc<float>(V);
@@ -585,6 +722,22 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     launch_fill_f32(c->d_r, 0.0f, V, c->stream);
     launch_fill_u8(c->d_act, 0, static_cast<int64_t>(c->G) * kRing, c->stream);
     launch_fill_f64(c->d_rz, 0.0, static_cast<int64_t>(c->G) * kRing, c->stream);
+    check(hipMemsetAsync(c->d_cgcount, 0, sizeof(int32_t) * c->G, c->stream), "memset");
+    check(hipMemsetAsync(c->d_cgtotal, 0, sizeof(int64_t) * c->G, c->stream), "memset");
+    if (c->dense) {
+      hipEvent_t f0, f1;
+      check(hipEventCreate(&f0), "hipEventCreate");
+      check(hipEventCreate(&f1), "hipEventCreate");
+      check(hipEventRecord(f0, c->stream), "hipEventRecord");
+      for (int p = 0; p < num_patients; ++p) c->factorize(p, true);
+      check(hipEventRecord(f1, c->stream), "hipEventRecord");
+      check(hipEventSynchronize(f1), "hipEventSynchronize");
+      float ms = 0.0f;
+      check(hipEventElapsedTime(&ms, f0, f1), "hipEventElapsedTime");
+      c->factor_ms = ms;
+      (void)hipEventDestroy(f0);
+      (void)hipEventDestroy(f1);
+    }
     for (int p = 0; p < num_patients; ++p) c->reset_patient(p, nullptr, 0.0);
     if (o.pass_threads) c->pass_threads = o.pass_threads;
     if (o.pass_unroll) c->pass_unroll = o.pass_unroll;
@@ -632,6 +785,13 @@ admm_status admm_get_timing(const admm_ctx* ctx, double* total_ms, double* pass_
   if (total_ms) *total_ms = ctx->total_ms;
   if (pass_ms) *pass_ms = ctx->pass_count ? ctx->pass_ms_sum / ctx->pass_count : 0.0;
   if (pass_launches) *pass_launches = static_cast<int32_t>(ctx->pass_count);
+  return ADMM_OK;
+}
+
+admm_status admm_get_xupdate(const admm_ctx* ctx, int32_t* mode, double* setup_ms) {
+  if (!ctx) return ADMM_E_ARG;
+  if (mode) *mode = ctx->dense ? ADMM_XUPDATE_DENSE : ADMM_XUPDATE_CG;
+  if (setup_ms) *setup_ms = ctx->factor_ms;
   return ADMM_OK;
 }
 
@@ -1163,6 +1323,14 @@ admm_status admm_get_state(admm_ctx* ctx, int32_t patient, double* z, double* y,
     scalars[5] = s.status;
     scalars[6] = s.rho;
     scalars[7] = s.cg_total;
+    scalars[8] = s.f_cur;
+    scalars[9] = s.r_prim;
+    scalars[10] = s.r_dual;
+    scalars[11] = s.eps_prim;
+    scalars[12] = s.eps_dual;
+    scalars[13] = s.xnorm;
+    scalars[14] = s.znorm;
+    scalars[15] = s.cg_steps;
   }
   return ADMM_OK;
   GUARD_END(ctx)
@@ -1189,6 +1357,7 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
   check(hipMemcpy(ctx->d_y + base, yf.data(), sizeof(float) * len, hipMemcpyHostToDevice), "H2D");
   check(hipMemcpy(ctx->d_dprev + base, d, sizeof(double) * len, hipMemcpyHostToDevice), "H2D");
   if (scalars[6] > 0) ctx->rho[patient] = scalars[6];
+  if (ctx->dense && ctx->factored_rho[patient] != ctx->rho[patient]) ctx->factorize(patient, false);
   PatState s{};
   s.iter = static_cast<int32_t>(scalars[0]);
   s.tau = scalars[1];
@@ -1198,6 +1367,14 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
   s.status = static_cast<int32_t>(scalars[5]);
   s.rho = ctx->rho[patient];
   s.cg_total = static_cast<int32_t>(scalars[7]);
+  s.f_cur = scalars[8];
+  s.r_prim = scalars[9];
+  s.r_dual = scalars[10];
+  s.eps_prim = scalars[11];
+  s.eps_dual = scalars[12];
+  s.xnorm = scalars[13];
+  s.znorm = scalars[14];
+  s.cg_steps = static_cast<int32_t>(scalars[15]);
   ctx->h_ps[patient] = s;
   check(hipMemcpy(ctx->d_ps + patient, &s, sizeof(PatState), hipMemcpyHostToDevice), "H2D");
   return ADMM_OK;

@@ -1,0 +1,419 @@
+// Dense x-update: the exact solve of every scenario subproblem through a
+// cached inverse of its system matrix (Appendix A factors B_s = A_s^T W~_s A_s
+// + rho/2 I once and reuses the factor in every iteration; here the factor is
+// the inverse itself, so that each x-update is one bandwidth-bound GEMV).
+//
+//  1. k_gram: G_s = A_s^T diag(c_s w) A_s, upper triangle, fp64 atomics (one
+//     wave per stored row: every pair j <= k of its nonzeros).
+//  2. k_gram_finish: mirror to the lower triangle, sum_s G_s, and the sweep
+//     work matrix A = G_s + rho/2 I (identity on the padding to npad).
+//  3. block sweep (Gauss-Jordan on 64-blocks, no pivoting: the pivot blocks
+//     are Schur complements of an SPD matrix): for each block K,
+//        P = A_KK^-1, U = A_:K P, R = A_K: (old),
+//        A_ij -= U_i R_j off the block row and column,
+//        A_:K = U, A_K: = U^T, A_KK = -P;
+//     after the last block A = -B_s^-1.  k_sweep_store writes M_s = B_s^-1 in fp32.
+//  4. every iteration: k_fhead (pending dual update, right-hand side c_s),
+//     k_fobj (objective at z from the quadratic form), k_xgemv (x_s = M_s c_s).
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace admmbb {
+
+namespace {
+
+constexpr int kFb = 64;  // sweep block size
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrix
+// ---------------------------------------------------------------------------
+
+template <bool C16>
+__global__ __launch_bounds__(256) void k_gram(MatDev mat, const double* __restrict__ rw64, Scen sc,
+                                              double* __restrict__ G, int ld) {
+  const int row = static_cast<int>(blockIdx.x) * 4 + static_cast<int>(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= sc.rows) return;
+  const uint32_t c0 = mat.rp[sc.rp_base + row], c1 = mat.rp[sc.rp_base + row + 1];
+  const int64_t e0 = sc.nnz_base + 4 * static_cast<int64_t>(c0);
+  const int k = 4 * static_cast<int>(c1 - c0);
+  const double rw = rw64[sc.row_base + row];
+  const float* val = static_cast<const float*>(mat.val);
+  auto colat = [&](int64_t e) -> int {
+    if constexpr (C16)
+      return static_cast<const uint16_t*>(mat.col)[e];
+    else
+      return static_cast<const int32_t*>(mat.col)[e];
+  };
+  for (int base = 0; base < k; base += 64) {
+    const int kk = base + lane;
+    const bool valid = kk < k;
+    const int ck = valid ? colat(e0 + kk) : 0;
+    const double vk = valid ? rw * static_cast<double>(val[e0 + kk]) : 0.0;
+    const int jend = base + 64 < k ? base + 64 : k;
+    for (int jj = 0; jj < jend; ++jj) {
+      const float vj = val[e0 + jj];
+      if (vj == 0.0f) continue;  // chunk padding
+      const int cj = colat(e0 + jj);
+      // columns increase along a stored row, so jj <= kk gives cj <= ck
+      if (valid && jj <= kk && vk != 0.0)
+        unsafeAtomicAdd(&G[static_cast<int64_t>(cj) * ld + ck], vk * static_cast<double>(vj));
+    }
+  }
+}
+
+// mirror the upper triangle, add sum_s G_s, build A = G + rho/2 I (identity on the padding)
+__global__ __launch_bounds__(256) void k_gram_finish(FactorArgs f, int patient, int nscen, int npad, int n,
+                                                     double rho) {
+  const Pat pt = f.pat[patient];
+  const int64_t nn = static_cast<int64_t>(npad) * npad;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nn; idx += stride) {
+    const int i = static_cast<int>(idx / npad), j = static_cast<int>(idx % npad);
+    double sum = 0.0;
+    for (int s = 0; s < nscen; ++s) {
+      const Scen sc = f.scen[pt.scen_begin + s];
+      double* G = f.G + sc.fmat_off;
+      const double gv = (i <= j) ? G[idx] : G[static_cast<int64_t>(j) * npad + i];
+      if (i > j) G[idx] = gv;  // lower triangle written only here, upper only read
+      sum += gv;
+      double a = gv;
+      if (i == j) a += (i < n) ? 0.5 * rho : 1.0;
+      f.A[sc.fmat_off + idx] = a;
+    }
+    f.Gsum[pt.gsum_off + idx] = sum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block sweep
+// ---------------------------------------------------------------------------
+
+// P = A_KK^-1 by the scalar sweep in LDS (one workgroup per scenario)
+__global__ __launch_bounds__(256) void k_sweep_pivot(FactorArgs f, int scen_begin, int npad, int k0) {
+  __shared__ double a[kFb][kFb + 1];
+  const int g = scen_begin + static_cast<int>(blockIdx.x);
+  const Scen sc = f.scen[g];
+  const double* A = f.A + sc.fmat_off;
+  for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
+    const int i = e / kFb, j = e % kFb;
+    a[i][j] = A[static_cast<int64_t>(k0 + i) * npad + k0 + j];
+  }
+  __syncthreads();
+  double nv[16];
+  for (int t = 0; t < kFb; ++t) {
+    const double d = a[t][t];
+    const double inv = 1.0 / d;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + q * 256;
+      const int i = e / kFb, j = e % kFb;
+      double v;
+      if (i == t && j == t)
+        v = -inv;
+      else if (i == t)
+        v = a[t][j] * inv;
+      else if (j == t)
+        v = a[i][t] * inv;
+      else
+        v = a[i][j] - a[i][t] * a[t][j] * inv;
+      nv[q] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + q * 256;
+      a[e / kFb][e % kFb] = nv[q];
+    }
+    __syncthreads();
+  }
+  // the swept block is -A_KK^-1
+  double* P = f.P + static_cast<int64_t>(g) * kFb * kFb;
+  for (int e = threadIdx.x; e < kFb * kFb; e += 256) P[e] = -a[e / kFb][e % kFb];
+}
+
+// U_I = A_IK P (64 x 64 per workgroup) and R tile = A_K,I (old row panel copy)
+__global__ __launch_bounds__(256) void k_sweep_panel(FactorArgs f, int scen_begin, int npad, int k0) {
+  __shared__ double at[kFb][kFb];  // A_IK
+  __shared__ double p[kFb][kFb];   // P
+  const int g = scen_begin + static_cast<int>(blockIdx.y);
+  const Scen sc = f.scen[g];
+  const double* A = f.A + sc.fmat_off;
+  const int i0 = static_cast<int>(blockIdx.x) * kFb;
+  const double* Pg = f.P + static_cast<int64_t>(g) * kFb * kFb;
+  double* Ut = f.U + static_cast<int64_t>(g) * f.npmax * kFb;
+  double* R = f.R + static_cast<int64_t>(g) * f.npmax * kFb;
+  for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
+    const int i = e / kFb, j = e % kFb;
+    at[i][j] = A[static_cast<int64_t>(i0 + i) * npad + k0 + j];
+    p[i][j] = Pg[e];
+    // row panel: R[t][i0 + j] = A[k0 + t][i0 + j]
+    R[static_cast<int64_t>(i) * npad + i0 + j] = A[static_cast<int64_t>(k0 + i) * npad + i0 + j];
+  }
+  __syncthreads();
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;  // 4 x 4 outputs each
+  double acc[4][4] = {};
+  for (int t = 0; t < kFb; ++t) {
+    double av[4], pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      av[q] = at[4 * ti + q][t];
+      pv[q] = p[t][4 * tj + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[q][r] = fma(av[q], pv[r], acc[q][r]);
+  }
+  // stored transposed: Ut[c][i] = U[i][c]
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ut[static_cast<int64_t>(4 * tj + r) * npad + i0 + 4 * ti + q] = acc[q][r];
+}
+
+// rank-64 update of every tile off the pivot row and column; panel tiles replaced
+__global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_begin, int npad, int k0) {
+  __shared__ double ut[kFb][kFb];  // ut[t][i] = U[i0 + i][t]
+  __shared__ double rs[kFb][kFb];  // rs[t][j] = R[t][j0 + j]
+  const int nbk = npad / kFb;
+  const int bi = static_cast<int>(blockIdx.x) / nbk, bj = static_cast<int>(blockIdx.x) % nbk;
+  const int g = scen_begin + static_cast<int>(blockIdx.y);
+  const Scen sc = f.scen[g];
+  double* A = f.A + sc.fmat_off;
+  const int i0 = bi * kFb, j0 = bj * kFb, kb = k0 / kFb;
+  const double* Ut = f.U + static_cast<int64_t>(g) * f.npmax * kFb;
+  const double* R = f.R + static_cast<int64_t>(g) * f.npmax * kFb;
+  if (bi == kb || bj == kb) {
+    const double* Pg = f.P + static_cast<int64_t>(g) * kFb * kFb;
+    for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
+      const int i = e / kFb, j = e % kFb;
+      double v;
+      if (bi == kb && bj == kb)
+        v = -Pg[e];
+      else if (bj == kb)
+        v = Ut[static_cast<int64_t>(j) * npad + i0 + i];  // U[i0 + i][j]
+      else
+        v = Ut[static_cast<int64_t>(i) * npad + j0 + j];  // U[j0 + j][i]
+      A[static_cast<int64_t>(i0 + i) * npad + j0 + j] = v;
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
+    const int t = e / kFb, c = e % kFb;
+    ut[t][c] = Ut[static_cast<int64_t>(t) * npad + i0 + c];
+    rs[t][c] = R[static_cast<int64_t>(t) * npad + j0 + c];
+  }
+  __syncthreads();
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  double acc[4][4] = {};
+  for (int t = 0; t < kFb; ++t) {
+    double uv[4], rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uv[q] = ut[t][4 * ti + q];
+      rv[q] = rs[t][4 * tj + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[q][r] = fma(uv[q], rv[r], acc[q][r]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t o = static_cast<int64_t>(i0 + 4 * ti + q) * npad + j0 + 4 * tj + r;
+      A[o] -= acc[q][r];
+    }
+}
+
+// M = -A in fp32
+__global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int scen_begin, int npad) {
+  const int g = scen_begin + static_cast<int>(blockIdx.y);
+  const Scen sc = f.scen[g];
+  const int64_t nn = static_cast<int64_t>(npad) * npad;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nn; idx += stride)
+    f.M[sc.fmat_off + idx] = static_cast<float>(-f.A[sc.fmat_off + idx]);
+}
+
+// ---------------------------------------------------------------------------
+// per-iteration kernels
+// ---------------------------------------------------------------------------
+
+// x_s = M_s c_s for kXRows rows of one scenario; c_s staged in LDS
+__global__ __launch_bounds__(256) void k_xgemv(FactorArgs f, const float* __restrict__ c, float* __restrict__ x) {
+  extern __shared__ float cs[];
+  const XJob job = f.xjobs[blockIdx.x];
+  const Scen sc = f.scen[job.g];
+  if (f.ps[sc.patient].stopped) return;
+  const int ld = f.pat[sc.patient].npad;
+  const int n = sc.n;
+  for (int j = threadIdx.x; j < ld; j += 256) cs[j] = j < n ? c[sc.vec_base + j] : 0.0f;
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float* Mb = f.M + sc.fmat_off;
+  const float4* c4 = reinterpret_cast<const float4*>(cs);
+  const int n4 = ld / 4;
+  constexpr int kRowsPerWave = kXRows / 4;
+  float acc[kRowsPerWave];
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) acc[q] = 0.0f;
+  for (int k4 = lane; k4 < n4; k4 += 64) {
+    const float4 cv = c4[k4];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+      const int row = job.row0 + w * kRowsPerWave + q;
+      if (row < n) {
+        const float4 mv = reinterpret_cast<const float4*>(Mb + static_cast<int64_t>(row) * ld)[k4];
+        acc[q] = fmaf(mv.x, cv.x, acc[q]);
+        acc[q] = fmaf(mv.y, cv.y, acc[q]);
+        acc[q] = fmaf(mv.z, cv.z, acc[q]);
+        acc[q] = fmaf(mv.w, cv.w, acc[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    const float s = wave_sum_f(acc[q]);
+    const int row = job.row0 + w * kRowsPerWave + q;
+    if (lane == 0 && row < n) x[sc.vec_base + row] = s;
+  }
+}
+
+// completion of the pending dual update and the right-hand side
+// c_s = b_s + rho/2 z - y_s/2 (one scenario column block of 64 per workgroup)
+__global__ __launch_bounds__(kColBlock) void k_fhead(VecArgs a) {
+  const int bi = static_cast<int>(blockIdx.x);
+  const Blk bk = a.blk[bi];
+  const int g = bk.owner;
+  const Scen sc = a.scen[g];
+  const Pat pt = a.pat[sc.patient];
+  const PatState* ps = a.ps + sc.patient;
+  if (ps->stopped) return;
+  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  double yy = 0.0;
+  if (j < sc.n) {
+    const int64_t vi = sc.vec_base + j;
+    float yv = a.y[vi];
+    if (ps->pending) {
+      yv = static_cast<float>(static_cast<double>(yv) + ps->tau * a.dprev[vi]);
+      a.y[vi] = yv;
+    }
+    const float zj = a.z[pt.zvec_base + j];
+    a.r[vi] = static_cast<float>(static_cast<double>(a.b[vi]) + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv));
+    yy = static_cast<double>(yv) * yv;
+  }
+  yy = wave_sum_d(yy);
+  if (threadIdx.x == 0) {
+    double* bp = a.bpart + static_cast<int64_t>(bi) * 8;
+    bp[0] = 0.0;
+    bp[1] = 0.0;
+    bp[2] = yy;
+  }
+}
+
+// objective partial over kXRows rows: sum_r z_r ((Gsum z)_r - g0_r), fp64
+__global__ __launch_bounds__(256) void k_fobj(FactorArgs f, const float* __restrict__ z) {
+  extern __shared__ double zs[];
+  const XJob job = f.fjobs[blockIdx.x];
+  const Pat pt = f.pat[job.g];
+  if (f.ps[job.g].stopped) return;
+  const int ld = pt.npad, n = pt.n;
+  for (int j = threadIdx.x; j < ld; j += 256) zs[j] = j < n ? static_cast<double>(z[pt.zvec_base + j]) : 0.0;
+  __syncthreads();
+  __shared__ double red[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double* Gb = f.Gsum + pt.gsum_off;
+  constexpr int kRowsPerWave = kXRows / 4;
+  double part = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRowsPerWave; ++q) {
+    const int row = job.row0 + w * kRowsPerWave + q;
+    if (row >= n) continue;
+    double acc = 0.0;
+    const double2* gr = reinterpret_cast<const double2*>(Gb + static_cast<int64_t>(row) * ld);
+    const double2* z2 = reinterpret_cast<const double2*>(zs);
+    for (int k2 = lane; k2 < ld / 2; k2 += 64) {
+      const double2 gv = gr[k2], zv = z2[k2];
+      acc = fma(gv.x, zv.x, acc);
+      acc = fma(gv.y, zv.y, acc);
+    }
+    acc = wave_sum_d(acc);
+    part += zs[row] * (acc - f.g0[pt.zvec_base + row]);
+  }
+  if (lane == 0) red[w] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) f.fpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+}  // namespace
+
+void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G, int ld, hipStream_t st) {
+  if (sc.rows <= 0) return;
+  const unsigned nb = static_cast<unsigned>((sc.rows + 3) / 4);
+  if (m.col16)
+    hipLaunchKernelGGL(k_gram<true>, dim3(nb), dim3(256), 0, st, m, rw64, sc, G, ld);
+  else
+    hipLaunchKernelGGL(k_gram<false>, dim3(nb), dim3(256), 0, st, m, rw64, sc, G, ld);
+}
+
+void launch_gram_finish(FactorArgs f, int patient, int nscen, int npad, int n, double rho, hipStream_t st) {
+  int64_t nb = (static_cast<int64_t>(npad) * npad + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(k_gram_finish, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, f, patient, nscen, npad, n,
+                     rho);
+}
+
+void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st) {
+  const int nbk = npad / kFb;
+  hipLaunchKernelGGL(k_sweep_pivot, dim3(nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
+  hipLaunchKernelGGL(k_sweep_panel, dim3(nbk, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
+  hipLaunchKernelGGL(k_sweep_update, dim3(nbk * nbk, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
+}
+
+void launch_sweep_store(FactorArgs f, int scen_begin, int nscen, int npad, hipStream_t st) {
+  int64_t nb = (static_cast<int64_t>(npad) * npad + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_sweep_store, dim3(static_cast<unsigned>(nb), nscen), dim3(256), 0, st, f, scen_begin, npad);
+}
+
+void launch_xgemv(const FactorArgs& f, const float* c, float* x, int njobs, int ldmax, hipStream_t st, hipEvent_t e0,
+                  hipEvent_t e1) {
+  if (njobs <= 0) return;
+  const size_t smem = sizeof(float) * static_cast<size_t>(ldmax);
+  if (e0 != nullptr)
+    hipExtLaunchKernelGGL(k_xgemv, dim3(njobs), dim3(256), smem, st, e0, e1, 0, f, c, x);
+  else
+    hipLaunchKernelGGL(k_xgemv, dim3(njobs), dim3(256), smem, st, f, c, x);
+}
+
+void launch_fhead(const VecArgs& a, int nblk, hipStream_t st) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL(k_fhead, dim3(nblk), dim3(kColBlock), 0, st, a);
+}
+
+void launch_fobj(const FactorArgs& f, const float* z, int njobs, int ldmax, hipStream_t st) {
+  if (njobs <= 0) return;
+  const size_t smem = sizeof(double) * static_cast<size_t>(ldmax);
+  hipLaunchKernelGGL(k_fobj, dim3(njobs), dim3(256), smem, st, f, z);
+}
+
+}  // namespace admmbb

@@ -27,6 +27,7 @@ struct Packed {
   std::vector<uint16_t> val_lp;   // bf16 or fp16 bits
   std::vector<float> rscale;
   std::vector<float> rw, rpres;
+  std::vector<double> rw64;       // c_s w_i per sorted row in fp64 (Gram matrices of the dense x-update)
   std::vector<int32_t> rorig;
   std::vector<float> b;           // A_s^T c_s W p per scenario (stacked)
   std::vector<float> dinv;        // Jacobi inverse diagonal (stacked), filled when requested

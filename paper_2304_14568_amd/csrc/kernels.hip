@@ -410,8 +410,11 @@ static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStrea
   auto kern = k_pass<VK, C16, MODE, ACC, NT, PIPE>;
   static bool attr_done = false;
   if (!attr_done && smem > 65536) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              163840);
+    // a refusal here leaves the launch to report whether the size fits; do not
+    // leave the refusal behind as the thread's last error
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            163840) != hipSuccess)
+      (void)hipGetLastError();
     attr_done = true;
   }
   if (e0 != nullptr)
@@ -591,8 +594,12 @@ __global__ __launch_bounds__(kThreads) void k_head_scalars(VecArgs a, int nscen,
     const Pat pt = a.pat[p];
     PatState* ps = a.ps + p;
     if (ps->stopped) continue;  // uniform
-    const double f = pt.fzero + block_list_sum(pt.tile_end - pt.tile_begin,
-                                               [&](int i) { return a.objpart[pt.tile_begin + i]; }, sh);
+    const double f =
+        a.fpart != nullptr
+            ? pt.fconst + block_list_sum(pt.fobj_end - pt.fobj_begin,
+                                         [&](int i) { return a.fpart[pt.fobj_begin + i]; }, sh)
+            : pt.fzero + block_list_sum(pt.tile_end - pt.tile_begin,
+                                        [&](int i) { return a.objpart[pt.tile_begin + i]; }, sh);
     const int sb0 = a.scen[pt.scen_begin].blk_begin;
     const Scen last = a.scen[pt.scen_begin + pt.num_scen - 1];
     const int sb1 = last.blk_begin + last.nblk;

@@ -393,6 +393,7 @@ admm_status mlp_set_params(admm_mlp* n, const float* in) {
 
 admm_status mlp_forward(admm_mlp* n, const float* X, int32_t rows, int32_t precision, float* y_out,
                         float* log_rho_out) {
+  (void)hipGetLastError();  // report only this call's errors
   if (!n || !X || rows < 1 || (precision != ADMM_PREC_FP32 && precision != ADMM_PREC_BF16)) return ADMM_E_ARG;
   try {
     n->ensure(rows);
@@ -412,6 +413,7 @@ admm_status mlp_forward(admm_mlp* n, const float* X, int32_t rows, int32_t preci
 
 admm_status mlp_loss_grad(admm_mlp* n, const float* X, const float* target, int32_t rows, float target_log_rho,
                           float lam, double* loss_out, float* grad_out) {
+  (void)hipGetLastError();  // report only this call's errors
   if (!n || !X || !target || rows < 1 || !std::isfinite(target_log_rho) || !(lam >= 0)) return ADMM_E_ARG;
   try {
     const int B = rows, H = n->H, F = n->F;
@@ -446,6 +448,7 @@ admm_status mlp_loss_grad(admm_mlp* n, const float* X, const float* target, int3
 }
 
 admm_status mlp_adam_step(admm_mlp* n, float lr, float beta1, float beta2, float eps) {
+  (void)hipGetLastError();  // report only this call's errors
   if (!n || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0)) return ADMM_E_ARG;
   try {
     n->step += 1;

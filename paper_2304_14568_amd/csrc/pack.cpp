@@ -137,8 +137,11 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
           if (len > 0) order[static_cast<size_t>(cnt[static_cast<size_t>(maxlen - len)]++)] = i;
         }
         sc.rows = static_cast<int32_t>(rows);
-        for (int i = 0; i < m; ++i)
-          if (A.row_ptr[i + 1] == A.row_ptr[i]) pt.fzero += c * w[i] * pr.presc[i] * pr.presc[i];
+        for (int i = 0; i < m; ++i) {
+          const double wp2 = c * w[i] * pr.presc[i] * pr.presc[i];
+          pt.fconst += wp2;
+          if (A.row_ptr[i + 1] == A.row_ptr[i]) pt.fzero += wp2;
+        }
 
         // rows, values, per-row constants
         uint32_t off = 0;
@@ -186,6 +189,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
             if (lp) P.val_lp.push_back(0);
           }
           P.rw.push_back(static_cast<float>(cwi));
+          P.rw64.push_back(cwi);
           P.rpres.push_back(static_cast<float>(pr.presc[i]));
           P.rorig.push_back(i);
           off += static_cast<uint32_t>(len4 / 4);

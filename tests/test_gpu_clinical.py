@@ -51,7 +51,7 @@ def test_clinical_metrics_match_definitions(plan):
     from paper_2304_14568_amd import clinical
     P, W, xs = plan
     with A.Solver(P) as S:
-        ev = clinical.evaluate(S, P, xs, nbins=4096)
+        ev = clinical.evaluate(S, P, xs)
     Dref = oc.doses(W, xs)
     ref = oc.structure_metrics(Dref, P.struct_id, len(P.struct_weight))
     w = ev["bin_width"]
@@ -62,7 +62,7 @@ def test_clinical_metrics_match_definitions(plan):
         assert np.all(np.abs(got[ok] - r[ok]) <= tol * np.maximum(1.0, np.abs(r[ok]))), key
     # DVH at the bin edges: fraction of voxels with dose >= edge (allow voxels within
     # fp32 rounding of an edge to fall either side)
-    levels = ev["levels"][::64]
+    levels = ev["levels"][::32]
     for s in (0, P.num_scen - 1):
         for g in range(len(P.struct_weight)):
             sel = P.struct_id == g
@@ -70,5 +70,5 @@ def test_clinical_metrics_match_definitions(plan):
                 continue
             d = Dref[s, sel]
             near = np.array([np.count_nonzero(np.abs(d - L) <= 1e-6 * max(L, 1e-12)) for L in levels]) / d.size
-            assert np.all(np.abs(ev["dvh"][s, g, ::64] - oc.dvh(d, levels)) <= near + 1e-12)
+            assert np.all(np.abs(ev["dvh"][s, g, ::32] - oc.dvh(d, levels)) <= near + 1e-12)
     assert any(c["structure"].startswith("target") for c in ev["criteria"])

@@ -1,0 +1,114 @@
+"""The dense x-update (cached inverse of every A_s^T c_s W A_s + rho/2 I, the
+exact subproblem solve of Appendix A) against the FP64 oracle, whose ADMM-BB
+also solves every subproblem exactly (Cholesky): the iterates themselves must
+agree, not only the final objective."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import admm as oadmm, exact, wls
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_path(W, iters, rho=None, z0=None):
+    zs, fs = [], []
+    oadmm.admm_bb(W, rho=rho, max_iter=iters, obj_rel_tol=0.0, eps_abs=0.0, eps_rel=0.0, z0=z0, record=False,
+                  callback=lambda k, z, f: (zs.append(z.copy()), fs.append(f)))
+    return zs, fs
+
+
+@pytest.fixture(scope="module")
+def probs():
+    out = []
+    for P in (synth.make_tiny(2), synth.hn_small(6)):
+        W = wls.from_problem(P)
+        Hm, g0, _ = wls.quadratic_form(W)
+        xs, _ = exact.active_set(W, H=Hm, g0=g0)
+        out.append((P, W, xs, wls.objective(W, xs)))
+    return out
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_dense_iterates_follow_the_oracle(probs, which):
+    import paper_2304_14568_amd as A
+    P, W, xs, fs = probs[which]
+    K = 12
+    zr, fr = _oracle_path(W, K)
+    with A.Solver(P, xupdate="dense", max_iter=1000) as S:
+        assert S.xupdate()[0] == "dense"
+        assert abs(S.rho() - wls.default_rho(W)) <= 1e-6 * S.rho()
+        for k in (1, 2, 3, 6, K):
+            S.reset()
+            S.iterate(k)
+            z = S.z()
+            # fp32 inverse and fp32 iterates against fp64 Cholesky solves
+            err = np.linalg.norm(z - zr[k - 1]) / max(1e-30, np.linalg.norm(zr[k - 1]))
+            assert err <= 2e-4 * k, (k, err)
+        tr = S.trace()
+        for t in tr[:K]:
+            f_ref = fr[t["iter"] - 1]
+            assert abs(t["obj"] - f_ref) <= 1e-4 * f_ref
+        # the objective from the quadratic form (fp64 Gram matrix, fp64 p) equals the
+        # sparse-pass objective at the same z up to the fp32 rounding of p in the pass
+        assert abs(tr[K - 1]["obj"] - S.objective(S.z())) <= 1e-7 * tr[K - 1]["obj"]
+        assert abs(tr[K - 1]["obj"] - wls.objective(W, S.z())) <= 1e-9 * tr[K - 1]["obj"]
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_dense_solve_reaches_the_minimum(probs, which):
+    import paper_2304_14568_amd as A
+    P, W, xs, fs = probs[which]
+    with A.Solver(P, xupdate="dense", max_iter=3000) as S:
+        zs, info, st = S.solve()
+        assert st == 0, info
+        f = wls.objective(W, zs[0])
+        assert abs(f - fs) <= 1e-5 * fs, (f, fs)
+        assert info[0]["cg_steps"] == 0
+
+
+def test_dense_penalty_change_refactors(probs):
+    """A new rho rebuilds the cached inverses: the iterates then follow the
+    oracle run at that rho."""
+    import paper_2304_14568_amd as A
+    P, W, xs, fs = probs[1]
+    rho2 = 3.0 * wls.default_rho(W)
+    zr, _ = _oracle_path(W, 5, rho=rho2)
+    with A.Solver(P, xupdate="dense") as S:
+        S.iterate(4)
+        S.warm_start(0, None, rho2)
+        S.iterate(5)
+        z = S.z()
+        assert np.linalg.norm(z - zr[4]) / np.linalg.norm(zr[4]) <= 1e-3
+
+
+def test_dense_batch_and_cg_agree_on_the_minimum(probs):
+    import paper_2304_14568_amd as A
+    Ps = [probs[0][0], probs[1][0]]
+    with A.Solver(Ps, xupdate="dense", max_iter=3000) as S:
+        zs, infos, st = S.solve()
+    for (P, W, xs, fs), z in zip(probs, zs):
+        assert abs(wls.objective(W, z) - fs) <= 1e-5 * fs
+
+
+def test_auto_selects_dense_for_small_problems(probs):
+    import paper_2304_14568_amd as A
+    with A.Solver(probs[0][0], xupdate="auto") as S:
+        assert S.xupdate()[0] == "dense"
+    with A.Solver(probs[0][0], xupdate="cg") as S:
+        assert S.xupdate()[0] == "cg"
+
+
+def test_dense_checkpoint_resume_is_exact(probs):
+    import paper_2304_14568_amd as A
+    P = probs[1][0]
+    with A.Solver(P, xupdate="dense", use_graph=0) as S:
+        S.iterate(5)
+        saved = S.get_state()
+        S.iterate(6)
+        za = S.z()
+        S.set_state(saved)
+        S.iterate(6)
+        assert np.array_equal(S.z(), za)
