@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--cg-max", type=int, default=8)
+    ap.add_argument("--xupdate", default="auto", choices=["auto", "cg", "dense"],
+                    help="x-update: warm-started CG on the sparse A_s, or the cached dense inverse")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance measurement")
@@ -124,9 +126,10 @@ def main():
 
     t0 = time.perf_counter()
     S = A.Solver(P, precision=args.precision, cg_max=args.cg_max, max_iter=2000, stream=stream,
-                 use_graph=1 if args.graph else 0)
+                 use_graph=1 if args.graph else 0, xupdate=args.xupdate)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    xmode, factor_ms = S.xupdate()
 
     # warm-up: graph capture, caches, clocks
     S.iterate(max(1, args.warmup))
@@ -151,13 +154,31 @@ def main():
     counts = S.cg_counts()
     S.enable_timing(False)
 
-    # fused CG pass roofline: algorithmic bytes of the scenario passes actually
-    # performed / summed duration of all CG pass launches in the timed region
-    pb = pass_bytes(P, args.precision)
-    total_bytes = float(np.dot(counts, pb))
-    pass_time_s = tm["pass_ms"] * tm["pass_launches"] * 1e-3
-    achieved = total_bytes / pass_time_s / 1e9 if pass_time_s > 0 else 0.0
-    launches = tm["pass_launches"]
+    if xmode == "dense":
+        # x-update roofline (k_xsym): every launch reads each scenario's packed fp32
+        # inverse once (upper 64 x 64 tiles of M_s, 16 KiB each) and its right-hand side
+        nb = (P.n + 63) // 64
+        tiles = nb * (nb + 1) // 2
+        bytes_per_launch = float(P.num_scen * (tiles * 64 * 64 * 4 + 4 * P.n))
+        launches = tm["pass_launches"]
+        achieved = bytes_per_launch / (tm["pass_ms"] * 1e-3) / 1e9 if tm["pass_ms"] > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_xsym (x_s = M_s c_s over the packed upper tiles of the cached fp32 inverses)",
+                "avg_launch_ms": tm["pass_ms"], "launches": launches, "bytes_per_launch": bytes_per_launch}
+    else:
+        # fused CG pass roofline: algorithmic bytes of the scenario passes actually
+        # performed / summed duration of all CG pass launches in the timed region
+        pb = pass_bytes(P, args.precision)
+        total_bytes = float(np.dot(counts, pb))
+        pass_time_s = tm["pass_ms"] * tm["pass_launches"] * 1e-3
+        achieved = total_bytes / pass_time_s / 1e9 if pass_time_s > 0 else 0.0
+        launches = tm["pass_launches"]
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_pass (fused CG pass A_s^T diag(c_s w) A_s v)",
+                "avg_launch_ms": tm["pass_ms"], "launches": launches,
+                "bytes_per_full_pass": float(pb.sum()), "scenario_passes": int(counts.sum())}
 
     result = {
         "metric": METRIC,
@@ -175,17 +196,14 @@ def main():
         "config": {"workload": f"head-and-neck-shaped phantom seed {args.seed}: 120x120x80 grid at 2.5 mm, "
                                f"{P.m} body voxels, {P.n} spots (3 beams x 15 layers), 13 scenarios",
                    "m": P.m, "n": P.n, "scenarios": P.num_scen, "nnz": P.nnz, "precision": args.precision,
-                   "cg_max": args.cg_max, "parallelism": "single GPU, all scenarios per launch"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_pass (fused CG pass A_s^T diag(c_s w) A_s v)",
-                     "avg_launch_ms": tm["pass_ms"], "launches": launches,
-                     "bytes_per_full_pass": float(pb.sum()),
-                     "scenario_passes": int(counts.sum())},
+                   "cg_max": args.cg_max, "xupdate": xmode,
+                   "parallelism": "single GPU, all scenarios per launch"},
+        "roofline": roof,
         "instrumented_ms_per_step": 1e3 * t_inst / args.steps,
         "graph": bool(args.graph),
         "tuning": S.tuning(),
         "setup_s": t_setup,
+        "dense_factor_ms": factor_ms if xmode == "dense" else None,
         "generate_s": t_gen,
         "obj_after_steps": info[0]["obj"],
     }

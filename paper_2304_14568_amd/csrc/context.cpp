@@ -76,12 +76,12 @@ struct admm_ctx {
   int64_t pass_count = 0;
   // dense x-update (cached inverses)
   bool dense = false;
-  double *d_G = nullptr, *d_Aw = nullptr, *d_Gsum = nullptr, *d_g0 = nullptr;
+  double *d_G = nullptr, *d_Aw = nullptr, *d_Gp = nullptr, *d_g0 = nullptr;
   double *d_Pb = nullptr, *d_U = nullptr, *d_R = nullptr, *d_fpart = nullptr;
-  float* d_M = nullptr;
+  float *d_Mp = nullptr, *d_xpart = nullptr;
   double* d_rw64 = nullptr;
-  XJob *d_xjobs = nullptr, *d_fjobs = nullptr;
-  int n_xjobs = 0, n_fjobs = 0, ld_max = 0;
+  XJob *d_xjobs = nullptr, *d_rjobs = nullptr, *d_fjobs = nullptr;
+  int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
   std::vector<double> factored_rho;  // per patient: penalty of the cached inverse
   double factor_ms = 0.0;            // time of the last set-up of the cached inverses
 
@@ -183,13 +183,15 @@ struct admm_ctx {
     f.ps = d_ps;
     f.G = d_G;
     f.A = d_Aw;
-    f.M = d_M;
-    f.Gsum = d_Gsum;
+    f.Mp = d_Mp;
+    f.Gp = d_Gp;
     f.g0 = d_g0;
     f.P = d_Pb;
     f.U = d_U;
     f.R = d_R;
+    f.xpart = d_xpart;
     f.xjobs = d_xjobs;
+    f.rjobs = d_rjobs;
     f.fjobs = d_fjobs;
     f.fpart = d_fpart;
     f.npmax = ld_max;
@@ -213,7 +215,7 @@ struct admm_ctx {
     }
     launch_gram_finish(f, p, pt.num_scen, npad, pt.n, rho[p], stream);
     for (int k0 = 0; k0 < npad; k0 += 64) launch_sweep_step(f, pt.scen_begin, pt.num_scen, npad, k0, stream);
-    launch_sweep_store(f, pt.scen_begin, pt.num_scen, npad, stream);
+    launch_sweep_store(f, p, pt.num_scen, npad, stream);
     check(hipGetLastError(), "factor launch");
     factored_rho[p] = rho[p];
   }
@@ -224,7 +226,7 @@ struct admm_ctx {
     if (dense) {
       VecArgs va = vec_args(stop_enabled);
       launch_fhead(va, NB, stream);
-      launch_fobj(fargs(), d_z, n_fjobs, ld_max, stream);
+      launch_fobj(fargs(), d_z, n_fjobs, stream);
       launch_head_scalars(va, G, 0, stream);
       return;
     }
@@ -242,10 +244,12 @@ struct admm_ctx {
     const MatDev& m = (opts.precision == ADMM_PREC_FP32) ? mat32 : matlp;
     VecArgs va = vec_args(stop_enabled);
     if (dense) {
+      const FactorArgs f = fargs();
       if (with_events)
-        launch_xgemv(fargs(), d_r, d_x, n_xjobs, ld_max, stream, ev[0], ev[1]);
+        launch_xsym(f, d_r, n_xjobs, stream, ev[0], ev[1]);
       else
-        launch_xgemv(fargs(), d_r, d_x, n_xjobs, ld_max, stream);
+        launch_xsym(f, d_r, n_xjobs, stream);
+      launch_xsym_reduce(f, d_x, n_rjobs, stream);
       launch_zres(va, NPB, stream);
       launch_body_scalars(va, stream);
       return;
@@ -329,7 +333,9 @@ struct admm_ctx {
     for (int it = 0; it < k; ++it) {
       one_iteration(stop_enabled);
       const bool last = (it + 1 == k);
-      if (timing || last || ((it + 1) % every == 0)) {
+      // without the stopping test the device skips stopped patients by itself:
+      // the host only waits when it needs the flags or the pass timings
+      if (timing || last || (stop_enabled && (it + 1) % every == 0)) {
         read_state();
         accumulate_pass_times();
         bool all = true;
@@ -602,14 +608,18 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->trace_cap = std::max(1, o.max_iter + 2);
 
     // dense x-update: sizes, offsets and work lists (before the tables go to the device)
-    std::vector<XJob> xjobs, fjobs;
+    std::vector<XJob> xjobs, rjobs, fjobs;
     {
       int64_t need = 0;
       bool fits_n = true;
       for (const Pat& pt : H.pat) {
-        const int64_t npad = (pt.n + 63) / 64 * 64;
+        const int64_t npad = (pt.n + 63) / 64 * 64, nb = npad / 64, tiles = nb * (nb + 1) / 2;
         fits_n = fits_n && pt.n <= 8128;
-        need += npad * npad * (20 * static_cast<int64_t>(pt.num_scen) + 8) + 2 * 8 * 64 * npad * pt.num_scen;
+        // set-up: G and the sweep matrix (fp64, full); every iteration: packed fp32
+        // inverses, packed fp64 sum of G, tile partials; U, R panels
+        need += npad * npad * 16 * static_cast<int64_t>(pt.num_scen) +
+                tiles * 4096 * (4 * static_cast<int64_t>(pt.num_scen) + 8) + tiles * 512 * pt.num_scen +
+                2 * 8 * 64 * npad * pt.num_scen;
       }
       size_t free_b = 0, total_b = 0;
       check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
@@ -623,35 +633,46 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       }
     }
     if (c->dense) {
-      int64_t off = 0, goff = 0;
+      int64_t off = 0, moff = 0, goff = 0;
       for (int p = 0; p < num_patients; ++p) {
         Pat& pt = H.pat[p];
         pt.npad = (pt.n + 63) / 64 * 64;
+        pt.nbk = pt.npad / 64;
         c->ld_max = std::max(c->ld_max, pt.npad);
         const int64_t nn = static_cast<int64_t>(pt.npad) * pt.npad;
-        pt.gsum_off = goff;
-        goff += nn;
+        const int64_t tiles = static_cast<int64_t>(pt.nbk) * (pt.nbk + 1) / 2;
+        pt.gpack_off = goff;
+        goff += tiles * 4096;
         pt.fobj_begin = static_cast<int32_t>(fjobs.size());
-        for (int r = 0; r < pt.n; r += kXRows) fjobs.push_back(XJob{p, r});
+        for (int I = 0; I < pt.nbk; ++I)
+          for (int J = I; J < pt.nbk; ++J) fjobs.push_back(XJob{p, I * 65536 + J});
         pt.fobj_end = static_cast<int32_t>(fjobs.size());
         for (int s = 0; s < pt.num_scen; ++s) {
-          Scen& sc = H.scen[pt.scen_begin + s];
+          const int g = pt.scen_begin + s;
+          Scen& sc = H.scen[g];
           sc.fmat_off = off;
           off += nn;
-          for (int r = 0; r < pt.n; r += kXRows) xjobs.push_back(XJob{pt.scen_begin + s, r});
+          sc.mpack_off = moff;
+          moff += tiles * 4096;
+          for (int I = 0; I < pt.nbk; ++I)
+            for (int J = I; J < pt.nbk; ++J) xjobs.push_back(XJob{g, I * 65536 + J});
+          for (int I = 0; I < pt.nbk; ++I) rjobs.push_back(XJob{g, I});
         }
       }
       c->n_xjobs = static_cast<int>(xjobs.size());
+      c->n_rjobs = static_cast<int>(rjobs.size());
       c->n_fjobs = static_cast<int>(fjobs.size());
       c->d_G = c->alloc<double>(static_cast<size_t>(off));
       c->d_Aw = c->alloc<double>(static_cast<size_t>(off));
-      c->d_M = c->alloc<float>(static_cast<size_t>(off));
-      c->d_Gsum = c->alloc<double>(static_cast<size_t>(goff));
+      c->d_Mp = c->alloc<float>(static_cast<size_t>(moff));
+      c->d_xpart = c->alloc<float>(static_cast<size_t>(moff / 4096) * 128);
+      c->d_Gp = c->alloc<double>(static_cast<size_t>(goff));
       c->d_Pb = c->alloc<double>(static_cast<size_t>(c->G) * 64 * 64);
       c->d_U = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
       c->d_R = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
       c->d_fpart = c->alloc<double>(fjobs.size());
       c->d_xjobs = c->upload(xjobs);
+      c->d_rjobs = c->upload(rjobs);
       c->d_fjobs = c->upload(fjobs);
       std::vector<double> g0all(static_cast<size_t>(H.zvec_total));
       for (int p = 0; p < num_patients; ++p)

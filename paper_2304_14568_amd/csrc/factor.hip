@@ -14,7 +14,10 @@
 //        A_:K = U, A_K: = U^T, A_KK = -P;
 //     after the last block A = -B_s^-1.  k_sweep_store writes M_s = B_s^-1 in fp32.
 //  4. every iteration: k_fhead (pending dual update, right-hand side c_s),
-//     k_fobj (objective at z from the quadratic form), k_xgemv (x_s = M_s c_s).
+//     k_fobj (objective at z from the quadratic form), k_xsym + k_xsym_reduce
+//     (x_s = M_s c_s).
+// The symmetric matrices used in every iteration (M_s and sum_s G_s) are stored
+// as their upper 64 x 64 tiles only, which halves the bytes each iteration reads.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -26,7 +29,11 @@ namespace admmbb {
 
 namespace {
 
-constexpr int kFb = 64;  // sweep block size
+constexpr int kFb = 64;  // sweep block size and packed tile size
+
+__host__ __device__ __forceinline__ int64_t tile_index(int I, int J, int nb) {
+  return static_cast<int64_t>(I) * nb - static_cast<int64_t>(I) * (I - 1) / 2 + (J - I);
+}
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -97,7 +104,9 @@ __global__ __launch_bounds__(256) void k_gram_finish(FactorArgs f, int patient, 
       if (i == j) a += (i < n) ? 0.5 * rho : 1.0;
       f.A[sc.fmat_off + idx] = a;
     }
-    f.Gsum[pt.gsum_off + idx] = sum;
+    const int I = i / kFb, J = j / kFb;
+    if (I <= J)
+      f.Gp[pt.gpack_off + tile_index(I, J, pt.nbk) * kFb * kFb + (i % kFb) * kFb + (j % kFb)] = sum;
   }
 }
 
@@ -244,58 +253,90 @@ __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_beg
     }
 }
 
-// M = -A in fp32
-__global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int scen_begin, int npad) {
-  const int g = scen_begin + static_cast<int>(blockIdx.y);
-  const Scen sc = f.scen[g];
+// packed M = -A (upper tiles) in fp32
+__global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, int npad) {
+  const Pat pt = f.pat[patient];
+  const Scen sc = f.scen[pt.scen_begin + static_cast<int>(blockIdx.y)];
   const int64_t nn = static_cast<int64_t>(npad) * npad;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nn; idx += stride)
-    f.M[sc.fmat_off + idx] = static_cast<float>(-f.A[sc.fmat_off + idx]);
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nn; idx += stride) {
+    const int i = static_cast<int>(idx / npad), j = static_cast<int>(idx % npad);
+    const int I = i / kFb, J = j / kFb;
+    if (I <= J)
+      f.Mp[sc.mpack_off + tile_index(I, J, pt.nbk) * kFb * kFb + (i % kFb) * kFb + (j % kFb)] =
+          static_cast<float>(-f.A[sc.fmat_off + idx]);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // per-iteration kernels
 // ---------------------------------------------------------------------------
 
-// x_s = M_s c_s for kXRows rows of one scenario; c_s staged in LDS
-__global__ __launch_bounds__(256) void k_xgemv(FactorArgs f, const float* __restrict__ c, float* __restrict__ x) {
-  extern __shared__ float cs[];
+// One packed tile T = M_s[I, J] (I <= J) of a scenario: a = T c_J and, off the
+// diagonal, b = T^T c_I (the tile's contribution to the rows of block J).
+// Thread t holds row t/4, columns 16 (t%4) .. +15 (four float4 loads).
+__global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const float* __restrict__ c) {
+  __shared__ float red[kFb][kFb + 1];
+  __shared__ float cI[kFb], cJ[kFb];
   const XJob job = f.xjobs[blockIdx.x];
   const Scen sc = f.scen[job.g];
   if (f.ps[sc.patient].stopped) return;
-  const int ld = f.pat[sc.patient].npad;
-  const int n = sc.n;
-  for (int j = threadIdx.x; j < ld; j += 256) cs[j] = j < n ? c[sc.vec_base + j] : 0.0f;
+  const Pat pt = f.pat[sc.patient];
+  const int I = job.ij >> 16, J = job.ij & 0xffff;
+  const int64_t t = tile_index(I, J, pt.nbk);
+  const float4* T = reinterpret_cast<const float4*>(f.Mp + sc.mpack_off + t * kFb * kFb);
+  const int tid = threadIdx.x;
+  // the tile's 16 KB, in flight before the vectors arrive
+  float4 m[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m[k] = T[tid * 4 + k];
+  if (tid < kFb) {
+    const int jc = J * kFb + tid, ic = I * kFb + tid;
+    cJ[tid] = jc < sc.n ? c[sc.vec_base + jc] : 0.0f;
+    cI[tid] = ic < sc.n ? c[sc.vec_base + ic] : 0.0f;
+  }
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const float* Mb = f.M + sc.fmat_off;
-  const float4* c4 = reinterpret_cast<const float4*>(cs);
-  const int n4 = ld / 4;
-  constexpr int kRowsPerWave = kXRows / 4;
-  float acc[kRowsPerWave];
+  const int i = tid >> 2, q = tid & 3;
+  float a = 0.0f;
+  const float ci = cI[i];
 #pragma unroll
-  for (int q = 0; q < kRowsPerWave; ++q) acc[q] = 0.0f;
-  for (int k4 = lane; k4 < n4; k4 += 64) {
-    const float4 cv = c4[k4];
-#pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q) {
-      const int row = job.row0 + w * kRowsPerWave + q;
-      if (row < n) {
-        const float4 mv = reinterpret_cast<const float4*>(Mb + static_cast<int64_t>(row) * ld)[k4];
-        acc[q] = fmaf(mv.x, cv.x, acc[q]);
-        acc[q] = fmaf(mv.y, cv.y, acc[q]);
-        acc[q] = fmaf(mv.z, cv.z, acc[q]);
-        acc[q] = fmaf(mv.w, cv.w, acc[q]);
-      }
-    }
+  for (int k = 0; k < 4; ++k) {
+    const int j0 = 16 * q + 4 * k;
+    a = fmaf(m[k].x, cJ[j0 + 0], a);
+    a = fmaf(m[k].y, cJ[j0 + 1], a);
+    a = fmaf(m[k].z, cJ[j0 + 2], a);
+    a = fmaf(m[k].w, cJ[j0 + 3], a);
+    red[i][j0 + 0] = m[k].x * ci;
+    red[i][j0 + 1] = m[k].y * ci;
+    red[i][j0 + 2] = m[k].z * ci;
+    red[i][j0 + 3] = m[k].w * ci;
   }
-#pragma unroll
-  for (int q = 0; q < kRowsPerWave; ++q) {
-    const float s = wave_sum_f(acc[q]);
-    const int row = job.row0 + w * kRowsPerWave + q;
-    if (lane == 0 && row < n) x[sc.vec_base + row] = s;
+  a += __shfl_xor(a, 1, 64);
+  a += __shfl_xor(a, 2, 64);
+  float* out = f.xpart + (sc.mpack_off / (kFb * kFb) + t) * (2 * kFb);
+  if (q == 0) out[i] = a;
+  if (I == J) return;
+  __syncthreads();
+  if (tid < kFb) {
+    float bsum = 0.0f;
+    for (int r = 0; r < kFb; ++r) bsum += red[r][tid];
+    out[kFb + tid] = bsum;
   }
+}
+
+// x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of (T_JI^T c_J), fixed order
+__global__ __launch_bounds__(kFb) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
+  const XJob job = f.rjobs[blockIdx.x];
+  const Scen sc = f.scen[job.g];
+  if (f.ps[sc.patient].stopped) return;
+  const Pat pt = f.pat[sc.patient];
+  const int I = job.ij, nb = pt.nbk, i = threadIdx.x;
+  const float* base = f.xpart + (sc.mpack_off / (kFb * kFb)) * (2 * kFb);
+  float s = 0.0f;
+  for (int J = 0; J < I; ++J) s += base[tile_index(J, I, nb) * (2 * kFb) + kFb + i];
+  for (int J = I; J < nb; ++J) s += base[tile_index(I, J, nb) * (2 * kFb) + i];
+  const int row = I * kFb + i;
+  if (row < sc.n) x[sc.vec_base + row] = s;
 }
 
 // completion of the pending dual update and the right-hand side
@@ -330,38 +371,46 @@ __global__ __launch_bounds__(kColBlock) void k_fhead(VecArgs a) {
   }
 }
 
-// objective partial over kXRows rows: sum_r z_r ((Gsum z)_r - g0_r), fp64
+// objective partial of one packed tile T of sum_s G_s: z_I^T T z_J, doubled off
+// the diagonal; a diagonal tile also carries -g0_I^T z_I.  fp64.
 __global__ __launch_bounds__(256) void k_fobj(FactorArgs f, const float* __restrict__ z) {
-  extern __shared__ double zs[];
+  __shared__ double zI[kFb], zJ[kFb], red[4];
   const XJob job = f.fjobs[blockIdx.x];
   const Pat pt = f.pat[job.g];
   if (f.ps[job.g].stopped) return;
-  const int ld = pt.npad, n = pt.n;
-  for (int j = threadIdx.x; j < ld; j += 256) zs[j] = j < n ? static_cast<double>(z[pt.zvec_base + j]) : 0.0;
-  __syncthreads();
-  __shared__ double red[4];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double* Gb = f.Gsum + pt.gsum_off;
-  constexpr int kRowsPerWave = kXRows / 4;
-  double part = 0.0;
+  const int I = job.ij >> 16, J = job.ij & 0xffff;
+  const double2* T =
+      reinterpret_cast<const double2*>(f.Gp + pt.gpack_off + tile_index(I, J, pt.nbk) * kFb * kFb);
+  const int tid = threadIdx.x;
+  double2 g[8];
 #pragma unroll
-  for (int q = 0; q < kRowsPerWave; ++q) {
-    const int row = job.row0 + w * kRowsPerWave + q;
-    if (row >= n) continue;
-    double acc = 0.0;
-    const double2* gr = reinterpret_cast<const double2*>(Gb + static_cast<int64_t>(row) * ld);
-    const double2* z2 = reinterpret_cast<const double2*>(zs);
-    for (int k2 = lane; k2 < ld / 2; k2 += 64) {
-      const double2 gv = gr[k2], zv = z2[k2];
-      acc = fma(gv.x, zv.x, acc);
-      acc = fma(gv.y, zv.y, acc);
-    }
-    acc = wave_sum_d(acc);
-    part += zs[row] * (acc - f.g0[pt.zvec_base + row]);
+  for (int k = 0; k < 8; ++k) g[k] = T[tid * 8 + k];
+  if (tid < kFb) {
+    const int jc = J * kFb + tid, ic = I * kFb + tid;
+    zJ[tid] = jc < pt.n ? static_cast<double>(z[pt.zvec_base + jc]) : 0.0;
+    zI[tid] = ic < pt.n ? static_cast<double>(z[pt.zvec_base + ic]) : 0.0;
   }
-  if (lane == 0) red[w] = part;
   __syncthreads();
-  if (threadIdx.x == 0) f.fpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  const int i = tid >> 2, q = tid & 3;
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int j0 = 16 * q + 2 * k;
+    a = fma(g[k].x, zJ[j0], a);
+    a = fma(g[k].y, zJ[j0 + 1], a);
+  }
+  a += __shfl_xor(a, 1, 64);
+  a += __shfl_xor(a, 2, 64);
+  double v = 0.0;
+  if (q == 0) {
+    v = (I == J ? 1.0 : 2.0) * zI[i] * a;
+    const int row = I * kFb + i;
+    if (I == J && row < pt.n) v -= f.g0[pt.zvec_base + row] * zI[i];
+  }
+  v = wave_sum_d(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) f.fpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 }  // namespace
@@ -389,20 +438,23 @@ void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0
   hipLaunchKernelGGL(k_sweep_update, dim3(nbk * nbk, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
 }
 
-void launch_sweep_store(FactorArgs f, int scen_begin, int nscen, int npad, hipStream_t st) {
+void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStream_t st) {
   int64_t nb = (static_cast<int64_t>(npad) * npad + 255) / 256;
   if (nb > 4096) nb = 4096;
-  hipLaunchKernelGGL(k_sweep_store, dim3(static_cast<unsigned>(nb), nscen), dim3(256), 0, st, f, scen_begin, npad);
+  hipLaunchKernelGGL(k_sweep_store, dim3(static_cast<unsigned>(nb), nscen), dim3(256), 0, st, f, patient, npad);
 }
 
-void launch_xgemv(const FactorArgs& f, const float* c, float* x, int njobs, int ldmax, hipStream_t st, hipEvent_t e0,
-                  hipEvent_t e1) {
+void launch_xsym(const FactorArgs& f, const float* c, int njobs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (njobs <= 0) return;
-  const size_t smem = sizeof(float) * static_cast<size_t>(ldmax);
   if (e0 != nullptr)
-    hipExtLaunchKernelGGL(k_xgemv, dim3(njobs), dim3(256), smem, st, e0, e1, 0, f, c, x);
+    hipExtLaunchKernelGGL(k_xsym, dim3(njobs), dim3(256), 0, st, e0, e1, 0, f, c);
   else
-    hipLaunchKernelGGL(k_xgemv, dim3(njobs), dim3(256), smem, st, f, c, x);
+    hipLaunchKernelGGL(k_xsym, dim3(njobs), dim3(256), 0, st, f, c);
+}
+
+void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(kFb), 0, st, f, x);
 }
 
 void launch_fhead(const VecArgs& a, int nblk, hipStream_t st) {
@@ -410,10 +462,9 @@ void launch_fhead(const VecArgs& a, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(k_fhead, dim3(nblk), dim3(kColBlock), 0, st, a);
 }
 
-void launch_fobj(const FactorArgs& f, const float* z, int njobs, int ldmax, hipStream_t st) {
+void launch_fobj(const FactorArgs& f, const float* z, int njobs, hipStream_t st) {
   if (njobs <= 0) return;
-  const size_t smem = sizeof(double) * static_cast<size_t>(ldmax);
-  hipLaunchKernelGGL(k_fobj, dim3(njobs), dim3(256), smem, st, f, z);
+  hipLaunchKernelGGL(k_fobj, dim3(njobs), dim3(256), 0, st, f, z);
 }
 
 }  // namespace admmbb

@@ -35,7 +35,8 @@ struct Scen {
   int32_t tile_begin, tile_end;
   float cw;             // scenario probability c_s (already folded into rw)
   int32_t pad;
-  int64_t fmat_off;     // dense x-update: offset of this scenario's npad x npad matrices
+  int64_t fmat_off;     // dense x-update: offset of this scenario's npad x npad matrices (set-up)
+  int64_t mpack_off;    // dense x-update: offset of its packed inverse (upper 64 x 64 tiles, 4096 each)
 };
 
 // One per patient.
@@ -48,9 +49,9 @@ struct Pat {
   double fzero;                 // sum_s c_s sum_{i: row i of A_s empty} w_i p_i^2 (objective of dropped rows)
   double fconst;                // sum_s c_s sum_i w_i p_i^2 (objective at x = 0)
   int32_t npad;                 // dense x-update: n rounded up to whole 64-blocks
-  int32_t fobj_begin, fobj_end; // dense x-update: objective workgroups of this patient
-  int32_t pad;
-  int64_t gsum_off;             // dense x-update: offset of sum_s G_s (npad x npad, fp64)
+  int32_t fobj_begin, fobj_end; // dense x-update: objective workgroups (one per packed tile) of this patient
+  int32_t nbk;                  // dense x-update: npad / 64
+  int64_t gpack_off;            // dense x-update: offset of sum_s G_s, packed upper tiles, fp64
 };
 
 // A contiguous range of length-sorted rows of one scenario, handled by one
@@ -178,26 +179,31 @@ struct VecArgs {
 
 // Dense x-update (cached inverse of every B_s): device arrays and work tables.
 struct XJob {
-  int32_t g;     // scenario (x-update GEMV) or patient (objective)
-  int32_t row0;  // first of the rows of the workgroup
+  int32_t g;    // scenario (x-update) or patient (objective)
+  int32_t ij;   // tile (I, J) as I * 65536 + J, or the block row I (reduction)
 };
 
+// Symmetric matrices of the dense x-update are stored as their upper 64 x 64
+// tiles (I <= J) in the order t(I, J) = I nb - I (I - 1) / 2 + (J - I), each
+// tile row-major.
 struct FactorArgs {
   const Scen* scen;
   const Pat* pat;
   const PatState* ps;
-  double* G;          // per scenario: G_s = A_s^T c_s W A_s (upper triangle accumulated, then mirrored), fp64
-  double* A;          // per scenario: sweep work matrix, ends as -(G_s + rho/2 I)^-1
-  float* M;           // per scenario: (G_s + rho/2 I)^-1, fp32
-  double* Gsum;       // per patient: sum_s G_s, fp64
+  double* G;          // per scenario: G_s = A_s^T c_s W A_s, full npad x npad, fp64 (set-up)
+  double* A;          // per scenario: sweep work matrix, ends as -(G_s + rho/2 I)^-1 (set-up)
+  float* Mp;          // per scenario: packed (G_s + rho/2 I)^-1, fp32
+  double* Gp;         // per patient: packed sum_s G_s, fp64
   const double* g0;   // per patient: 2 sum_s A_s^T c_s W p, fp64 (zvec layout)
   double* P;          // per scenario: 64 x 64 pivot-block inverse
-  double* U;          // per scenario: 64 x npad column panel, transposed
-  double* R;          // per scenario: 64 x npad row panel
-  const XJob* xjobs;  // x-update GEMV workgroups
-  const XJob* fjobs;  // objective workgroups
-  double* fpart;      // objective partial per objective workgroup
-  int32_t npmax;      // largest npad: per-scenario stride of U and R (npmax x 64 each)
+  double* U;          // per scenario: 64 x npmax column panel, transposed
+  double* R;          // per scenario: 64 x npmax row panel
+  float* xpart;       // per packed tile of every scenario: T c_J (64) and T^T c_I (64)
+  const XJob* xjobs;  // x-update: one per packed tile of every scenario
+  const XJob* rjobs;  // x-update reduction: one per block row of every scenario
+  const XJob* fjobs;  // objective: one per packed tile of every patient
+  double* fpart;      // objective partial per objective job
+  int32_t npmax;      // largest npad
   int32_t pad;
 };
 
@@ -223,15 +229,15 @@ void launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st);
 int pass_smem_bytes(int nmax, int acc);
 int dose_hist_smem_bytes(int G, int nbins);
-constexpr int kXRows = 16;     // rows of a dense x-update / objective workgroup
 void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G, int ld, hipStream_t st);
 void launch_gram_finish(FactorArgs f, int patient, int nscen, int npad, int n, double rho, hipStream_t st);
 void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st);
-void launch_sweep_store(FactorArgs f, int scen_begin, int nscen, int npad, hipStream_t st);
-void launch_xgemv(const FactorArgs& f, const float* c, float* x, int njobs, int ldmax, hipStream_t st,
-                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStream_t st);
+void launch_xsym(const FactorArgs& f, const float* c, int njobs, hipStream_t st, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr);
+void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st);
 void launch_fhead(const VecArgs& a, int nblk, hipStream_t st);
-void launch_fobj(const FactorArgs& f, const float* z, int njobs, int ldmax, hipStream_t st);
+void launch_fobj(const FactorArgs& f, const float* z, int njobs, hipStream_t st);
 void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
                       double* sums, uint32_t* maxkey, hipStream_t st);
 
