@@ -762,7 +762,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     for (int p = 0; p < num_patients; ++p) c->reset_patient(p, nullptr, 0.0);
     if (o.pass_threads) c->pass_threads = o.pass_threads;
     if (o.pass_unroll) c->pass_unroll = o.pass_unroll;
-    c->autotune();
+    if (!c->dense) c->autotune();  // the dense x-update does not run the CG pass per iteration
     check(hipEventCreate(&c->ev_a), "hipEventCreate");
     check(hipEventCreate(&c->ev_b), "hipEventCreate");
     check(hipStreamSynchronize(c->stream), "setup sync");

@@ -324,19 +324,27 @@ __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const float* __restr
   }
 }
 
-// x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of (T_JI^T c_J), fixed order
-__global__ __launch_bounds__(kFb) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
+// x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
+// (T_JI^T c_J).  Wave w adds the blocks J = w, w + 4, ...; the four partial
+// sums are then added in a fixed order.
+__global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
+  __shared__ float part[4][kFb];
   const XJob job = f.rjobs[blockIdx.x];
   const Scen sc = f.scen[job.g];
   if (f.ps[sc.patient].stopped) return;
   const Pat pt = f.pat[sc.patient];
-  const int I = job.ij, nb = pt.nbk, i = threadIdx.x;
+  const int I = job.ij, nb = pt.nbk;
+  const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
   const float* base = f.xpart + (sc.mpack_off / (kFb * kFb)) * (2 * kFb);
   float s = 0.0f;
-  for (int J = 0; J < I; ++J) s += base[tile_index(J, I, nb) * (2 * kFb) + kFb + i];
-  for (int J = I; J < nb; ++J) s += base[tile_index(I, J, nb) * (2 * kFb) + i];
-  const int row = I * kFb + i;
-  if (row < sc.n) x[sc.vec_base + row] = s;
+  for (int J = w; J < nb; J += 4)
+    s += (J < I) ? base[tile_index(J, I, nb) * (2 * kFb) + kFb + i] : base[tile_index(I, J, nb) * (2 * kFb) + i];
+  part[w][i] = s;
+  __syncthreads();
+  if (w == 0) {
+    const int row = I * kFb + i;
+    if (row < sc.n) x[sc.vec_base + row] = (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
+  }
 }
 
 // completion of the pending dual update and the right-hand side
@@ -454,7 +462,7 @@ void launch_xsym(const FactorArgs& f, const float* c, int njobs, hipStream_t st,
 
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st) {
   if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(kFb), 0, st, f, x);
+  hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(256), 0, st, f, x);
 }
 
 void launch_fhead(const VecArgs& a, int nblk, hipStream_t st) {

@@ -741,7 +741,13 @@ void launch_cg_dir(const VecArgs& a, int nblk, hipStream_t st) {
 // workgroup (every quantity is columnwise until the final sums)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kColBlock) void k_zres(VecArgs a) {
+// Four waves per 64-column block: wave w takes the scenarios s = w, w + 4, ...
+// (more loads in flight than one wave looping over all scenarios); partial
+// sums are combined in a fixed order, so the result does not depend on timing.
+__global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
+  __shared__ double sacc[4][64];
+  __shared__ double sloc[4][4];
+  __shared__ float zsh[64];
   const int bi = static_cast<int>(blockIdx.x);
   const Blk bk = a.pblk[bi];
   const int p = bk.owner;
@@ -749,46 +755,74 @@ __global__ __launch_bounds__(kColBlock) void k_zres(VecArgs a) {
   const PatState* ps = a.ps + p;
   if (ps->stopped) return;
   const double rho = ps->rho;
-  const int j = bk.col0 + static_cast<int>(threadIdx.x);
-  double loc[6] = {0, 0, 0, 0, 0, 0};  // ||dz||^2, ||z||^2, ||d||^2, <dd,d_prev>, ||dd||^2, ||x||^2
-  if (j < pt.n) {
-    double acc = 0.0;
-    for (int s = 0; s < pt.num_scen; ++s) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = bk.col0 + lane;
+  const bool valid = j < pt.n;
+  double acc = 0.0;
+  if (valid)
+    for (int s = w; s < pt.num_scen; s += 4) {
       const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
       acc += static_cast<double>(a.x[vi]);
       if (a.prm.z_mode == 0) acc += static_cast<double>(a.y[vi]) / rho;
     }
-    const int64_t zi = pt.zvec_base + j;
-    double zn = acc / pt.num_scen;
-    zn = fmin(fmax(zn, static_cast<double>(a.lb[zi])), static_cast<double>(a.ub[zi]));
-    const float znf = static_cast<float>(zn);
-    const double dz = static_cast<double>(znf) - static_cast<double>(a.z[zi]);
-    a.z[zi] = znf;
-    loc[0] = dz * dz;
-    loc[1] = static_cast<double>(znf) * znf;
-    for (int s = 0; s < pt.num_scen; ++s) {
+  sacc[w][lane] = acc;
+  __syncthreads();
+  double loc0 = 0.0, loc1 = 0.0;
+  if (w == 0) {
+    float znf = 0.0f;
+    if (valid) {
+      const int64_t zi = pt.zvec_base + j;
+      double zn = ((sacc[0][lane] + sacc[1][lane]) + (sacc[2][lane] + sacc[3][lane])) / pt.num_scen;
+      zn = fmin(fmax(zn, static_cast<double>(a.lb[zi])), static_cast<double>(a.ub[zi]));
+      znf = static_cast<float>(zn);
+      const double dz = static_cast<double>(znf) - static_cast<double>(a.z[zi]);
+      a.z[zi] = znf;
+      loc0 = dz * dz;
+      loc1 = static_cast<double>(znf) * znf;
+    }
+    zsh[lane] = znf;
+  }
+  __syncthreads();
+  // ||d||^2, <dd, d_prev>, ||dd||^2, ||x||^2 over this wave's scenarios
+  double l2 = 0.0, l3 = 0.0, l4 = 0.0, l5 = 0.0;
+  if (valid) {
+    const double znd = static_cast<double>(zsh[lane]);
+    for (int s = w; s < pt.num_scen; s += 4) {
       const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
       const double xv = static_cast<double>(a.x[vi]);
-      const double d = xv - static_cast<double>(znf);
+      const double d = xv - znd;
       const double dp = a.dprev[vi];
       const double dd = d - dp;
-      loc[2] += d * d;
-      loc[3] += dd * dp;
-      loc[4] += dd * dd;
-      loc[5] += xv * xv;
+      l2 += d * d;
+      l3 += dd * dp;
+      l4 += dd * dd;
+      l5 += xv * xv;
       a.dprev[vi] = d;
     }
   }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) loc[k] = wave_sum(loc[k]);
+  l2 = wave_sum(l2);
+  l3 = wave_sum(l3);
+  l4 = wave_sum(l4);
+  l5 = wave_sum(l5);
+  if (lane == 0) {
+    sloc[w][0] = l2;
+    sloc[w][1] = l3;
+    sloc[w][2] = l4;
+    sloc[w][3] = l5;
+  }
+  loc0 = wave_sum(loc0);
+  loc1 = wave_sum(loc1);
+  __syncthreads();
   if (threadIdx.x == 0) {
     double* bp = a.bpartp + static_cast<int64_t>(bi) * 8;
-    for (int k = 0; k < 6; ++k) bp[k] = loc[k];
+    bp[0] = loc0;
+    bp[1] = loc1;
+    for (int k = 0; k < 4; ++k) bp[2 + k] = (sloc[0][k] + sloc[1][k]) + (sloc[2][k] + sloc[3][k]);
   }
 }
 
 void launch_zres(const VecArgs& a, int npblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_zres, dim3(npblk), dim3(kColBlock), 0, st, a);
+  hipLaunchKernelGGL(k_zres, dim3(npblk), dim3(kThreads), 0, st, a);
 }
 
 // Residual norms, tolerances and the Barzilai-Borwein dual step per patient.

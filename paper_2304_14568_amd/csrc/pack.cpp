@@ -6,9 +6,15 @@
 // rows is free; sorting lets each workgroup tile use one lanes-per-row width
 // that keeps a row's nonzeros in registers (at most kRegChunks per lane),
 // and makes neighbouring rows of a tile equally long.
+//
+// Every (patient, scenario) pair is packed by its own host thread into
+// preallocated ranges of the shared arrays; the per-patient sums are then
+// formed in scenario order, so the result does not depend on the threads.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "host.h"
 
@@ -38,6 +44,41 @@ static int lanes_for(int64_t chunks) {
   return L;
 }
 
+namespace {
+
+// What one thread produces for one (patient, scenario) pair besides the shared arrays.
+struct ScenOut {
+  int64_t rows = 0, chunks = 0;        // nonempty rows, 4-element chunks after padding
+  int64_t nnz_base = 0, row_base = 0, rp_base = 0;
+  std::vector<Tile> tiles;             // part_off filled at the merge
+  std::vector<double> b, gdiag;        // n each
+  double fzero = 0.0, fconst = 0.0;
+};
+
+template <class F>
+void parallel_for(int count, F&& fn) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = static_cast<int>(std::min<unsigned>(hw, static_cast<unsigned>(std::max(1, count))));
+  std::atomic<int> next{0};
+  std::atomic<bool> oom{false};
+  auto worker = [&]() {
+    for (int k = next++; k < count; k = next++) {
+      try {
+        fn(k);
+      } catch (const std::bad_alloc&) {
+        oom = true;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+  if (oom) throw std::bad_alloc();
+}
+
+}  // namespace
+
 admm_status pack_problems(const admm_problem* probs, int num_patients, const admm_options& o, Packed* out,
                           std::string* msg) {
   Packed& P = *out;
@@ -55,24 +96,186 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
     if (probs[p].n > 65535) P.col16_used = false;
   }
   const bool lp = o.precision != ADMM_PREC_FP32;
-  try {
-    const size_t cap = static_cast<size_t>(nnz_all + nnz_all / 16 + 1024);
-    P.val.reserve(cap);
-    if (P.col16_used)
-      P.col16.reserve(cap);
-    else
-      P.col32.reserve(cap);
-    if (lp) P.val_lp.reserve(cap);
-  } catch (const std::bad_alloc&) {
-    if (msg) *msg = "host allocation failed while packing";
-    return ADMM_E_OOM;
-  }
 
-  int64_t nnz_base = 0, row_base = 0, rp_base = 0;
-  int blk_s = 0, blk_p = 0;
-  P.g0.resize(num_patients);
-  P.gdiag_mean.resize(num_patients);
+  // jobs in (patient, scenario) order
+  std::vector<int> job_p, job_s;
+  for (int p = 0; p < num_patients; ++p)
+    for (int s = 0; s < probs[p].num_scen; ++s) {
+      job_p.push_back(p);
+      job_s.push_back(s);
+    }
+  const int J = static_cast<int>(job_p.size());
   try {
+    std::vector<ScenOut> so(J);
+    // sizes: nonempty rows and padded chunks of every scenario
+    parallel_for(J, [&](int k) {
+      const admm_csr& A = probs[job_p[k]].A[job_s[k]];
+      const int m = probs[job_p[k]].m;
+      int64_t rows = 0, chunks = 0;
+      for (int i = 0; i < m; ++i) {
+        const int64_t len = A.row_ptr[i + 1] - A.row_ptr[i];
+        if (len > 0) {
+          rows++;
+          chunks += (len + 3) / 4;
+        }
+      }
+      so[k].rows = rows;
+      so[k].chunks = chunks;
+    });
+    int64_t nnz_base = 0, row_base = 0, rp_base = 0;
+    for (int k = 0; k < J; ++k) {
+      so[k].nnz_base = nnz_base;
+      so[k].row_base = row_base;
+      so[k].rp_base = rp_base;
+      nnz_base += 4 * so[k].chunks;
+      row_base += so[k].rows;
+      rp_base += so[k].rows + 1;
+    }
+    const size_t ntot = static_cast<size_t>(nnz_base + 4 * 256);  // trailing zero chunks
+    P.val.assign(ntot, 0.0f);
+    if (P.col16_used)
+      P.col16.assign(ntot, 0);
+    else
+      P.col32.assign(ntot, 0);
+    if (lp) {
+      P.val_lp.assign(ntot, 0);
+      P.rscale.resize(static_cast<size_t>(row_base));
+    }
+    P.rw.resize(static_cast<size_t>(row_base));
+    P.rw64.resize(static_cast<size_t>(row_base));
+    P.rpres.resize(static_cast<size_t>(row_base));
+    P.rorig.resize(static_cast<size_t>(row_base));
+    P.rp.resize(static_cast<size_t>(rp_base));
+
+    // fill every scenario's ranges
+    parallel_for(J, [&](int k) {
+      const admm_problem& pr = probs[job_p[k]];
+      const admm_csr& A = pr.A[job_s[k]];
+      const int n = pr.n, m = pr.m;
+      ScenOut& r = so[k];
+      const double c = A.prob == 0.0 ? 1.0 : A.prob;
+      // counting sort of the nonzero rows by decreasing length (stable)
+      int64_t maxlen = 0;
+      for (int i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, A.row_ptr[i + 1] - A.row_ptr[i]);
+      std::vector<int64_t> cnt(static_cast<size_t>(maxlen) + 2, 0);
+      for (int i = 0; i < m; ++i) {
+        const int64_t len = A.row_ptr[i + 1] - A.row_ptr[i];
+        if (len > 0) cnt[static_cast<size_t>(maxlen - len)]++;
+      }
+      int64_t acc = 0;
+      for (auto& c2 : cnt) {
+        const int64_t t = c2;
+        c2 = acc;
+        acc += t;
+      }
+      std::vector<int32_t> order(static_cast<size_t>(r.rows));
+      for (int i = 0; i < m; ++i) {
+        const int64_t len = A.row_ptr[i + 1] - A.row_ptr[i];
+        if (len > 0) order[static_cast<size_t>(cnt[static_cast<size_t>(maxlen - len)]++)] = i;
+      }
+      for (int i = 0; i < m; ++i) {
+        const double wp2 = c * pr.struct_weight[pr.struct_id[i]] * pr.presc[i] * pr.presc[i];
+        r.fconst += wp2;
+        if (A.row_ptr[i + 1] == A.row_ptr[i]) r.fzero += wp2;
+      }
+      r.b.assign(n, 0.0);
+      r.gdiag.assign(n, 0.0);
+      std::vector<double> row_w(static_cast<size_t>(r.rows)), row_p(static_cast<size_t>(r.rows));
+      uint32_t* rpp = P.rp.data() + r.rp_base;
+      rpp[0] = 0;
+      uint32_t off = 0;
+      for (int64_t q = 0; q < r.rows; ++q) {
+        const int i = order[static_cast<size_t>(q)];
+        const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
+        const double wi = pr.struct_weight[pr.struct_id[i]];
+        const double cwi = c * wi;
+        float rmax = 0.0f;
+        double rsum = 0.0;
+        for (int64_t t = b; t < e; ++t) {
+          rsum += A.val[t];
+          rmax = std::max(rmax, A.val[t]);
+        }
+        row_w[static_cast<size_t>(q)] = cwi * rsum;
+        row_p[static_cast<size_t>(q)] = cwi * pr.presc[i];
+        const int64_t dst = r.nnz_base + 4 * static_cast<int64_t>(off);
+        const float scl = rmax > 0.0f ? rmax : 1.0f;
+        const int64_t len = e - b, len4 = (len + 3) & ~int64_t(3);
+        for (int64_t t = 0; t < len4; ++t) {
+          // pad the row to whole 4-element chunks: value 0, column = the row's last column
+          const int64_t src = t < len ? b + t : e - 1;
+          const int32_t j = A.col[src];
+          const float v = t < len ? A.val[src] : 0.0f;
+          if (P.col16_used)
+            P.col16[static_cast<size_t>(dst + t)] = static_cast<uint16_t>(j);
+          else
+            P.col32[static_cast<size_t>(dst + t)] = j;
+          P.val[static_cast<size_t>(dst + t)] = v;
+          if (lp) {
+            const float qv = v / scl;
+            P.val_lp[static_cast<size_t>(dst + t)] =
+                t < len ? (o.precision == ADMM_PREC_BF16 ? to_bf16_bits(qv) : to_f16_bits(qv)) : 0;
+          }
+          if (t < len) {
+            r.b[j] += cwi * pr.presc[i] * static_cast<double>(v);
+            r.gdiag[j] += cwi * static_cast<double>(v) * static_cast<double>(v);
+          }
+        }
+        const int64_t ro = r.row_base + q;
+        if (lp) P.rscale[static_cast<size_t>(ro)] = scl;
+        P.rw[static_cast<size_t>(ro)] = static_cast<float>(cwi);
+        P.rw64[static_cast<size_t>(ro)] = cwi;
+        P.rpres[static_cast<size_t>(ro)] = static_cast<float>(pr.presc[i]);
+        P.rorig[static_cast<size_t>(ro)] = i;
+        off += static_cast<uint32_t>(len4 / 4);
+        rpp[q + 1] = off;
+      }
+      // tiles: consecutive rows with one lanes-per-row width, ~tile_nnz nonzeros each
+      std::vector<double> colsum(n, 0.0);
+      std::vector<int32_t> touched;
+      auto round_up = [](double x) { return static_cast<float>(x * (1.0 + 1e-6)); };
+      int64_t q = 0;
+      while (q < r.rows) {
+        const int L = lanes_for(rpp[q + 1] - rpp[q]);
+        int64_t q1 = q;
+        int64_t nz = 0;
+        while (q1 < r.rows && lanes_for(rpp[q1 + 1] - rpp[q1]) == L && (nz < tile_chunks || q1 == q)) {
+          nz += rpp[q1 + 1] - rpp[q1];
+          ++q1;
+        }
+        Tile t{};
+        t.scen = k;  // global scenario index = job index
+        t.row_begin = static_cast<int32_t>(q);
+        t.row_end = static_cast<int32_t>(q1);
+        t.lanes = L;
+        double wm = 0.0, pm = 0.0, cm = 0.0;
+        for (int64_t rr = q; rr < q1; ++rr) {
+          wm = std::max(wm, row_w[static_cast<size_t>(rr)]);
+          pm = std::max(pm, row_p[static_cast<size_t>(rr)]);
+          for (int64_t e = r.nnz_base + 4 * static_cast<int64_t>(rpp[rr]);
+               e < r.nnz_base + 4 * static_cast<int64_t>(rpp[rr + 1]); ++e) {
+            const int32_t j = P.col16_used ? P.col16[static_cast<size_t>(e)] : P.col32[static_cast<size_t>(e)];
+            if (colsum[j] == 0.0) touched.push_back(j);
+            colsum[j] += P.val[static_cast<size_t>(e)];
+          }
+        }
+        for (int32_t j : touched) {
+          cm = std::max(cm, colsum[j]);
+          colsum[j] = 0.0;
+        }
+        touched.clear();
+        t.wmax = round_up(wm);
+        t.pmax = round_up(pm);
+        t.cmax = round_up(cm);
+        r.tiles.push_back(t);
+        q = q1;
+      }
+    });
+
+    // merge in (patient, scenario) order
+    P.g0.resize(num_patients);
+    P.gdiag_mean.resize(num_patients);
+    int blk_s = 0, blk_p = 0;
+    int k = 0;
     for (int p = 0; p < num_patients; ++p) {
       const admm_problem& pr = probs[p];
       const int n = pr.n, m = pr.m, N = pr.num_scen;
@@ -87,170 +290,43 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       pt.nblk = (n + kColBlock - 1) / kColBlock;
       for (int b = 0; b < pt.nblk; ++b) P.pblk.push_back(Blk{p, b * kColBlock});
       blk_p += pt.nblk;
-
-      std::vector<double> w(m);
-      for (int i = 0; i < m; ++i) w[i] = pr.struct_weight[pr.struct_id[i]];
       std::vector<double> g0(n, 0.0);
-      std::vector<std::vector<double>> gdiag(N, std::vector<double>(n, 0.0));
       double gsum = 0.0;
-      std::vector<int64_t> cnt;
-      std::vector<int32_t> order;
-      for (int s = 0; s < N; ++s) {
+      const int k0 = k;
+      for (int s = 0; s < N; ++s, ++k) {
+        ScenOut& r = so[k];
         const admm_csr& A = pr.A[s];
-        const double c = A.prob == 0.0 ? 1.0 : A.prob;
         Scen sc{};
         sc.patient = p;
         sc.n = n;
         sc.m = m;
-        sc.cw = static_cast<float>(c);
-        sc.row_base = row_base;
-        sc.rp_base = rp_base;
-        sc.nnz_base = nnz_base;
+        sc.cw = static_cast<float>(A.prob == 0.0 ? 1.0 : A.prob);
+        sc.rows = static_cast<int32_t>(r.rows);
+        sc.row_base = r.row_base;
+        sc.rp_base = r.rp_base;
+        sc.nnz_base = r.nnz_base;
         sc.vec_base = P.vec_total;
         sc.blk_begin = blk_s;
         sc.nblk = (n + kColBlock - 1) / kColBlock;
-        const int g = static_cast<int>(P.scen.size());
-        for (int b = 0; b < sc.nblk; ++b) P.blk.push_back(Blk{g, b * kColBlock});
+        for (int b = 0; b < sc.nblk; ++b) P.blk.push_back(Blk{k, b * kColBlock});
         blk_s += sc.nblk;
-
-        // counting sort of the nonzero rows by decreasing length (stable)
-        int64_t maxlen = 0;
-        for (int i = 0; i < m; ++i) maxlen = std::max<int64_t>(maxlen, A.row_ptr[i + 1] - A.row_ptr[i]);
-        cnt.assign(static_cast<size_t>(maxlen) + 2, 0);
-        int64_t rows = 0;
-        for (int i = 0; i < m; ++i) {
-          const int64_t len = A.row_ptr[i + 1] - A.row_ptr[i];
-          if (len > 0) {
-            cnt[static_cast<size_t>(maxlen - len)]++;
-            rows++;
-          }
-        }
-        int64_t acc = 0;
-        for (auto& c2 : cnt) {
-          const int64_t t = c2;
-          c2 = acc;
-          acc += t;
-        }
-        order.assign(static_cast<size_t>(rows), 0);
-        for (int i = 0; i < m; ++i) {
-          const int64_t len = A.row_ptr[i + 1] - A.row_ptr[i];
-          if (len > 0) order[static_cast<size_t>(cnt[static_cast<size_t>(maxlen - len)]++)] = i;
-        }
-        sc.rows = static_cast<int32_t>(rows);
-        for (int i = 0; i < m; ++i) {
-          const double wp2 = c * w[i] * pr.presc[i] * pr.presc[i];
-          pt.fconst += wp2;
-          if (A.row_ptr[i + 1] == A.row_ptr[i]) pt.fzero += wp2;
-        }
-
-        // rows, values, per-row constants
-        uint32_t off = 0;
-        P.rp.push_back(0);
-        std::vector<double> bs(n, 0.0);
-        std::vector<double> row_w(static_cast<size_t>(rows)), row_p(static_cast<size_t>(rows));
-        for (int64_t r = 0; r < rows; ++r) {
-          const int i = order[static_cast<size_t>(r)];
-          const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
-          const double cwi = c * w[i];
-          float rmax = 0.0f;
-          double rsum = 0.0;
-          for (int64_t k = b; k < e; ++k) rsum += A.val[k];
-          row_w[static_cast<size_t>(r)] = cwi * rsum;
-          row_p[static_cast<size_t>(r)] = cwi * pr.presc[i];
-          for (int64_t k = b; k < e; ++k) {
-            const int32_t j = A.col[k];
-            const float v = A.val[k];
-            if (P.col16_used)
-              P.col16.push_back(static_cast<uint16_t>(j));
-            else
-              P.col32.push_back(j);
-            P.val.push_back(v);
-            rmax = std::max(rmax, v);
-            bs[j] += cwi * pr.presc[i] * static_cast<double>(v);
-            gdiag[s][j] += cwi * static_cast<double>(v) * static_cast<double>(v);
-          }
-          if (lp) {
-            const float scl = rmax > 0.0f ? rmax : 1.0f;
-            P.rscale.push_back(scl);
-            for (int64_t k = b; k < e; ++k) {
-              const float q = A.val[k] / scl;
-              P.val_lp.push_back(o.precision == ADMM_PREC_BF16 ? to_bf16_bits(q) : to_f16_bits(q));
-            }
-          }
-          // pad the row to whole 4-element chunks: value 0, column = the row's last column
-          const int64_t len = e - b, len4 = (len + 3) & ~int64_t(3);
-          for (int64_t k = len; k < len4; ++k) {
-            const int32_t j = A.col[e - 1];
-            if (P.col16_used)
-              P.col16.push_back(static_cast<uint16_t>(j));
-            else
-              P.col32.push_back(j);
-            P.val.push_back(0.0f);
-            if (lp) P.val_lp.push_back(0);
-          }
-          P.rw.push_back(static_cast<float>(cwi));
-          P.rw64.push_back(cwi);
-          P.rpres.push_back(static_cast<float>(pr.presc[i]));
-          P.rorig.push_back(i);
-          off += static_cast<uint32_t>(len4 / 4);
-          P.rp.push_back(off);
-        }
-        for (int j = 0; j < n; ++j) {
-          P.gdiag.push_back(static_cast<float>(gdiag[s][j]));
-          P.b.push_back(static_cast<float>(bs[j]));
-          g0[j] += 2.0 * bs[j];
-          gsum += gdiag[s][j];
-        }
-
-        // tiles: consecutive rows with one lanes-per-row width, ~tile_nnz nonzeros each
         sc.tile_begin = static_cast<int32_t>(P.tiles.size());
-        int64_t r = 0;
-        const uint32_t* rpp = P.rp.data() + rp_base;
-        std::vector<double> colsum(n, 0.0);
-        std::vector<int32_t> touched;
-        auto round_up = [](double x) { return static_cast<float>(x * (1.0 + 1e-6)) ; };
-        while (r < rows) {
-          const int L = lanes_for(rpp[r + 1] - rpp[r]);
-          int64_t r1 = r;
-          int64_t nz = 0;
-          while (r1 < rows && lanes_for(rpp[r1 + 1] - rpp[r1]) == L && (nz < tile_chunks || r1 == r)) {
-            nz += rpp[r1 + 1] - rpp[r1];
-            ++r1;
-          }
-          Tile t{};
-          t.scen = g;
-          t.row_begin = static_cast<int32_t>(r);
-          t.row_end = static_cast<int32_t>(r1);
-          t.lanes = L;
-          double wm = 0.0, pm = 0.0, cm = 0.0;
-          for (int64_t rr = r; rr < r1; ++rr) {
-            wm = std::max(wm, row_w[static_cast<size_t>(rr)]);
-            pm = std::max(pm, row_p[static_cast<size_t>(rr)]);
-            for (int64_t k = nnz_base + 4 * static_cast<int64_t>(rpp[rr]); k < nnz_base + 4 * static_cast<int64_t>(rpp[rr + 1]); ++k) {
-              const int32_t j = P.col16_used ? P.col16[static_cast<size_t>(k)] : P.col32[static_cast<size_t>(k)];
-              if (colsum[j] == 0.0) touched.push_back(j);
-              colsum[j] += P.val[static_cast<size_t>(k)];
-            }
-          }
-          for (int32_t j : touched) {
-            cm = std::max(cm, colsum[j]);
-            colsum[j] = 0.0;
-          }
-          touched.clear();
-          t.wmax = round_up(wm);
-          t.pmax = round_up(pm);
-          t.cmax = round_up(cm);
+        for (Tile t : r.tiles) {
           t.part_off = P.part_total;
           P.part_total += n;
           P.tiles.push_back(t);
-          r = r1;
         }
         sc.tile_end = static_cast<int32_t>(P.tiles.size());
         P.scen.push_back(sc);
         P.scen_nnz.push_back(A.nnz);
-        nnz_base += static_cast<int64_t>(off) * 4;
-        row_base += rows;
-        rp_base += rows + 1;
+        pt.fzero += r.fzero;
+        pt.fconst += r.fconst;
+        for (int j = 0; j < n; ++j) {
+          P.gdiag.push_back(static_cast<float>(r.gdiag[j]));
+          P.b.push_back(static_cast<float>(r.b[j]));
+          g0[j] += 2.0 * r.b[j];
+          gsum += r.gdiag[j];
+        }
         P.vec_total += n;
       }
       const double mean_diag = gsum / (static_cast<double>(N) * n);
@@ -259,7 +335,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       if (o.precond) {
         for (int s = 0; s < N; ++s)
           for (int j = 0; j < n; ++j) {
-            const double d = gdiag[s][j] + 0.5 * rho;
+            const double d = so[k0 + s].gdiag[j] + 0.5 * rho;
             P.dinv.push_back(d > 0 ? static_cast<float>(1.0 / d) : 1.0f);
           }
       }
@@ -272,18 +348,11 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       P.pat.push_back(pt);
       P.zvec_total += n;
     }
+    P.nnz_total = nnz_base;
+    P.rows_total = row_base;
   } catch (const std::bad_alloc&) {
     if (msg) *msg = "host allocation failed while packing";
     return ADMM_E_OOM;
-  }
-  // trailing zero chunks so that no chunk load can leave the arrays
-  for (int k = 0; k < 256; ++k) {
-    P.val.push_back(0.0f);
-    if (P.col16_used)
-      P.col16.push_back(0);
-    else
-      P.col32.push_back(0);
-    if (lp) P.val_lp.push_back(0);
   }
   // the column reductions address tile t's partials as first_tile_offset + (t - first) * n
   for (const Pat& pt : P.pat)
@@ -292,8 +361,6 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         if (msg) *msg = "internal: tile partials are not contiguous";
         return ADMM_E_STATE;
       }
-  P.nnz_total = nnz_base;
-  P.rows_total = row_base;
   return ADMM_OK;
 }
 

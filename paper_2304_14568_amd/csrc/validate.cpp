@@ -1,7 +1,11 @@
 // Host-side validation of admm_problem (no device calls; usable without a GPU).
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "../../include/admmbb.h"
 #include "host.h"
@@ -45,33 +49,56 @@ admm_status validate_problem(const admm_problem* p, std::string* msg) {
       return fail(msg, ADMM_E_NONFINITE, "bound of spot %lld is NaN or lb is infinite", j);
     if (lo > hi) return fail(msg, ADMM_E_ARG, "lb > ub at spot %lld", j);
   }
-  for (int s = 0; s < p->num_scen; ++s) {
+  // scenarios are checked by parallel host threads; the first failing
+  // scenario in index order decides the status and message
+  const int N = p->num_scen;
+  std::vector<admm_status> st(N, ADMM_OK);
+  std::vector<std::string> ms(N);
+  auto check_scen = [&](int s) -> admm_status {
+    std::string* msg1 = &ms[s];
     const admm_csr& A = p->A[s];
     if (!A.row_ptr || (A.nnz > 0 && (!A.col || !A.val)))
-      return fail(msg, ADMM_E_ARG, "scenario %lld: NULL CSR array", s);
+      return fail(msg1, ADMM_E_ARG, "scenario %lld: NULL CSR array", s);
     if (A.nnz < 0 || A.nnz > (int64_t)0xFFFFFFFFLL)
-      return fail(msg, ADMM_E_CSR, "scenario %lld: nnz=%lld outside 0..2^32-1", s, A.nnz);
-    if (!std::isfinite(A.prob)) return fail(msg, ADMM_E_NONFINITE, "scenario %lld: probability not finite", s);
-    if (A.prob < 0) return fail(msg, ADMM_E_NEGATIVE, "scenario %lld: probability < 0", s);
-    if (A.row_ptr[0] != 0) return fail(msg, ADMM_E_CSR, "scenario %lld: row_ptr[0] != 0", s);
+      return fail(msg1, ADMM_E_CSR, "scenario %lld: nnz=%lld outside 0..2^32-1", s, A.nnz);
+    if (!std::isfinite(A.prob)) return fail(msg1, ADMM_E_NONFINITE, "scenario %lld: probability not finite", s);
+    if (A.prob < 0) return fail(msg1, ADMM_E_NEGATIVE, "scenario %lld: probability < 0", s);
+    if (A.row_ptr[0] != 0) return fail(msg1, ADMM_E_CSR, "scenario %lld: row_ptr[0] != 0", s);
     if (A.row_ptr[p->m] != A.nnz)
-      return fail(msg, ADMM_E_CSR, "scenario %lld: row_ptr[m]=%lld != nnz=%lld", s, A.row_ptr[p->m], A.nnz);
+      return fail(msg1, ADMM_E_CSR, "scenario %lld: row_ptr[m]=%lld != nnz=%lld", s, A.row_ptr[p->m], A.nnz);
     for (int i = 0; i < p->m; ++i) {
       const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
-      if (e < b) return fail(msg, ADMM_E_CSR, "scenario %lld: row_ptr decreases at row %lld", s, i);
-      if (e - b > p->n) return fail(msg, ADMM_E_CSR, "scenario %lld: row %lld has more than n entries", s, i);
+      if (e < b) return fail(msg1, ADMM_E_CSR, "scenario %lld: row_ptr decreases at row %lld", s, i);
+      if (e - b > p->n) return fail(msg1, ADMM_E_CSR, "scenario %lld: row %lld has more than n entries", s, i);
       int32_t prev = -1;
       for (int64_t k = b; k < e; ++k) {
         const int32_t c = A.col[k];
-        if (c < 0 || c >= p->n) return fail(msg, ADMM_E_CSR, "scenario %lld: column %lld out of range at row %lld", s, c, i);
-        if (c <= prev) return fail(msg, ADMM_E_CSR, "scenario %lld: columns not increasing in row %lld", s, i);
+        if (c < 0 || c >= p->n)
+          return fail(msg1, ADMM_E_CSR, "scenario %lld: column %lld out of range at row %lld", s, c, i);
+        if (c <= prev) return fail(msg1, ADMM_E_CSR, "scenario %lld: columns not increasing in row %lld", s, i);
         prev = c;
         const float v = A.val[k];
-        if (!std::isfinite(v)) return fail(msg, ADMM_E_NONFINITE, "scenario %lld: non-finite value at row %lld", s, i);
-        if (v < 0) return fail(msg, ADMM_E_NEGATIVE, "scenario %lld: negative value at row %lld", s, i);
+        if (!std::isfinite(v)) return fail(msg1, ADMM_E_NONFINITE, "scenario %lld: non-finite value at row %lld", s, i);
+        if (v < 0) return fail(msg1, ADMM_E_NEGATIVE, "scenario %lld: negative value at row %lld", s, i);
       }
     }
-  }
+    return ADMM_OK;
+  };
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = static_cast<int>(std::min<unsigned>(hw, static_cast<unsigned>(N)));
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    for (int s = next++; s < N; s = next++) st[s] = check_scen(s);
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+  for (int s = 0; s < N; ++s)
+    if (st[s] != ADMM_OK) {
+      if (msg) *msg = ms[s];
+      return st[s];
+    }
   return ADMM_OK;
 }
 
