@@ -532,7 +532,7 @@ admm_status admm_default_options(admm_options* o) {
   o->tile_nnz = 0;
   o->pass_threads = 0;
   o->pass_unroll = 0;
-  o->xupdate = ADMM_XUPDATE_CG;
+  o->xupdate = ADMM_XUPDATE_AUTO;
   o->stream = nullptr;
   return ADMM_OK;
 }

@@ -137,7 +137,8 @@ def test_bad_options_rejected_before_device_work():
     A = _codes()
     P = _tiny()
     for kw in (dict(cg_max=0), dict(cg_max=65), dict(z_mode=2), dict(lds_acc=3), dict(pass_threads=128),
-               dict(pass_unroll=3), dict(max_iter=-1), dict(check_every=0), dict(precision=7)):
+               dict(pass_unroll=3), dict(max_iter=-1), dict(check_every=0), dict(precision=7),
+               dict(xupdate=2)):
         with pytest.raises(A.AdmmError) as e:
             A.Solver(P, **kw)
         assert e.value.code == -1, kw
@@ -162,3 +163,4 @@ def test_default_options_documented_values():
     assert o.obj_rel_tol == 1e-5 and o.eps_abs == 1e-6 and o.eps_rel == 1e-6
     assert o.bb == 1 and o.z_mode == 0 and o.bb_clamp == 0.0
     assert o.cg_max == 8 and o.max_iter == 1000
+    assert o.xupdate == -1  # automatic choice between the dense and the CG x-update

@@ -94,9 +94,10 @@ def test_gradient_objective_parity(tiny, small):
                 assert abs(S.objective(x32) - fr) <= 1e-6 * fr
 
 
-def test_admm_solve_tiny(tiny):
+@pytest.mark.parametrize("xupdate", ["cg", "dense"])
+def test_admm_solve_tiny(tiny, xupdate):
     P, W, xs, fs = tiny
-    with _solver(P, max_iter=3000) as S:
+    with _solver(P, max_iter=3000, xupdate=xupdate) as S:
         zs, info, st = S.solve()
         z = zs[0]
         assert st == 0, info
@@ -106,9 +107,10 @@ def test_admm_solve_tiny(tiny):
         assert S.kkt(z) <= 1e-3
 
 
-def test_admm_solve_hn_small(small):
+@pytest.mark.parametrize("xupdate", ["cg", "dense"])
+def test_admm_solve_hn_small(small, xupdate):
     P, W, xs, fs = small
-    with _solver(P, max_iter=3000) as S:
+    with _solver(P, max_iter=3000, xupdate=xupdate) as S:
         zs, info, st = S.solve()
         z = zs[0]
         assert st == 0, info
@@ -130,7 +132,7 @@ def test_fixed_point_pass_is_deterministic(small):
     """With 64-bit fixed-point column accumulators every sum in an iteration is
     order-independent or in a fixed order, so two runs agree bit for bit."""
     P = small[0]
-    with _solver(P, lds_acc=2) as S:
+    with _solver(P, lds_acc=2, xupdate="cg") as S:
         rng = np.random.default_rng(11)
         v = rng.normal(size=P.n).astype(np.float32)
         a = S.normal_apply(v, 3)

@@ -26,17 +26,18 @@ def patients():
     return [(P,) + _fstar(P) for P in Ps]
 
 
-def test_batched_patients_match_oracle_and_single(patients):
+@pytest.mark.parametrize("xupdate", ["cg", "dense"])
+def test_batched_patients_match_oracle_and_single(patients, xupdate):
     import paper_2304_14568_amd as A
     Ps = [p[0] for p in patients]
-    with A.Solver(Ps, max_iter=3000, tile_nnz=16384) as S:
+    with A.Solver(Ps, max_iter=3000, tile_nnz=16384, xupdate=xupdate) as S:
         zs, infos, st = S.solve()
         assert st == 0, infos
     for (P, W, xs, fs), z, info in zip(patients, zs, infos):
         f = wls.objective(W, z)
         assert abs(f - fs) <= 1e-5 * fs, (P.name, f, fs)
         assert abs(info["obj"] - f) <= 1e-6 * fs
-        with A.Solver(P, max_iter=3000, tile_nnz=16384) as S1:
+        with A.Solver(P, max_iter=3000, tile_nnz=16384, xupdate=xupdate) as S1:
             z1, i1, _ = S1.solve()
         assert abs(wls.objective(W, z1[0]) - f) <= 2e-6 * fs
 
@@ -48,7 +49,7 @@ def test_reduced_precision_reaches_fp32_objective(patients, precision):
     the fp32 problem's and the objective meets the same 1e-5 bar."""
     import paper_2304_14568_amd as A
     P, W, xs, fs = patients[0]
-    with A.Solver(P, max_iter=3000, precision=precision) as S:
+    with A.Solver(P, max_iter=3000, precision=precision, xupdate="cg") as S:
         zs, info, st = S.solve()
         assert st == 0, info
         f = wls.objective(W, zs[0])
@@ -74,7 +75,7 @@ def test_large_spot_count_uses_extended_lds():
     assert 12 * P.n > 65536
     W = wls.from_problem(P)
     rng = np.random.default_rng(4)
-    with A.Solver(P, max_iter=400, lds_acc=2) as S:
+    with A.Solver(P, max_iter=400, lds_acc=2, xupdate="cg") as S:
         for s in range(P.num_scen):
             v = rng.normal(size=P.n).astype(np.float32)
             got = S.normal_apply(v, s)
@@ -93,7 +94,7 @@ def test_large_spot_count_uses_extended_lds():
 def test_checkpoint_resume_is_exact(patients):
     import paper_2304_14568_amd as A
     P = patients[0][0]
-    with A.Solver(P, lds_acc=2, use_graph=0) as S:
+    with A.Solver(P, lds_acc=2, use_graph=0, xupdate="cg") as S:
         S.iterate(7)
         saved = S.get_state()
         S.iterate(9)
@@ -103,18 +104,19 @@ def test_checkpoint_resume_is_exact(patients):
         zb = S.z()
         assert np.array_equal(za, zb)
     # resume in a fresh context
-    with A.Solver(P, lds_acc=2, use_graph=0) as S2:
+    with A.Solver(P, lds_acc=2, use_graph=0, xupdate="cg") as S2:
         S2.set_state(saved)
         S2.iterate(9)
         assert np.array_equal(S2.z(), za)
 
 
-def test_graph_replay_matches_direct_launches(patients):
+@pytest.mark.parametrize("xupdate", ["cg", "dense"])
+def test_graph_replay_matches_direct_launches(patients, xupdate):
     import paper_2304_14568_amd as A
     P = patients[0][0]
     out = []
     for g in (0, 1):
-        with A.Solver(P, lds_acc=2, use_graph=g) as S:
+        with A.Solver(P, lds_acc=2, use_graph=g, xupdate=xupdate) as S:
             S.iterate(12)
             z1 = S.z()
             S.reset()

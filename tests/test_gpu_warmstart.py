@@ -97,7 +97,8 @@ def test_spot_features_parity():
     _close(got, ref, 1e-4, 1e-6)
 
 
-def test_dual_consistent_warm_start_at_optimum():
+@pytest.mark.parametrize("xupdate", ["cg", "dense"])
+def test_dual_consistent_warm_start_at_optimum(xupdate):
     """Restarting at x* with y_s = -grad f_s(x*) leaves every x-update at x*
     and the consensus step at x*: the stop rule holds within a few iterations."""
     import paper_2304_14568_amd as A
@@ -106,7 +107,7 @@ def test_dual_consistent_warm_start_at_optimum():
     Hm, g0, _ = wls.quadratic_form(W)
     xs, _ = exact.active_set(W, H=Hm, g0=g0)
     fs = wls.objective(W, xs)
-    with A.Solver(P, max_iter=3000) as S:
+    with A.Solver(P, max_iter=3000, xupdate=xupdate) as S:
         zs0, info0, st0 = S.solve()
         it_zero = info0[0]["iter"]
         S.warm_start(0, xs, dual_init=True)
