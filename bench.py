@@ -156,10 +156,11 @@ def main():
 
     if xmode == "dense":
         # x-update roofline (k_xsym): every launch reads each scenario's packed fp32
-        # inverse once (upper 64 x 64 tiles of M_s, 16 KiB each) and its right-hand side
+        # inverse once (upper 64 x 64 tiles of M_s, 16 KiB each) and its fp64
+        # right-hand side
         nb = (P.n + 63) // 64
         tiles = nb * (nb + 1) // 2
-        bytes_per_launch = float(P.num_scen * (tiles * 64 * 64 * 4 + 4 * P.n))
+        bytes_per_launch = float(P.num_scen * (tiles * 64 * 64 * 4 + 8 * P.n))
         launches = tm["pass_launches"]
         achieved = bytes_per_launch / (tm["pass_ms"] * 1e-3) / 1e9 if tm["pass_ms"] > 0 else 0.0
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

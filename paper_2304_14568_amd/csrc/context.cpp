@@ -78,7 +78,8 @@ struct admm_ctx {
   bool dense = false;
   double *d_G = nullptr, *d_Aw = nullptr, *d_Gp = nullptr, *d_g0 = nullptr;
   double *d_Pb = nullptr, *d_U = nullptr, *d_R = nullptr, *d_fpart = nullptr;
-  float *d_Mp = nullptr, *d_xpart = nullptr;
+  float* d_Mp = nullptr;
+  double *d_xpart = nullptr, *d_c64 = nullptr, *d_b64 = nullptr;
   double* d_rw64 = nullptr;
   XJob *d_xjobs = nullptr, *d_rjobs = nullptr, *d_fjobs = nullptr;
   int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
@@ -173,6 +174,8 @@ struct admm_ctx {
     a.prm.trace_cap = trace_cap;
     a.prm.num_pat = P;
     a.fpart = dense ? d_fpart : nullptr;
+    a.c64 = d_c64;
+    a.b64 = d_b64;
     return a;
   }
 
@@ -246,9 +249,9 @@ struct admm_ctx {
     if (dense) {
       const FactorArgs f = fargs();
       if (with_events)
-        launch_xsym(f, d_r, n_xjobs, stream, ev[0], ev[1]);
+        launch_xsym(f, d_c64, n_xjobs, stream, ev[0], ev[1]);
       else
-        launch_xsym(f, d_r, n_xjobs, stream);
+        launch_xsym(f, d_c64, n_xjobs, stream);
       launch_xsym_reduce(f, d_x, n_rjobs, stream);
       launch_zres(va, NPB, stream);
       launch_body_scalars(va, stream);
@@ -618,7 +621,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
         // set-up: G and the sweep matrix (fp64, full); every iteration: packed fp32
         // inverses, packed fp64 sum of G, tile partials; U, R panels
         need += npad * npad * 16 * static_cast<int64_t>(pt.num_scen) +
-                tiles * 4096 * (4 * static_cast<int64_t>(pt.num_scen) + 8) + tiles * 512 * pt.num_scen +
+                tiles * 4096 * (4 * static_cast<int64_t>(pt.num_scen) + 8) + tiles * 1024 * pt.num_scen +
                 2 * 8 * 64 * npad * pt.num_scen;
       }
       size_t free_b = 0, total_b = 0;
@@ -665,7 +668,9 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       c->d_G = c->alloc<double>(static_cast<size_t>(off));
       c->d_Aw = c->alloc<double>(static_cast<size_t>(off));
       c->d_Mp = c->alloc<float>(static_cast<size_t>(moff));
-      c->d_xpart = c->alloc<float>(static_cast<size_t>(moff / 4096) * 128);
+      c->d_xpart = c->alloc<double>(static_cast<size_t>(moff / 4096) * 128);
+      c->d_c64 = c->alloc<double>(static_cast<size_t>(H.vec_total));
+      c->d_b64 = c->upload(H.b64);
       c->d_Gp = c->alloc<double>(static_cast<size_t>(goff));
       c->d_Pb = c->alloc<double>(static_cast<size_t>(c->G) * 64 * 64);
       c->d_U = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);

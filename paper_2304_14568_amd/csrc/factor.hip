@@ -274,10 +274,14 @@ __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, 
 
 // One packed tile T = M_s[I, J] (I <= J) of a scenario: a = T c_J and, off the
 // diagonal, b = T^T c_I (the tile's contribution to the rows of block J).
-// Thread t holds row t/4, columns 16 (t%4) .. +15 (four float4 loads).
-__global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const float* __restrict__ c) {
-  __shared__ float red[kFb][kFb + 1];
-  __shared__ float cI[kFb], cJ[kFb];
+// Thread t holds row t/4, columns 16 (t%4) .. +15 (four float4 loads).  The
+// right-hand side and all sums are fp64: the inverse has entries of both signs
+// and |M| |c| exceeds |M c| by two orders of magnitude, so fp32 sums would put
+// a floor of about 1e-5 relative under every x-update; the fp32 storage of M
+// itself contributes about 1e-6.
+__global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __restrict__ c) {
+  __shared__ float tl[kFb][kFb + 1];  // the tile again, read by columns for T^T c_I
+  __shared__ double cI[kFb], cJ[kFb];
   const XJob job = f.xjobs[blockIdx.x];
   const Scen sc = f.scen[job.g];
   if (f.ps[sc.patient].stopped) return;
@@ -286,64 +290,71 @@ __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const float* __restr
   const int64_t t = tile_index(I, J, pt.nbk);
   const float4* T = reinterpret_cast<const float4*>(f.Mp + sc.mpack_off + t * kFb * kFb);
   const int tid = threadIdx.x;
+  const int i = tid >> 2, q = tid & 3;
   // the tile's 16 KB, in flight before the vectors arrive
   float4 m[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) m[k] = T[tid * 4 + k];
   if (tid < kFb) {
     const int jc = J * kFb + tid, ic = I * kFb + tid;
-    cJ[tid] = jc < sc.n ? c[sc.vec_base + jc] : 0.0f;
-    cI[tid] = ic < sc.n ? c[sc.vec_base + ic] : 0.0f;
+    cJ[tid] = jc < sc.n ? c[sc.vec_base + jc] : 0.0;
+    cI[tid] = ic < sc.n ? c[sc.vec_base + ic] : 0.0;
+  }
+  if (I != J) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j0 = 16 * q + 4 * k;
+      tl[i][j0 + 0] = m[k].x;
+      tl[i][j0 + 1] = m[k].y;
+      tl[i][j0 + 2] = m[k].z;
+      tl[i][j0 + 3] = m[k].w;
+    }
   }
   __syncthreads();
-  const int i = tid >> 2, q = tid & 3;
-  float a = 0.0f;
-  const float ci = cI[i];
+  double a = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int j0 = 16 * q + 4 * k;
-    a = fmaf(m[k].x, cJ[j0 + 0], a);
-    a = fmaf(m[k].y, cJ[j0 + 1], a);
-    a = fmaf(m[k].z, cJ[j0 + 2], a);
-    a = fmaf(m[k].w, cJ[j0 + 3], a);
-    red[i][j0 + 0] = m[k].x * ci;
-    red[i][j0 + 1] = m[k].y * ci;
-    red[i][j0 + 2] = m[k].z * ci;
-    red[i][j0 + 3] = m[k].w * ci;
+    a = fma(static_cast<double>(m[k].x), cJ[j0 + 0], a);
+    a = fma(static_cast<double>(m[k].y), cJ[j0 + 1], a);
+    a = fma(static_cast<double>(m[k].z), cJ[j0 + 2], a);
+    a = fma(static_cast<double>(m[k].w), cJ[j0 + 3], a);
   }
   a += __shfl_xor(a, 1, 64);
   a += __shfl_xor(a, 2, 64);
-  float* out = f.xpart + (sc.mpack_off / (kFb * kFb) + t) * (2 * kFb);
+  double* out = f.xpart + (sc.mpack_off / (kFb * kFb) + t) * (2 * kFb);
   if (q == 0) out[i] = a;
   if (I == J) return;
-  __syncthreads();
-  if (tid < kFb) {
-    float bsum = 0.0f;
-    for (int r = 0; r < kFb; ++r) bsum += red[r][tid];
-    out[kFb + tid] = bsum;
-  }
+  // b_j over rows 16 q .. 16 q + 15 (thread: column j = tid / 4, row quarter q)
+  double b = 0.0;
+  const int j = i;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) b = fma(static_cast<double>(tl[16 * q + r][j]), cI[16 * q + r], b);
+  b += __shfl_xor(b, 1, 64);
+  b += __shfl_xor(b, 2, 64);
+  if (q == 0) out[kFb + j] = b;
 }
 
 // x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
 // (T_JI^T c_J).  Wave w adds the blocks J = w, w + 4, ...; the four partial
 // sums are then added in a fixed order.
 __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
-  __shared__ float part[4][kFb];
+  __shared__ double part[4][kFb];
   const XJob job = f.rjobs[blockIdx.x];
   const Scen sc = f.scen[job.g];
   if (f.ps[sc.patient].stopped) return;
   const Pat pt = f.pat[sc.patient];
   const int I = job.ij, nb = pt.nbk;
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
-  const float* base = f.xpart + (sc.mpack_off / (kFb * kFb)) * (2 * kFb);
-  float s = 0.0f;
+  const double* base = f.xpart + (sc.mpack_off / (kFb * kFb)) * (2 * kFb);
+  double s = 0.0;
   for (int J = w; J < nb; J += 4)
     s += (J < I) ? base[tile_index(J, I, nb) * (2 * kFb) + kFb + i] : base[tile_index(I, J, nb) * (2 * kFb) + i];
   part[w][i] = s;
   __syncthreads();
   if (w == 0) {
     const int row = I * kFb + i;
-    if (row < sc.n) x[sc.vec_base + row] = (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
+    if (row < sc.n) x[sc.vec_base + row] = static_cast<float>((part[0][i] + part[1][i]) + (part[2][i] + part[3][i]));
   }
 }
 
@@ -367,7 +378,7 @@ __global__ __launch_bounds__(kColBlock) void k_fhead(VecArgs a) {
       a.y[vi] = yv;
     }
     const float zj = a.z[pt.zvec_base + j];
-    a.r[vi] = static_cast<float>(static_cast<double>(a.b[vi]) + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv));
+    a.c64[vi] = a.b64[vi] + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv);
     yy = static_cast<double>(yv) * yv;
   }
   yy = wave_sum_d(yy);
@@ -452,7 +463,7 @@ void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStrea
   hipLaunchKernelGGL(k_sweep_store, dim3(static_cast<unsigned>(nb), nscen), dim3(256), 0, st, f, patient, npad);
 }
 
-void launch_xsym(const FactorArgs& f, const float* c, int njobs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (njobs <= 0) return;
   if (e0 != nullptr)
     hipExtLaunchKernelGGL(k_xsym, dim3(njobs), dim3(256), 0, st, e0, e1, 0, f, c);

@@ -30,6 +30,7 @@ struct Packed {
   std::vector<double> rw64;       // c_s w_i per sorted row in fp64 (Gram matrices of the dense x-update)
   std::vector<int32_t> rorig;
   std::vector<float> b;           // A_s^T c_s W p per scenario (stacked)
+  std::vector<double> b64;        // the same in fp64 (dense x-update right-hand sides)
   std::vector<float> dinv;        // Jacobi inverse diagonal (stacked), filled when requested
   std::vector<float> gdiag;       // (A_s^T c_s W A_s)_jj per scenario (stacked)
   std::vector<double> gdiag_mean; // per patient: mean over scenarios and spots of (A_s^T c_s W A_s)_jj

@@ -173,6 +173,8 @@ struct VecArgs {
   float* out;              // RMAT / NORMAL output vector (n)
   double rho_out;          // NORMAL: diagonal shift rho/2 * v added when > 0
   const double* fpart;     // dense x-update: objective partials per workgroup (nullptr: tile partials)
+  double* c64;             // dense x-update: right-hand sides c_s in fp64 (stacked)
+  const double* b64;       // dense x-update: A_s^T c_s W p in fp64 (stacked)
   AlgoParams prm;
   IterRecord* trace;
 };
@@ -198,7 +200,7 @@ struct FactorArgs {
   double* P;          // per scenario: 64 x 64 pivot-block inverse
   double* U;          // per scenario: 64 x npmax column panel, transposed
   double* R;          // per scenario: 64 x npmax row panel
-  float* xpart;       // per packed tile of every scenario: T c_J (64) and T^T c_I (64)
+  double* xpart;      // per packed tile of every scenario: T c_J (64) and T^T c_I (64), fp64
   const XJob* xjobs;  // x-update: one per packed tile of every scenario
   const XJob* rjobs;  // x-update reduction: one per block row of every scenario
   const XJob* fjobs;  // objective: one per packed tile of every patient
@@ -233,7 +235,7 @@ void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G,
 void launch_gram_finish(FactorArgs f, int patient, int nscen, int npad, int n, double rho, hipStream_t st);
 void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st);
 void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStream_t st);
-void launch_xsym(const FactorArgs& f, const float* c, int njobs, hipStream_t st, hipEvent_t e0 = nullptr,
+void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st);
 void launch_fhead(const VecArgs& a, int nblk, hipStream_t st);

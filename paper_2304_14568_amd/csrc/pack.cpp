@@ -324,6 +324,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         for (int j = 0; j < n; ++j) {
           P.gdiag.push_back(static_cast<float>(r.gdiag[j]));
           P.b.push_back(static_cast<float>(r.b[j]));
+          P.b64.push_back(r.b[j]);
           g0[j] += 2.0 * r.b[j];
           gsum += r.gdiag[j];
         }
