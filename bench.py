@@ -16,6 +16,7 @@ fused-pass roofline, and the FP64 CPU oracle timed on this host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,6 +30,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-5 obj (s) & ADMM iters/s, 13 scen.; SpMV HBM GB/s vs ~8 TB/s"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per k_xsym launch on this workload, from rocprofv3 FETCH_SIZE (x 2.0) and
+# WRITE_SIZE (x 1.0) runs (profiles/k_xsym_hn13_fp32.md); valid only for the kernel
+# source they were taken with
+XSYM_TRAFFIC = {"source_sha256_16": "b4e61a278e73f423", "fetch_bytes": 119467.58 * 1024 * 2.0,
+                "write_bytes": 14358.5 * 1024 * 1.0}
 
 
 def pass_bytes(P, precision: str) -> np.ndarray:
@@ -163,8 +169,13 @@ def main():
         bytes_per_launch = float(P.num_scen * (tiles * 64 * 64 * 4 + 8 * P.n))
         launches = tm["pass_launches"]
         achieved = bytes_per_launch / (tm["pass_ms"] * 1e-3) / 1e9 if tm["pass_ms"] > 0 else 0.0
+        traffic = None
+        src = os.path.join(ROOT, "paper_2304_14568_amd", "csrc", "factor.hip")
+        if (args.seed == 0 and os.path.exists(src) and
+                hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == XSYM_TRAFFIC["source_sha256_16"]):
+            traffic = XSYM_TRAFFIC["fetch_bytes"] + XSYM_TRAFFIC["write_bytes"]
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_xsym (x_s = M_s c_s over the packed upper tiles of the cached fp32 inverses)",
                 "avg_launch_ms": tm["pass_ms"], "launches": launches, "bytes_per_launch": bytes_per_launch}
     else:

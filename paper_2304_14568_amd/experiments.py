@@ -71,7 +71,7 @@ def _admm_run(P, f_ref, xupdate: str, stream):
     return out
 
 
-def _pgd_run(P, f_ref, stream, max_doublings: int = 14):
+def _pgd_run(P, f_ref, stream, max_doublings: int = 10):
     S = Solver(P, xupdate="cg", stream=stream)
     _sync()
     t0 = time.perf_counter()

@@ -119,3 +119,22 @@ def test_dual_consistent_warm_start_at_optimum(xupdate):
         S.warm_start(0, xs, dual_init=False)
         zs, info, st = S.solve()
         assert abs(wls.objective(W, zs[0]) - fs) <= 1e-5 * fs
+
+
+def test_trained_warm_start_on_a_held_out_patient():
+    """The committed network on a patient outside its training seeds: its z0 is
+    feasible and much better than zero, and the dual-consistent restart from it
+    meets the acceptance rule (objective within 1e-5 of the zero-initialised solve)."""
+    import paper_2304_14568_amd as A
+    from paper_2304_14568_amd import warmstart as W
+    P = synth.hn_full(3001)
+    ws = W.WarmStart.load()
+    with A.Solver(P, max_iter=3000) as S:
+        z_ref, i_ref, _ = W.solve_zero(S)
+        f_ref = i_ref["obj"]
+        z0, rho = ws.predict(S, P)
+        assert np.all(z0 >= P.lb) and np.all(z0 <= P.ub)
+        assert S.objective(z0) < 0.5 * S.objective(np.zeros(P.n))
+        assert rho > 0
+        z_w, i_w, _, _, _, _ = W.solve_warm(S, P, ws, f_ref=f_ref)
+        assert i_w["obj"] - f_ref <= 1e-5 * f_ref
