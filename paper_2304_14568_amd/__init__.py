@@ -81,6 +81,13 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                           f"python -m paper_2304_14568_amd.build")
+    # With PyTorch installed, its HIP runtime is loaded first so that torch and
+    # the library share one runtime in the process (a torch stream can then be
+    # handed to the library, and neither initialises the device behind the other).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
