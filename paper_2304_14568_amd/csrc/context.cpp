@@ -81,7 +81,8 @@ struct admm_ctx {
   float* d_Mp = nullptr;
   double *d_xpart = nullptr, *d_c64 = nullptr, *d_b64 = nullptr;
   double* d_rw64 = nullptr;
-  XJob *d_xjobs = nullptr, *d_rjobs = nullptr, *d_fjobs = nullptr;
+  XJob *d_rjobs = nullptr, *d_fjobs = nullptr;
+  XTile* d_xtiles = nullptr;
   int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
   std::vector<double> factored_rho;  // per patient: penalty of the cached inverse
   double factor_ms = 0.0;            // time of the last set-up of the cached inverses
@@ -193,7 +194,8 @@ struct admm_ctx {
     f.U = d_U;
     f.R = d_R;
     f.xpart = d_xpart;
-    f.xjobs = d_xjobs;
+    f.xtiles = d_xtiles;
+    f.nxtiles = n_xjobs;
     f.rjobs = d_rjobs;
     f.fjobs = d_fjobs;
     f.fpart = d_fpart;
@@ -611,7 +613,8 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->trace_cap = std::max(1, o.max_iter + 2);
 
     // dense x-update: sizes, offsets and work lists (before the tables go to the device)
-    std::vector<XJob> xjobs, rjobs, fjobs;
+    std::vector<XJob> rjobs, fjobs;
+    std::vector<XTile> xtiles;
     {
       int64_t need = 0;
       bool fits_n = true;
@@ -658,11 +661,22 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
           sc.mpack_off = moff;
           moff += tiles * 4096;
           for (int I = 0; I < pt.nbk; ++I)
-            for (int J = I; J < pt.nbk; ++J) xjobs.push_back(XJob{g, I * 65536 + J});
+            for (int J = I; J < pt.nbk; ++J) {
+              XTile xt{};
+              const int64_t t = static_cast<int64_t>(I) * pt.nbk - static_cast<int64_t>(I) * (I - 1) / 2 + (J - I);
+              xt.moff = sc.mpack_off + t * 4096;
+              xt.vbase = sc.vec_base;
+              xt.pidx = sc.mpack_off / 4096 + t;
+              xt.n = pt.n;
+              xt.patient = p;
+              xt.I = I;
+              xt.J = J;
+              xtiles.push_back(xt);
+            }
           for (int I = 0; I < pt.nbk; ++I) rjobs.push_back(XJob{g, I});
         }
       }
-      c->n_xjobs = static_cast<int>(xjobs.size());
+      c->n_xjobs = static_cast<int>(xtiles.size());
       c->n_rjobs = static_cast<int>(rjobs.size());
       c->n_fjobs = static_cast<int>(fjobs.size());
       c->d_G = c->alloc<double>(static_cast<size_t>(off));
@@ -676,7 +690,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       c->d_U = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
       c->d_R = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
       c->d_fpart = c->alloc<double>(fjobs.size());
-      c->d_xjobs = c->upload(xjobs);
+      c->d_xtiles = c->upload(xtiles);
       c->d_rjobs = c->upload(rjobs);
       c->d_fjobs = c->upload(fjobs);
       std::vector<double> g0all(static_cast<size_t>(H.zvec_total));
@@ -730,7 +744,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->d_part = c->alloc<float>(static_cast<size_t>(H.part_total));
     c->d_objpart = c->alloc<double>(c->T);
     c->d_bpart = c->alloc<double>(static_cast<size_t>(c->NB) * 8);
-    c->d_bpartp = c->alloc<double>(static_cast<size_t>(c->NPB) * 8);
+    c->d_bpartp = c->alloc<double>(static_cast<size_t>(c->NPB) * 4 * 8);
     c->d_scratch = c->alloc<double>(std::max(64, (H.nmax + kThreads - 1) / kThreads + 8));
     c->d_act = c->alloc<uint8_t>(static_cast<size_t>(c->G) * kRing);
     c->d_rz = c->alloc<double>(static_cast<size_t>(c->G) * kRing);

@@ -272,35 +272,33 @@ __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, 
 // per-iteration kernels
 // ---------------------------------------------------------------------------
 
-// One packed tile T = M_s[I, J] (I <= J) of a scenario: a = T c_J and, off the
-// diagonal, b = T^T c_I (the tile's contribution to the rows of block J).
+// One packed tile T = M_s[I, J] (I <= J) per workgroup: a = T c_J and, off
+// the diagonal, b = T^T c_I (the tile's contribution to the rows of block J).
 // Thread t holds row t/4, columns 16 (t%4) .. +15 (four float4 loads).  The
-// right-hand side and all sums are fp64: the inverse has entries of both signs
-// and |M| |c| exceeds |M c| by two orders of magnitude, so fp32 sums would put
-// a floor of about 1e-5 relative under every x-update; the fp32 storage of M
-// itself contributes about 1e-6.
+// tile table entry carries every address, so the tile load depends on one
+// table read only.  The right-hand side and all sums are fp64: the inverse
+// has entries of both signs and |M| |c| exceeds |M c| by two orders of
+// magnitude, so fp32 sums would put a floor of about 1e-5 relative under every
+// x-update; the fp32 storage of M itself contributes about 1e-6.
 __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __restrict__ c) {
   __shared__ float tl[kFb][kFb + 1];  // the tile again, read by columns for T^T c_I
   __shared__ double cI[kFb], cJ[kFb];
-  const XJob job = f.xjobs[blockIdx.x];
-  const Scen sc = f.scen[job.g];
-  if (f.ps[sc.patient].stopped) return;
-  const Pat pt = f.pat[sc.patient];
-  const int I = job.ij >> 16, J = job.ij & 0xffff;
-  const int64_t t = tile_index(I, J, pt.nbk);
-  const float4* T = reinterpret_cast<const float4*>(f.Mp + sc.mpack_off + t * kFb * kFb);
+  const XTile tj = f.xtiles[blockIdx.x];
   const int tid = threadIdx.x;
   const int i = tid >> 2, q = tid & 3;
-  // the tile's 16 KB, in flight before the vectors arrive
+  // the tile's 16 KB, in flight before anything else
+  const float4* T = reinterpret_cast<const float4*>(f.Mp + tj.moff);
   float4 m[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) m[k] = T[tid * 4 + k];
+  if (f.ps[tj.patient].stopped) return;
   if (tid < kFb) {
-    const int jc = J * kFb + tid, ic = I * kFb + tid;
-    cJ[tid] = jc < sc.n ? c[sc.vec_base + jc] : 0.0;
-    cI[tid] = ic < sc.n ? c[sc.vec_base + ic] : 0.0;
+    const int jc = tj.J * kFb + tid, ic = tj.I * kFb + tid;
+    cJ[tid] = jc < tj.n ? c[tj.vbase + jc] : 0.0;
+    cI[tid] = ic < tj.n ? c[tj.vbase + ic] : 0.0;
   }
-  if (I != J) {
+  const bool offdiag = tj.I != tj.J;
+  if (offdiag) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int j0 = 16 * q + 4 * k;
@@ -322,17 +320,16 @@ __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __rest
   }
   a += __shfl_xor(a, 1, 64);
   a += __shfl_xor(a, 2, 64);
-  double* out = f.xpart + (sc.mpack_off / (kFb * kFb) + t) * (2 * kFb);
+  double* out = f.xpart + tj.pidx * (2 * kFb);
   if (q == 0) out[i] = a;
-  if (I == J) return;
-  // b_j over rows 16 q .. 16 q + 15 (thread: column j = tid / 4, row quarter q)
-  double b = 0.0;
-  const int j = i;
+  if (!offdiag) return;
+  // b over rows 16 q .. 16 q + 15 of column i
+  double bsum = 0.0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) b = fma(static_cast<double>(tl[16 * q + r][j]), cI[16 * q + r], b);
-  b += __shfl_xor(b, 1, 64);
-  b += __shfl_xor(b, 2, 64);
-  if (q == 0) out[kFb + j] = b;
+  for (int r = 0; r < 16; ++r) bsum = fma(static_cast<double>(tl[16 * q + r][i]), cI[16 * q + r], bsum);
+  bsum += __shfl_xor(bsum, 1, 64);
+  bsum += __shfl_xor(bsum, 2, 64);
+  if (q == 0) out[kFb + i] = bsum;
 }
 
 // x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
@@ -347,10 +344,20 @@ __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __rest
   const int I = job.ij, nb = pt.nbk;
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
   const double* base = f.xpart + (sc.mpack_off / (kFb * kFb)) * (2 * kFb);
-  double s = 0.0;
-  for (int J = w; J < nb; J += 4)
-    s += (J < I) ? base[tile_index(J, I, nb) * (2 * kFb) + kFb + i] : base[tile_index(I, J, nb) * (2 * kFb) + i];
-  part[w][i] = s;
+  // four independent accumulators keep four loads in flight per lane
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  auto ld = [&](int J) {
+    return (J < I) ? base[tile_index(J, I, nb) * (2 * kFb) + kFb + i] : base[tile_index(I, J, nb) * (2 * kFb) + i];
+  };
+  int J = w;
+  for (; J + 12 < nb; J += 16) {
+    s0 += ld(J);
+    s1 += ld(J + 4);
+    s2 += ld(J + 8);
+    s3 += ld(J + 12);
+  }
+  for (; J < nb; J += 4) s0 += ld(J);
+  part[w][i] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   if (w == 0) {
     const int row = I * kFb + i;
@@ -465,10 +472,11 @@ void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStrea
 
 void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (njobs <= 0) return;
+  const int grid = njobs;
   if (e0 != nullptr)
-    hipExtLaunchKernelGGL(k_xsym, dim3(njobs), dim3(256), 0, st, e0, e1, 0, f, c);
+    hipExtLaunchKernelGGL(k_xsym, dim3(grid), dim3(256), 0, st, e0, e1, 0, f, c);
   else
-    hipLaunchKernelGGL(k_xsym, dim3(njobs), dim3(256), 0, st, f, c);
+    hipLaunchKernelGGL(k_xsym, dim3(grid), dim3(256), 0, st, f, c);
 }
 
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st) {

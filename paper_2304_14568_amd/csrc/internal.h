@@ -169,7 +169,7 @@ struct VecArgs {
   const float* ub;
   double* dprev;           // d = x - z of the last iteration (stacked, fp64)
   double* bpart;           // per scenario-block partials [blk * 8 + k]
-  double* bpartp;          // per patient-block partials [pblk * 8 + k]
+  double* bpartp;          // per quarter patient-block partials [(4 * pblk + quarter) * 8 + k]
   float* out;              // RMAT / NORMAL output vector (n)
   double rho_out;          // NORMAL: diagonal shift rho/2 * v added when > 0
   const double* fpart;     // dense x-update: objective partials per workgroup (nullptr: tile partials)
@@ -180,6 +180,17 @@ struct VecArgs {
 };
 
 // Dense x-update (cached inverse of every B_s): device arrays and work tables.
+// One packed tile of an inverse M_s, with everything its x-update workgroup
+// needs to address it (no dependent table lookups before the tile load).
+struct XTile {
+  int64_t moff;    // float offset of the tile in Mp
+  int64_t vbase;   // vec_base of the scenario
+  int64_t pidx;    // index of the tile's partial pair in xpart (units of 2 x 64 doubles)
+  int32_t n;       // spots of the patient
+  int32_t patient;
+  int32_t I, J;    // block row and block column
+};
+
 struct XJob {
   int32_t g;    // scenario (x-update) or patient (objective)
   int32_t ij;   // tile (I, J) as I * 65536 + J, or the block row I (reduction)
@@ -201,7 +212,8 @@ struct FactorArgs {
   double* U;          // per scenario: 64 x npmax column panel, transposed
   double* R;          // per scenario: 64 x npmax row panel
   double* xpart;      // per packed tile of every scenario: T c_J (64) and T^T c_I (64), fp64
-  const XJob* xjobs;  // x-update: one per packed tile of every scenario
+  const XTile* xtiles; // x-update: one per packed tile of every scenario
+  int32_t nxtiles;
   const XJob* rjobs;  // x-update reduction: one per block row of every scenario
   const XJob* fjobs;  // objective: one per packed tile of every patient
   double* fpart;      // objective partial per objective job

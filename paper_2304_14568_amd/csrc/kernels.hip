@@ -741,88 +741,83 @@ void launch_cg_dir(const VecArgs& a, int nblk, hipStream_t st) {
 // workgroup (every quantity is columnwise until the final sums)
 // ---------------------------------------------------------------------------
 
-// Four waves per 64-column block: wave w takes the scenarios s = w, w + 4, ...
-// (more loads in flight than one wave looping over all scenarios); partial
-// sums are combined in a fixed order, so the result does not depend on timing.
+// One workgroup per 16 columns of a patient block: thread (g, c) = (tid / 16,
+// tid % 16) takes column c and the scenarios s = g, g + 16, ... (one each for
+// N <= 16), so every load of x, y and d_prev is independent of the others.
+// Partial sums over scenarios and columns are combined in a fixed order, so
+// the result does not depend on timing.  Partials: bpartp[(4 * pblk + sub) * 8 + k].
+constexpr int kZCols = 16;
 __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
-  __shared__ double sacc[4][64];
-  __shared__ double sloc[4][4];
-  __shared__ float zsh[64];
-  const int bi = static_cast<int>(blockIdx.x);
-  const Blk bk = a.pblk[bi];
+  __shared__ double sacc[kThreads / kZCols][kZCols];
+  __shared__ float zsh[kZCols];
+  __shared__ double sred[4][6];
+  const int bi4 = static_cast<int>(blockIdx.x);
+  const Blk bk = a.pblk[bi4 >> 2];
   const int p = bk.owner;
   const Pat pt = a.pat[p];
   const PatState* ps = a.ps + p;
   if (ps->stopped) return;
   const double rho = ps->rho;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = bk.col0 + lane;
-  const bool valid = j < pt.n;
+  const int tid = threadIdx.x;
+  const int col = tid % kZCols, grp = tid / kZCols;
+  constexpr int kGroups = kThreads / kZCols;
+  const int j = bk.col0 + (bi4 & 3) * kZCols + col;
+  const bool valid = j < pt.n && (bi4 & 3) * kZCols + col < kColBlock;
   double acc = 0.0;
   if (valid)
-    for (int s = w; s < pt.num_scen; s += 4) {
+    for (int s = grp; s < pt.num_scen; s += kGroups) {
       const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
       acc += static_cast<double>(a.x[vi]);
       if (a.prm.z_mode == 0) acc += static_cast<double>(a.y[vi]) / rho;
     }
-  sacc[w][lane] = acc;
+  sacc[grp][col] = acc;
   __syncthreads();
-  double loc0 = 0.0, loc1 = 0.0;
-  if (w == 0) {
+  double v[6] = {0, 0, 0, 0, 0, 0};  // ||dz||^2, ||z||^2, ||d||^2, <dd,d_prev>, ||dd||^2, ||x||^2
+  if (grp == 0) {
     float znf = 0.0f;
     if (valid) {
+      double sum = 0.0;
+      for (int g = 0; g < kGroups; ++g) sum += sacc[g][col];
       const int64_t zi = pt.zvec_base + j;
-      double zn = ((sacc[0][lane] + sacc[1][lane]) + (sacc[2][lane] + sacc[3][lane])) / pt.num_scen;
+      double zn = sum / pt.num_scen;
       zn = fmin(fmax(zn, static_cast<double>(a.lb[zi])), static_cast<double>(a.ub[zi]));
       znf = static_cast<float>(zn);
       const double dz = static_cast<double>(znf) - static_cast<double>(a.z[zi]);
       a.z[zi] = znf;
-      loc0 = dz * dz;
-      loc1 = static_cast<double>(znf) * znf;
+      v[0] = dz * dz;
+      v[1] = static_cast<double>(znf) * znf;
     }
-    zsh[lane] = znf;
+    zsh[col] = znf;
   }
   __syncthreads();
-  // ||d||^2, <dd, d_prev>, ||dd||^2, ||x||^2 over this wave's scenarios
-  double l2 = 0.0, l3 = 0.0, l4 = 0.0, l5 = 0.0;
   if (valid) {
-    const double znd = static_cast<double>(zsh[lane]);
-    for (int s = w; s < pt.num_scen; s += 4) {
+    const double znd = static_cast<double>(zsh[col]);
+    for (int s = grp; s < pt.num_scen; s += kGroups) {
       const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
       const double xv = static_cast<double>(a.x[vi]);
       const double d = xv - znd;
       const double dp = a.dprev[vi];
       const double dd = d - dp;
-      l2 += d * d;
-      l3 += dd * dp;
-      l4 += dd * dd;
-      l5 += xv * xv;
+      v[2] += d * d;
+      v[3] += dd * dp;
+      v[4] += dd * dd;
+      v[5] += xv * xv;
       a.dprev[vi] = d;
     }
   }
-  l2 = wave_sum(l2);
-  l3 = wave_sum(l3);
-  l4 = wave_sum(l4);
-  l5 = wave_sum(l5);
-  if (lane == 0) {
-    sloc[w][0] = l2;
-    sloc[w][1] = l3;
-    sloc[w][2] = l4;
-    sloc[w][3] = l5;
-  }
-  loc0 = wave_sum(loc0);
-  loc1 = wave_sum(loc1);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  if ((tid & 63) == 0)
+    for (int k = 0; k < 6; ++k) sred[tid >> 6][k] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double* bp = a.bpartp + static_cast<int64_t>(bi) * 8;
-    bp[0] = loc0;
-    bp[1] = loc1;
-    for (int k = 0; k < 4; ++k) bp[2 + k] = (sloc[0][k] + sloc[1][k]) + (sloc[2][k] + sloc[3][k]);
+  if (tid == 0) {
+    double* bp = a.bpartp + static_cast<int64_t>(bi4) * 8;
+    for (int k = 0; k < 6; ++k) bp[k] = (sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]);
   }
 }
 
 void launch_zres(const VecArgs& a, int npblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_zres, dim3(npblk), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(k_zres, dim3(4 * npblk), dim3(kThreads), 0, st, a);
 }
 
 // Residual norms, tolerances and the Barzilai-Borwein dual step per patient.
@@ -834,8 +829,8 @@ __global__ __launch_bounds__(kThreads) void k_body_scalars(VecArgs a) {
     PatState* ps = a.ps + p;
     if (ps->stopped) continue;
     double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < pt.nblk; b += kThreads)
-      for (int k = 0; k < 6; ++k) v[k] += a.bpartp[(int64_t)(pt.blk_begin + b) * 8 + k];
+    for (int b = threadIdx.x; b < 4 * pt.nblk; b += kThreads)
+      for (int k = 0; k < 6; ++k) v[k] += a.bpartp[(int64_t)(4 * pt.blk_begin + b) * 8 + k];
     block_sum<6>(v, sh);
     int cg = 0;
     if (threadIdx.x == 0) {
