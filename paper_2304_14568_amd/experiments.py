@@ -4,6 +4,7 @@
             number of scenarios N = 1..13 of one patient (Sec. 3.2, the
             scenario-count study), plus the time to reach the 1e-5 relative
             objective gap against the oracle's exact minimum where stored.
+  precision bf16 / fp16 values inside CG against fp32 and the oracle minimum
   batch     several patients of uneven size in one context (one launch per
             phase for all of them), bf16 values inside CG, a shift-lattice
             scenario set; each patient cross-checked against its own fp32
@@ -186,6 +187,54 @@ def cmd_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def cmd_precision(args):
+    """The precision forms of the CG x-update (bf16 / fp16 values with per-row
+    fp32 scales inside CG, fp32 residual every iteration) against fp32 and the
+    stored oracle minimum: objective, spot intensities, and the dose metrics a
+    planner reads (max target dose, max OAR dose over all scenarios)."""
+    import torch
+    import synth
+    from .clinical import evaluate
+    sys.path.insert(0, ROOT)
+    from tests.golden.make_references import load
+    stream = torch.cuda.Stream()
+    P = synth.hn_full(args.seed)
+    rec, xstar = load(f"hn_full_s{args.seed}")
+    if rec is None or rec["digest"] != P.digest():
+        raise SystemExit("stored oracle reference missing or stale")
+    fstar = rec["f_star"]
+    names = P.meta["struct_names"]
+    tg = [g for g, nm in enumerate(names) if nm.startswith("target")]
+    og = [g for g, nm in enumerate(names) if nm.startswith("oar")]
+    rows = []
+    with Solver(P, xupdate="cg", stream=stream) as S0:
+        ev0 = evaluate(S0, P, xstar)
+    ref_tmax = float(np.nanmax(ev0["metrics"]["Dmax"][:, tg]))
+    ref_omax = float(np.nanmax(ev0["metrics"]["Dmax"][:, og]))
+    for prec in ("fp32", "bf16", "fp16"):
+        with Solver(P, xupdate="cg", precision=prec, max_iter=3000, stream=stream) as S:
+            t0 = time.perf_counter()
+            zs, info, st = S.solve()
+            _sync()
+            dt = time.perf_counter() - t0
+            z = zs[0]
+            ev = evaluate(S, P, z)
+            f = S.objective(z)
+        tmax = float(np.nanmax(ev["metrics"]["Dmax"][:, tg]))
+        omax = float(np.nanmax(ev["metrics"]["Dmax"][:, og]))
+        row = dict(precision=prec, iters=info[0]["iter"], solve_s=dt, obj_rel_err=(f - fstar) / fstar,
+                   z_rel_err_l2=float(np.linalg.norm(z - xstar) / np.linalg.norm(xstar)),
+                   max_target_dose_rel_err=(tmax - ref_tmax) / ref_tmax,
+                   max_oar_dose_rel_err=(omax - ref_omax) / ref_omax)
+        rows.append(row)
+        print(f"[precision] {json.dumps(row)}", flush=True)
+    res = dict(workload=f"hn_full({args.seed})", reference="oracle x*, f* (tests/golden)",
+               ref_max_target_dose=ref_tmax, ref_max_oar_dose=ref_omax, rows=rows)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2304_14568_amd.experiments")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -193,6 +242,9 @@ def main(argv=None):
     a.add_argument("--seed", type=int, default=0)
     a.add_argument("--n", default="1,2,3,4,5,6,7,8,9,10,11,12,13")
     a.add_argument("--no-pgd", action="store_true")
+    a.add_argument("--out", default="")
+    a = sub.add_parser("precision")
+    a.add_argument("--seed", type=int, default=0)
     a.add_argument("--out", default="")
     a = sub.add_parser("batch")
     a.add_argument("--patients", type=int, default=8)
@@ -203,7 +255,7 @@ def main(argv=None):
     a.add_argument("--max-iter", type=int, default=1000)
     a.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    {"scaling": cmd_scaling, "batch": cmd_batch}[args.cmd](args)
+    {"scaling": cmd_scaling, "batch": cmd_batch, "precision": cmd_precision}[args.cmd](args)
 
 
 if __name__ == "__main__":
