@@ -12,7 +12,8 @@
 //        P = A_KK^-1, U = A_:K P, R = A_K: (old),
 //        A_ij -= U_i R_j off the block row and column,
 //        A_:K = U, A_K: = U^T, A_KK = -P;
-//     after the last block A = -B_s^-1.  k_sweep_store writes M_s = B_s^-1 in fp32.
+//     after the last block A = -B_s^-1.  The sweep matrix stays symmetric, so
+//     only its upper 64 x 64 tiles are updated (half the work).  k_sweep_store writes M_s = B_s^-1 in fp32.
 //  4. every iteration: k_fhead (pending dual update, right-hand side c_s),
 //     k_fobj (objective at z from the quadratic form), k_xsym + k_xsym_reduce
 //     (x_s = M_s c_s).
@@ -157,7 +158,10 @@ __global__ __launch_bounds__(256) void k_sweep_pivot(FactorArgs f, int scen_begi
   for (int e = threadIdx.x; e < kFb * kFb; e += 256) P[e] = -a[e / kFb][e % kFb];
 }
 
-// U_I = A_IK P (64 x 64 per workgroup) and R tile = A_K,I (old row panel copy)
+// U_I = A_IK P (64 x 64 per workgroup) and R tile = A_K,I (old row panel copy).
+// Only the upper tiles (I <= J) of the sweep matrix are kept up to date (it
+// stays symmetric), so blocks on the other side of the pivot are read from the
+// mirrored tile, transposed.
 __global__ __launch_bounds__(256) void k_sweep_panel(FactorArgs f, int scen_begin, int npad, int k0) {
   __shared__ double at[kFb][kFb];  // A_IK
   __shared__ double p[kFb][kFb];   // P
@@ -169,11 +173,18 @@ __global__ __launch_bounds__(256) void k_sweep_panel(FactorArgs f, int scen_begi
   double* Ut = f.U + static_cast<int64_t>(g) * f.npmax * kFb;
   double* R = f.R + static_cast<int64_t>(g) * f.npmax * kFb;
   for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
-    const int i = e / kFb, j = e % kFb;
-    at[i][j] = A[static_cast<int64_t>(i0 + i) * npad + k0 + j];
-    p[i][j] = Pg[e];
-    // row panel: R[t][i0 + j] = A[k0 + t][i0 + j]
-    R[static_cast<int64_t>(i) * npad + i0 + j] = A[static_cast<int64_t>(k0 + i) * npad + i0 + j];
+    const int r = e / kFb, c = e % kFb;
+    p[r][c] = Pg[e];
+    if (i0 <= k0) {
+      at[r][c] = A[static_cast<int64_t>(i0 + r) * npad + k0 + c];  // tile (I, K), stored
+    } else {
+      at[c][r] = A[static_cast<int64_t>(k0 + r) * npad + i0 + c];  // tile (K, I), transposed
+    }
+    // row panel R[t][i0 + j] = A[k0 + t][i0 + j]
+    if (i0 >= k0)
+      R[static_cast<int64_t>(r) * npad + i0 + c] = A[static_cast<int64_t>(k0 + r) * npad + i0 + c];
+    else
+      R[static_cast<int64_t>(c) * npad + i0 + r] = A[static_cast<int64_t>(i0 + r) * npad + k0 + c];
   }
   __syncthreads();
   const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;  // 4 x 4 outputs each
@@ -197,12 +208,18 @@ __global__ __launch_bounds__(256) void k_sweep_panel(FactorArgs f, int scen_begi
     for (int r = 0; r < 4; ++r) Ut[static_cast<int64_t>(4 * tj + r) * npad + i0 + 4 * ti + q] = acc[q][r];
 }
 
-// rank-64 update of every tile off the pivot row and column; panel tiles replaced
+// rank-64 update of every upper tile off the pivot row and column; panel tiles replaced
 __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_begin, int npad, int k0) {
   __shared__ double ut[kFb][kFb];  // ut[t][i] = U[i0 + i][t]
   __shared__ double rs[kFb][kFb];  // rs[t][j] = R[t][j0 + j]
   const int nbk = npad / kFb;
-  const int bi = static_cast<int>(blockIdx.x) / nbk, bj = static_cast<int>(blockIdx.x) % nbk;
+  // upper tile number -> (bi, bj), bi <= bj
+  int t0 = static_cast<int>(blockIdx.x), bi = 0;
+  while (t0 >= nbk - bi) {
+    t0 -= nbk - bi;
+    ++bi;
+  }
+  const int bj = bi + t0;
   const int g = scen_begin + static_cast<int>(blockIdx.y);
   const Scen sc = f.scen[g];
   double* A = f.A + sc.fmat_off;
@@ -461,7 +478,7 @@ void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0
   const int nbk = npad / kFb;
   hipLaunchKernelGGL(k_sweep_pivot, dim3(nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
   hipLaunchKernelGGL(k_sweep_panel, dim3(nbk, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
-  hipLaunchKernelGGL(k_sweep_update, dim3(nbk * nbk, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
+  hipLaunchKernelGGL(k_sweep_update, dim3(nbk * (nbk + 1) / 2, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
 }
 
 void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStream_t st) {
