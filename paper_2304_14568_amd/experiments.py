@@ -5,6 +5,7 @@
             scenario-count study), plus the time to reach the 1e-5 relative
             objective gap against the oracle's exact minimum where stored.
   precision bf16 / fp16 values inside CG against fp32 and the oracle minimum
+  plans     plan quality of ADMM-BB and PGD (Table 2 style criteria, DVH bands)
   batch     several patients of uneven size in one context (one launch per
             phase for all of them), bf16 values inside CG, a shift-lattice
             scenario set; each patient cross-checked against its own fp32
@@ -235,6 +236,42 @@ def cmd_precision(args):
             json.dump(res, f, indent=1)
 
 
+def cmd_plans(args):
+    """Plan quality of ADMM-BB and PGD on the same patient, the way Sec. 3
+    compares them: Table 2 style criteria over the scenarios and the DVH bands
+    of the targets (band width = max - min over scenarios of the DVH)."""
+    import torch
+    import synth
+    from .clinical import evaluate, criteria_table
+    stream = torch.cuda.Stream()
+    P = synth.hn_full(args.seed)
+    out = {}
+    with Solver(P, stream=stream, max_iter=3000) as S:
+        t0 = time.perf_counter()
+        zs, info, _ = S.solve()
+        _sync()
+        plans = {"admm_bb": (zs[0], time.perf_counter() - t0, info[0]["iter"])}
+        t0 = time.perf_counter()
+        x, pinfo, _ = S.pgd(0)
+        plans["pgd_paper_stop"] = (x, time.perf_counter() - t0, pinfo["iter"])
+        t0 = time.perf_counter()
+        x2, pinfo2, _ = S.pgd(0, obj_rel_tol=0.0, max_iter=args.pgd_iters)
+        plans[f"pgd_{args.pgd_iters}_iters"] = (x2, time.perf_counter() - t0, pinfo2["iter"])
+        for name, (x, dt, it) in plans.items():
+            ev = evaluate(S, P, x)
+            f = S.objective(x)
+            bands = {}
+            for g, nm in enumerate(ev["names"]):
+                if nm.startswith("target"):
+                    bands[nm] = float(np.nanmax(ev["dvh_band_max"][g] - ev["dvh_band_min"][g]))
+            out[name] = dict(obj=f, seconds=dt, iters=it, criteria=ev["criteria"], target_dvh_band_max_width=bands)
+            print(f"[plans] {name}: f={f:.6f} {dt:.3f}s {it} it, target DVH band widths {bands}", flush=True)
+            print(criteria_table(ev), flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(out, fh, indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2304_14568_amd.experiments")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -242,6 +279,10 @@ def main(argv=None):
     a.add_argument("--seed", type=int, default=0)
     a.add_argument("--n", default="1,2,3,4,5,6,7,8,9,10,11,12,13")
     a.add_argument("--no-pgd", action="store_true")
+    a.add_argument("--out", default="")
+    a = sub.add_parser("plans")
+    a.add_argument("--seed", type=int, default=0)
+    a.add_argument("--pgd-iters", type=int, default=2048)
     a.add_argument("--out", default="")
     a = sub.add_parser("precision")
     a.add_argument("--seed", type=int, default=0)
@@ -255,7 +296,7 @@ def main(argv=None):
     a.add_argument("--max-iter", type=int, default=1000)
     a.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    {"scaling": cmd_scaling, "batch": cmd_batch, "precision": cmd_precision}[args.cmd](args)
+    {"scaling": cmd_scaling, "batch": cmd_batch, "precision": cmd_precision, "plans": cmd_plans}[args.cmd](args)
 
 
 if __name__ == "__main__":
