@@ -120,7 +120,7 @@ def main():
     import torch
     import synth
     import paper_2304_14568_amd as A
-    from tests.golden.make_references import load as load_ref
+    from tests.golden.refs import load as load_ref
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -40,7 +40,7 @@ def _sync():
 def _stored_fstar(name: str, digest: str):
     sys.path.insert(0, ROOT)
     try:
-        from tests.golden.make_references import load
+        from tests.golden.refs import load
     except Exception:  # pragma: no cover
         return None
     rec, _ = load(name)
@@ -197,7 +197,7 @@ def cmd_precision(args):
     import synth
     from .clinical import evaluate
     sys.path.insert(0, ROOT)
-    from tests.golden.make_references import load
+    from tests.golden.refs import load
     stream = torch.cuda.Stream()
     P = synth.hn_full(args.seed)
     rec, xstar = load(f"hn_full_s{args.seed}")

@@ -57,17 +57,7 @@ def make(name: str) -> dict:
     return rec
 
 
-def load(name: str):
-    """Return (record, x_star) or (None, None) when no stored file exists."""
-    path = os.path.join(HERE, f"{name}.json")
-    if not os.path.exists(path):
-        return None, None
-    with open(path) as fh:
-        rec = json.load(fh)
-    x = np.zeros(rec["n"])
-    for k, v in rec["x_star_nonzero"].items():
-        x[int(k)] = v
-    return rec, x
+from tests.golden.refs import load  # noqa: E402,F401  (re-exported for the tests)
 
 
 if __name__ == "__main__":
