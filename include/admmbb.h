@@ -124,7 +124,9 @@ typedef struct {
                             the cached-factor solver of Appendix A); needs n <= 8128 and
                             about 20 N n^2 bytes of device memory per patient;
                           ADMM_XUPDATE_AUTO (default): DENSE when every patient has n <= 8128 and the
-                            matrices take at most a quarter of the free device memory, else CG */
+                            matrices take at most a quarter of the free device memory, else CG.
+                          The set-up works on chunks of scenarios whose fp64 matrices take at most
+                          8 GiB (environment variable ADMMBB_DENSE_CHUNK_MB overrides the limit). */
   void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
 } admm_options;
 

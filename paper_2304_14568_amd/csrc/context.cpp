@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -84,7 +85,9 @@ struct admm_ctx {
   XJob *d_rjobs = nullptr, *d_fjobs = nullptr;
   XTile* d_xtiles = nullptr;
   int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
+  int64_t gp_elems = 0;
   std::vector<double> factored_rho;  // per patient: penalty of the cached inverse
+  std::vector<int> chunk_scen;       // per patient: scenarios per set-up chunk
   double factor_ms = 0.0;            // time of the last set-up of the cached inverses
 
   template <class T>
@@ -203,24 +206,25 @@ struct admm_ctx {
     return f;
   }
 
-  // (Re)build the cached inverses of patient p at its current penalty: the
-  // Gram matrices (when form_gram), then B_s = G_s + rho/2 I swept in place.
-  void factorize(int p, bool form_gram) {
+  // (Re)build the cached inverses of patient p at its current penalty, a
+  // chunk of scenarios at a time: Gram matrices, B_s = G_s + rho/2 I swept in
+  // place, packed fp32 inverses.  With accumulate_gsum (the first time) the
+  // chunks also add up the packed sum_s G_s of the objective.
+  void factorize(int p, bool accumulate_gsum) {
     const Pat& pt = H.pat[p];
     const int npad = pt.npad;
     const int64_t nn = static_cast<int64_t>(npad) * npad;
-    const Scen& s0 = H.scen[pt.scen_begin];
     FactorArgs f = fargs();
-    if (form_gram) {
-      launch_fill_f64(d_G + s0.fmat_off, 0.0, nn * pt.num_scen, stream);
-      for (int s = 0; s < pt.num_scen; ++s) {
-        const Scen& sc = H.scen[pt.scen_begin + s];
-        launch_gram(mat32, d_rw64, sc, d_G + sc.fmat_off, npad, stream);
-      }
+    const int chunk = chunk_scen[p];
+    for (int c0 = 0; c0 < pt.num_scen; c0 += chunk) {
+      const int cs = std::min(chunk, pt.num_scen - c0);
+      const int g0 = pt.scen_begin + c0;
+      launch_fill_f64(d_G, 0.0, nn * cs, stream);
+      for (int s = 0; s < cs; ++s) launch_gram(mat32, d_rw64, H.scen[g0 + s], d_G + s * nn, npad, stream);
+      launch_gram_finish(f, p, g0, cs, npad, pt.n, rho[p], accumulate_gsum ? 1 : 0, stream);
+      for (int k0 = 0; k0 < npad; k0 += 64) launch_sweep_step(f, g0, cs, npad, k0, stream);
+      launch_sweep_store(f, p, g0, cs, npad, stream);
     }
-    launch_gram_finish(f, p, pt.num_scen, npad, pt.n, rho[p], stream);
-    for (int k0 = 0; k0 < npad; k0 += 64) launch_sweep_step(f, pt.scen_begin, pt.num_scen, npad, k0, stream);
-    launch_sweep_store(f, p, pt.num_scen, npad, stream);
     check(hipGetLastError(), "factor launch");
     factored_rho[p] = rho[p];
   }
@@ -440,7 +444,7 @@ struct admm_ctx {
     launch_fill_f64(d_dprev + s0.vec_base, 0.0, len, stream);
     check(hipMemsetAsync(d_cgtotal + pt.scen_begin, 0, sizeof(int64_t) * pt.num_scen, stream), "memset");
     if (new_rho > 0) rho[p] = new_rho;
-    if (dense && factored_rho[p] != rho[p]) factorize(p, false);
+    if (dense && factored_rho[p] != rho[p]) factorize(p, false);  // Sum_s G_s does not depend on rho
     PatState st{};
     st.rho = rho[p];
     st.tau = rho[p];
@@ -615,18 +619,27 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     // dense x-update: sizes, offsets and work lists (before the tables go to the device)
     std::vector<XJob> rjobs, fjobs;
     std::vector<XTile> xtiles;
+    // dense set-up works on chunks of scenarios: G and the sweep matrix (fp64,
+    // npad^2 each) for at most kChunkBytes at a time
+    int64_t kChunkBytes = int64_t(8) << 30;
+    if (const char* env = std::getenv("ADMMBB_DENSE_CHUNK_MB")) {
+      const long long mb = std::atoll(env);
+      if (mb > 0) kChunkBytes = static_cast<int64_t>(mb) << 20;
+    }
     {
-      int64_t need = 0;
+      int64_t need = 0, chunk_need = 0;
       bool fits_n = true;
       for (const Pat& pt : H.pat) {
         const int64_t npad = (pt.n + 63) / 64 * 64, nb = npad / 64, tiles = nb * (nb + 1) / 2;
         fits_n = fits_n && pt.n <= 8128;
-        // set-up: G and the sweep matrix (fp64, full); every iteration: packed fp32
-        // inverses, packed fp64 sum of G, tile partials; U, R panels
-        need += npad * npad * 16 * static_cast<int64_t>(pt.num_scen) +
-                tiles * 4096 * (4 * static_cast<int64_t>(pt.num_scen) + 8) + tiles * 1024 * pt.num_scen +
+        const int64_t per_scen = 16 * npad * npad;
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(pt.num_scen, kChunkBytes / per_scen));
+        chunk_need = std::max(chunk_need, chunk * per_scen);
+        // every iteration: packed fp32 inverses, packed fp64 sum of G, tile partials; U, R panels
+        need += tiles * 4096 * (4 * static_cast<int64_t>(pt.num_scen) + 8) + tiles * 1024 * pt.num_scen +
                 2 * 8 * 64 * npad * pt.num_scen;
       }
+      need += chunk_need;
       size_t free_b = 0, total_b = 0;
       check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
       if (o.xupdate == ADMM_XUPDATE_DENSE) {
@@ -639,7 +652,8 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       }
     }
     if (c->dense) {
-      int64_t off = 0, moff = 0, goff = 0;
+      int64_t chunk_elems = 0, moff = 0, goff = 0;
+      c->chunk_scen.assign(num_patients, 1);
       for (int p = 0; p < num_patients; ++p) {
         Pat& pt = H.pat[p];
         pt.npad = (pt.n + 63) / 64 * 64;
@@ -647,6 +661,9 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
         c->ld_max = std::max(c->ld_max, pt.npad);
         const int64_t nn = static_cast<int64_t>(pt.npad) * pt.npad;
         const int64_t tiles = static_cast<int64_t>(pt.nbk) * (pt.nbk + 1) / 2;
+        const int chunk = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(pt.num_scen, kChunkBytes / (16 * nn))));
+        c->chunk_scen[p] = chunk;
+        chunk_elems = std::max(chunk_elems, chunk * nn);
         pt.gpack_off = goff;
         goff += tiles * 4096;
         pt.fobj_begin = static_cast<int32_t>(fjobs.size());
@@ -656,8 +673,6 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
         for (int s = 0; s < pt.num_scen; ++s) {
           const int g = pt.scen_begin + s;
           Scen& sc = H.scen[g];
-          sc.fmat_off = off;
-          off += nn;
           sc.mpack_off = moff;
           moff += tiles * 4096;
           for (int I = 0; I < pt.nbk; ++I)
@@ -679,13 +694,14 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       c->n_xjobs = static_cast<int>(xtiles.size());
       c->n_rjobs = static_cast<int>(rjobs.size());
       c->n_fjobs = static_cast<int>(fjobs.size());
-      c->d_G = c->alloc<double>(static_cast<size_t>(off));
-      c->d_Aw = c->alloc<double>(static_cast<size_t>(off));
+      c->d_G = c->alloc<double>(static_cast<size_t>(chunk_elems));
+      c->d_Aw = c->alloc<double>(static_cast<size_t>(chunk_elems));
       c->d_Mp = c->alloc<float>(static_cast<size_t>(moff));
       c->d_xpart = c->alloc<double>(static_cast<size_t>(moff / 4096) * 128);
       c->d_c64 = c->alloc<double>(static_cast<size_t>(H.vec_total));
       c->d_b64 = c->upload(H.b64);
       c->d_Gp = c->alloc<double>(static_cast<size_t>(goff));
+      c->gp_elems = goff;
       c->d_Pb = c->alloc<double>(static_cast<size_t>(c->G) * 64 * 64);
       c->d_U = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
       c->d_R = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
@@ -769,6 +785,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       check(hipEventCreate(&f0), "hipEventCreate");
       check(hipEventCreate(&f1), "hipEventCreate");
       check(hipEventRecord(f0, c->stream), "hipEventRecord");
+      launch_fill_f64(c->d_Gp, 0.0, c->gp_elems, c->stream);
       for (int p = 0; p < num_patients; ++p) c->factorize(p, true);
       check(hipEventRecord(f1, c->stream), "hipEventRecord");
       check(hipEventSynchronize(f1), "hipEventSynchronize");

@@ -5,8 +5,10 @@
 //
 //  1. k_gram: G_s = A_s^T diag(c_s w) A_s, upper triangle, fp64 atomics (one
 //     wave per stored row: every pair j <= k of its nonzeros).
-//  2. k_gram_finish: mirror to the lower triangle, sum_s G_s, and the sweep
-//     work matrix A = G_s + rho/2 I (identity on the padding to npad).
+//  2. k_gram_finish: the upper tiles of the sweep work matrix
+//     A = G_s + rho/2 I (identity on the padding to npad) and sum_s G_s.
+//     Steps 1-3 run on chunks of scenarios, so that only a chunk's fp64
+//     set-up matrices occupy device memory at a time.
 //  3. block sweep (Gauss-Jordan on 64-blocks, no pivoting: the pivot blocks
 //     are Schur complements of an SPD matrix): for each block K,
 //        P = A_KK^-1, U = A_:K P, R = A_K: (old),
@@ -86,28 +88,32 @@ __global__ __launch_bounds__(256) void k_gram(MatDev mat, const double* __restri
   }
 }
 
-// mirror the upper triangle, add sum_s G_s, build A = G + rho/2 I (identity on the padding)
-__global__ __launch_bounds__(256) void k_gram_finish(FactorArgs f, int patient, int nscen, int npad, int n,
-                                                     double rho) {
+// For the chunk of scenarios [scen_begin, scen_begin + nscen) of one patient
+// (chunk buffers, npad x npad per scenario, upper triangle of G accumulated):
+// the upper tiles of A = G + rho/2 I (identity on the padding; inside a
+// diagonal tile both triangles, the lower one read from the upper), and, when
+// accumulate_gsum, their sum over the chunk added to the packed sum_s G_s.
+__global__ __launch_bounds__(256) void k_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen,
+                                                     int npad, int n, double rho, int accumulate_gsum) {
   const Pat pt = f.pat[patient];
   const int64_t nn = static_cast<int64_t>(npad) * npad;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  (void)scen_begin;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nn; idx += stride) {
     const int i = static_cast<int>(idx / npad), j = static_cast<int>(idx % npad);
+    const int I = i / kFb, J = j / kFb;
+    if (I > J) continue;  // only the upper tiles are used from here on
+    const int64_t src = (i <= j) ? idx : static_cast<int64_t>(j) * npad + i;
     double sum = 0.0;
     for (int s = 0; s < nscen; ++s) {
-      const Scen sc = f.scen[pt.scen_begin + s];
-      double* G = f.G + sc.fmat_off;
-      const double gv = (i <= j) ? G[idx] : G[static_cast<int64_t>(j) * npad + i];
-      if (i > j) G[idx] = gv;  // lower triangle written only here, upper only read
+      const double gv = f.G[s * nn + src];
       sum += gv;
       double a = gv;
       if (i == j) a += (i < n) ? 0.5 * rho : 1.0;
-      f.A[sc.fmat_off + idx] = a;
+      f.A[s * nn + idx] = a;
     }
-    const int I = i / kFb, J = j / kFb;
-    if (I <= J)
-      f.Gp[pt.gpack_off + tile_index(I, J, pt.nbk) * kFb * kFb + (i % kFb) * kFb + (j % kFb)] = sum;
+    if (accumulate_gsum)
+      f.Gp[pt.gpack_off + tile_index(I, J, pt.nbk) * kFb * kFb + (i % kFb) * kFb + (j % kFb)] += sum;
   }
 }
 
@@ -119,8 +125,7 @@ __global__ __launch_bounds__(256) void k_gram_finish(FactorArgs f, int patient, 
 __global__ __launch_bounds__(256) void k_sweep_pivot(FactorArgs f, int scen_begin, int npad, int k0) {
   __shared__ double a[kFb][kFb + 1];
   const int g = scen_begin + static_cast<int>(blockIdx.x);
-  const Scen sc = f.scen[g];
-  const double* A = f.A + sc.fmat_off;
+  const double* A = f.A + static_cast<int64_t>(blockIdx.x) * npad * npad;  // chunk buffer
   for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
     const int i = e / kFb, j = e % kFb;
     a[i][j] = A[static_cast<int64_t>(k0 + i) * npad + k0 + j];
@@ -166,8 +171,7 @@ __global__ __launch_bounds__(256) void k_sweep_panel(FactorArgs f, int scen_begi
   __shared__ double at[kFb][kFb];  // A_IK
   __shared__ double p[kFb][kFb];   // P
   const int g = scen_begin + static_cast<int>(blockIdx.y);
-  const Scen sc = f.scen[g];
-  const double* A = f.A + sc.fmat_off;
+  const double* A = f.A + static_cast<int64_t>(blockIdx.y) * npad * npad;  // chunk buffer
   const int i0 = static_cast<int>(blockIdx.x) * kFb;
   const double* Pg = f.P + static_cast<int64_t>(g) * kFb * kFb;
   double* Ut = f.U + static_cast<int64_t>(g) * f.npmax * kFb;
@@ -221,8 +225,7 @@ __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_beg
   }
   const int bj = bi + t0;
   const int g = scen_begin + static_cast<int>(blockIdx.y);
-  const Scen sc = f.scen[g];
-  double* A = f.A + sc.fmat_off;
+  double* A = f.A + static_cast<int64_t>(blockIdx.y) * npad * npad;  // chunk buffer
   const int i0 = bi * kFb, j0 = bj * kFb, kb = k0 / kFb;
   const double* Ut = f.U + static_cast<int64_t>(g) * f.npmax * kFb;
   const double* R = f.R + static_cast<int64_t>(g) * f.npmax * kFb;
@@ -270,18 +273,19 @@ __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_beg
     }
 }
 
-// packed M = -A (upper tiles) in fp32
-__global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, int npad) {
+// packed M = -A (upper tiles) in fp32, for the chunk of scenarios starting at scen_begin
+__global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, int scen_begin, int npad) {
   const Pat pt = f.pat[patient];
-  const Scen sc = f.scen[pt.scen_begin + static_cast<int>(blockIdx.y)];
+  const Scen sc = f.scen[scen_begin + static_cast<int>(blockIdx.y)];
   const int64_t nn = static_cast<int64_t>(npad) * npad;
+  const double* A = f.A + static_cast<int64_t>(blockIdx.y) * nn;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nn; idx += stride) {
     const int i = static_cast<int>(idx / npad), j = static_cast<int>(idx % npad);
     const int I = i / kFb, J = j / kFb;
     if (I <= J)
       f.Mp[sc.mpack_off + tile_index(I, J, pt.nbk) * kFb * kFb + (i % kFb) * kFb + (j % kFb)] =
-          static_cast<float>(-f.A[sc.fmat_off + idx]);
+          static_cast<float>(-A[idx]);
   }
 }
 
@@ -467,11 +471,12 @@ void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G,
     hipLaunchKernelGGL(k_gram<false>, dim3(nb), dim3(256), 0, st, m, rw64, sc, G, ld);
 }
 
-void launch_gram_finish(FactorArgs f, int patient, int nscen, int npad, int n, double rho, hipStream_t st) {
+void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, int npad, int n, double rho,
+                        int accumulate_gsum, hipStream_t st) {
   int64_t nb = (static_cast<int64_t>(npad) * npad + 255) / 256;
   if (nb > 8192) nb = 8192;
-  hipLaunchKernelGGL(k_gram_finish, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, f, patient, nscen, npad, n,
-                     rho);
+  hipLaunchKernelGGL(k_gram_finish, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, f, patient, scen_begin,
+                     nscen, npad, n, rho, accumulate_gsum);
 }
 
 void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st) {
@@ -481,10 +486,11 @@ void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0
   hipLaunchKernelGGL(k_sweep_update, dim3(nbk * (nbk + 1) / 2, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
 }
 
-void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStream_t st) {
+void launch_sweep_store(FactorArgs f, int patient, int scen_begin, int nscen, int npad, hipStream_t st) {
   int64_t nb = (static_cast<int64_t>(npad) * npad + 255) / 256;
   if (nb > 4096) nb = 4096;
-  hipLaunchKernelGGL(k_sweep_store, dim3(static_cast<unsigned>(nb), nscen), dim3(256), 0, st, f, patient, npad);
+  hipLaunchKernelGGL(k_sweep_store, dim3(static_cast<unsigned>(nb), nscen), dim3(256), 0, st, f, patient,
+                     scen_begin, npad);
 }
 
 void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {

@@ -35,7 +35,6 @@ struct Scen {
   int32_t tile_begin, tile_end;
   float cw;             // scenario probability c_s (already folded into rw)
   int32_t pad;
-  int64_t fmat_off;     // dense x-update: offset of this scenario's npad x npad matrices (set-up)
   int64_t mpack_off;    // dense x-update: offset of its packed inverse (upper 64 x 64 tiles, 4096 each)
 };
 
@@ -203,8 +202,8 @@ struct FactorArgs {
   const Scen* scen;
   const Pat* pat;
   const PatState* ps;
-  double* G;          // per scenario: G_s = A_s^T c_s W A_s, full npad x npad, fp64 (set-up)
-  double* A;          // per scenario: sweep work matrix, ends as -(G_s + rho/2 I)^-1 (set-up)
+  double* G;          // set-up chunk: G_s = A_s^T c_s W A_s per scenario, npad x npad, fp64
+  double* A;          // set-up chunk: sweep work matrices, end as -(G_s + rho/2 I)^-1
   float* Mp;          // per scenario: packed (G_s + rho/2 I)^-1, fp32
   double* Gp;         // per patient: packed sum_s G_s, fp64
   const double* g0;   // per patient: 2 sum_s A_s^T c_s W p, fp64 (zvec layout)
@@ -244,9 +243,10 @@ void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st);
 int pass_smem_bytes(int nmax, int acc);
 int dose_hist_smem_bytes(int G, int nbins);
 void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G, int ld, hipStream_t st);
-void launch_gram_finish(FactorArgs f, int patient, int nscen, int npad, int n, double rho, hipStream_t st);
+void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, int npad, int n, double rho,
+                        int accumulate_gsum, hipStream_t st);
 void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st);
-void launch_sweep_store(FactorArgs f, int patient, int nscen, int npad, hipStream_t st);
+void launch_sweep_store(FactorArgs f, int patient, int scen_begin, int nscen, int npad, hipStream_t st);
 void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st);
