@@ -151,10 +151,12 @@ def cmd_batch(args):
     res = dict(patients=[dict(m=P.m, n=P.n, nnz=P.nnz) for P in Ps], scenarios=args.scen,
                total_nnz=int(sum(P.nnz for P in Ps)), generate_s=gen_s, precision=args.precision)
     t0 = time.perf_counter()
-    S = Solver(Ps, xupdate="cg", precision=args.precision, max_iter=args.max_iter, stream=stream)
+    S = Solver(Ps, xupdate=args.xupdate, precision=args.precision, max_iter=args.max_iter, stream=stream)
     _sync()
     res["setup_s"] = time.perf_counter() - t0
-    print(f"[batch] set-up {res['setup_s']:.1f}s, {res['total_nnz']} nonzeros", flush=True)
+    res["xupdate"], res["dense_factor_ms"] = S.xupdate()
+    print(f"[batch] set-up {res['setup_s']:.1f}s ({res['xupdate']} x-update), {res['total_nnz']} nonzeros",
+          flush=True)
     S.iterate(2)
     S.reset()
     _sync()
@@ -292,6 +294,7 @@ def main(argv=None):
     a.add_argument("--scen", type=int, default=64)
     a.add_argument("--seed", type=int, default=10)
     a.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
+    a.add_argument("--xupdate", default="cg", choices=["auto", "cg", "dense"])
     a.add_argument("--steps", type=int, default=20)
     a.add_argument("--max-iter", type=int, default=1000)
     a.add_argument("--out", default="")
