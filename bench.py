@@ -252,6 +252,9 @@ def main():
                 torch.cuda.synchronize()
                 result["time_to_1e-5_s"] = time.perf_counter() - t0
                 result["iters_to_1e-5"] = k_hit
+                # the same, counted from the start of the set-up (validation, packing,
+                # upload, cached inverses)
+                result["time_to_1e-5_from_setup_s"] = t_setup + result["time_to_1e-5_s"]
             else:
                 result["time_to_1e-5_s"] = None
         else:
