@@ -61,6 +61,22 @@ def pass_bytes(P, precision: str) -> np.ndarray:
     return np.asarray(out, dtype=np.float64)
 
 
+def spmv_bytes(P) -> dict:
+    """Algorithmic bytes of one sparse pass over all scenarios (fp32 values, u16
+    columns): per nonzero 6 B; per nonempty row the chunk offset plus two 4 B
+    row values (weight and prescription for the forward pass, original index and
+    the gathered t_i for the transpose); the n-vector in or out."""
+    out = {}
+    tot = 0.0
+    for a in P.A:
+        rows = int(np.count_nonzero(np.diff(a.row_ptr)))
+        tot += a.nnz * 6 + rows * 12 + 4 * P.n
+    out["forward"] = tot
+    out["transpose"] = tot
+    out["normal"] = float(pass_bytes(P, "fp32").sum())
+    return out
+
+
 def cpu_baseline(P, seconds_budget: float = 25.0) -> dict:
     """Time the FP64 oracle's ADMM-BB on a bounded sample of the workload: the
     same patient restricted to 3 of its 13 scenarios (set-up: dense Gram matrix
@@ -230,6 +246,16 @@ def main():
         "generate_s": t_gen,
         "obj_after_steps": info[0]["obj"],
     }
+
+    # the sparse products on their own (dense and CG x-updates alike use them for
+    # the objective, gradients, features and the CG operator)
+    sb = spmv_bytes(P)
+    spmv = {}
+    for kind in ("forward", "transpose", "normal"):
+        ms = S.time_pass(kind, reps=20)
+        gbs = sb[kind] / (ms * 1e-3) / 1e9
+        spmv[kind] = {"ms": ms, "bytes": sb[kind], "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    result["spmv"] = spmv
 
     if not args.no_ttt:
         # time to reach (f - f*) / f* <= 1e-5 from zero initialisation

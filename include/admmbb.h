@@ -225,6 +225,14 @@ admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, con
                             int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
                             float* maxes, float* dose_out);
 
+/* Measurement: average device time in ms of one launch of a sparse pass over
+ * every scenario of every patient (reps launches back to back, HIP events on
+ * the context's stream).  kind 0: forward product A_s z fused with the
+ * weighted residual norm (the objective pass); 1: transpose product A_s^T t for
+ * a voxel vector t; 2: the fused normal operator A_s^T diag(c_s w) A_s v of a
+ * CG step.  Changes no solver state. */
+admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms_out);
+
 /* Dose-derived per-spot features for the learned warm start, computed on the GPU
  * from A_s^T applied to voxel indicator vectors.  voxel_class[m]: 0 other,
  * 1 target, 2 organ at risk.  feat: n x ADMM_NUM_DOSE_FEATURES floats, row-major:

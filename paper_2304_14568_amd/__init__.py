@@ -27,7 +27,7 @@ EXPORTS = [
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
     "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
-    "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate",
+    "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate", "admm_time_pass",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
     "mlp_loss_grad", "mlp_adam_step", "mlp_last_error",
 ]
@@ -100,6 +100,7 @@ def _load():
         "admm_spot_features": [P, i32, P, P],
         "admm_dose_stats": [P, i32, P, P, i32, i32, dbl, P, P, P, P],
         "admm_get_xupdate": [P, P, P],
+        "admm_time_pass": [P, i32, i32, P],
         "mlp_create": [i32, i32, ctypes.c_uint64, P, ctypes.POINTER(P)],
         "mlp_get_params": [P, P],
         "mlp_set_params": [P, P],
@@ -399,6 +400,13 @@ class Solver:
         mode, ms = ctypes.c_int32(), ctypes.c_double()
         _check(self.ctx, lib.admm_get_xupdate(self.ctx, ctypes.byref(mode), ctypes.byref(ms)))
         return ("dense" if mode.value == 1 else "cg"), ms.value
+
+    def time_pass(self, kind: str, reps: int = 20) -> float:
+        """Average ms of one sparse pass over all scenarios: 'forward', 'transpose' or 'normal'."""
+        k = {"forward": 0, "transpose": 1, "normal": 2}[kind]
+        ms = ctypes.c_double()
+        _check(self.ctx, lib.admm_time_pass(self.ctx, k, int(reps), ctypes.byref(ms)))
+        return ms.value
 
     def enable_timing(self, on: bool = True):
         _check(self.ctx, lib.admm_enable_timing(self.ctx, 1 if on else 0))

@@ -1438,6 +1438,49 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
   GUARD_END(ctx)
 }
 
+admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms_out) {
+  if (!ctx || !ms_out || kind < 0 || kind > 2 || reps < 1) return set_err(ctx, ADMM_E_ARG, "bad argument");
+  GUARD_BEGIN
+  PassArgs pa = ctx->pass_args(ctx->mat32);
+  int mode = PASS_CG;
+  if (kind == 0) {
+    mode = PASS_OBJ;
+    pa.src = ctx->d_z;
+    pa.src_per_scen = 0;
+    pa.part = nullptr;
+  } else if (kind == 1) {
+    mode = PASS_RMATVEC;
+    launch_fill_f32(ctx->d_mvec, 1.0f, ctx->H.mmax, ctx->stream);
+    pa.tin = ctx->d_mvec;
+    pa.objpart = nullptr;
+  } else {
+    pa.src = ctx->d_v;
+    pa.src_per_scen = 1;
+    pa.objpart = nullptr;
+  }
+  hipEvent_t e0, e1;
+  check(hipEventCreate(&e0), "hipEventCreate");
+  check(hipEventCreate(&e1), "hipEventCreate");
+  float ms = 0.0f;
+  try {
+    launch_pass(mode, pa, 0, ctx->T, ctx->stream);  // warm
+    check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+    for (int r = 0; r < reps; ++r) launch_pass(mode, pa, 0, ctx->T, ctx->stream);
+    check(hipEventRecord(e1, ctx->stream), "hipEventRecord");
+    check(hipEventSynchronize(e1), "hipEventSynchronize");
+    check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = static_cast<double>(ms) / reps;
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
 admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms) {
   if (!ctx) return ADMM_E_ARG;
   if (threads) *threads = ctx->pass_threads;

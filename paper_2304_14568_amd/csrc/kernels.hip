@@ -343,8 +343,15 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
     else
       for (int j = threadIdx.x; j < n; j += NT) static_cast<unsigned long long*>(qacc)[j] = 0ull;
   }
+  if constexpr (MODE == PASS_RMATVEC && ACC == ACC_FIX64) {
+    // the given t bounds the contributions: max |t_i| over the tile's rows
+    const int rb0 = static_cast<int>(sc.row_base);
+    for (int r = t.row_begin + static_cast<int>(threadIdx.x); r < t.row_end; r += NT)
+      vmax = fmaxf(vmax, fabsf(a.tin[a.mat.rorig[rb0 + r]]));
+  }
   // fixed-point scale: every partial column sum of this tile, and every single
-  // contribution, is below cmax * (wmax * max|v| + pmax) < 2^50 / 2^F
+  // contribution, is below cmax * (wmax * max|v| + pmax) < 2^50 / 2^F (for the
+  // transpose product: cmax * max|t_i|)
   double fscale = 1.0, funscale = 1.0;
   if constexpr (kScatter && ACC == ACC_FIX64) {
 #pragma unroll
@@ -354,7 +361,9 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
     float vm = 0.0f;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) vm = fmaxf(vm, vmax_sh[w]);
-    const double tb = static_cast<double>(t.wmax) * vm + (MODE == PASS_GRAD ? static_cast<double>(t.pmax) : 0.0);
+    const double tb = MODE == PASS_RMATVEC
+                          ? static_cast<double>(vm)
+                          : static_cast<double>(t.wmax) * vm + (MODE == PASS_GRAD ? static_cast<double>(t.pmax) : 0.0);
     const double bound = 1.0625 * tb * static_cast<double>(t.cmax);
     if (bound > 0.0 && isfinite(bound)) {
       const int F = 49 - ilogb(bound);
@@ -445,7 +454,10 @@ static void launch_acc(const PassArgs& a, int tb, int tc, hipStream_t st, hipEve
   if constexpr (MODE == PASS_OBJ || MODE == PASS_MATVEC) {
     launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st, e0, e1);  // no column accumulators
   } else if constexpr (MODE == PASS_RMATVEC) {
-    launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st, e0, e1);  // no bound on the given t
+    if (a.acc == ACC_FIX64)
+      launch_nt<VK, C16, MODE, ACC_FIX64>(a, tb, tc, st, e0, e1);  // scale from max |t_i| of the tile
+    else
+      launch_nt<VK, C16, MODE, ACC_F64>(a, tb, tc, st, e0, e1);
   } else {
     if (a.acc == ACC_FIX64)
       launch_nt<VK, C16, MODE, ACC_FIX64>(a, tb, tc, st, e0, e1);
