@@ -120,6 +120,29 @@ struct admm_ctx {
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 
+  // A sparse pass over the tiles [tile_begin, tile_begin + tile_count), one
+  // launch per patient they cover, each sized for that patient's spot count
+  // (the LDS of a workgroup holds n floats of v and n accumulators, so sizing
+  // every launch for the largest patient of a batch would cost occupancy).
+  // e0 / e1 stamp the start of the first and the end of the last launch.
+  void pass_launch(int mode, PassArgs pa, int tile_begin, int tile_count, hipEvent_t e0 = nullptr,
+                   hipEvent_t e1 = nullptr) const {
+    const int tile_end = tile_begin + tile_count;
+    int first = -1, last = -1;
+    for (int p = 0; p < P; ++p)
+      if (H.pat[p].tile_end > tile_begin && H.pat[p].tile_begin < tile_end) {
+        if (first < 0) first = p;
+        last = p;
+      }
+    for (int p = first; p >= 0 && p <= last; ++p) {
+      const Pat& pt = H.pat[p];
+      const int b = std::max(tile_begin, pt.tile_begin), e = std::min(tile_end, pt.tile_end);
+      if (e <= b) continue;
+      pa.nmax = pt.n;
+      launch_pass(mode, pa, b, e - b, stream, p == first ? e0 : nullptr, p == last ? e1 : nullptr);
+    }
+  }
+
   PassArgs pass_args(const MatDev& m) const {
     PassArgs a{};
     a.tiles = d_tiles;
@@ -243,7 +266,7 @@ struct admm_ctx {
     pa.src = d_z;
     pa.src_per_scen = 0;
     pa.ps = d_ps;
-    launch_pass(PASS_GRAD, pa, 0, T, stream);
+    pass_launch(PASS_GRAD, pa, 0, T);
     VecArgs va = vec_args(stop_enabled);
     launch_reduce(RED_HEAD, va, 0, NB, stream);
     launch_head_scalars(va, G, cg_setup, stream);
@@ -272,9 +295,9 @@ struct admm_ctx {
       pa.ps = d_ps;
       pa.objpart = nullptr;
       if (with_events)
-        launch_pass(PASS_CG, pa, 0, T, stream, ev[2 * k], ev[2 * k + 1]);
+        pass_launch(PASS_CG, pa, 0, T, ev[2 * k], ev[2 * k + 1]);
       else
-        launch_pass(PASS_CG, pa, 0, T, stream);
+        pass_launch(PASS_CG, pa, 0, T);
       va.step = k;
       launch_reduce(RED_CG, va, 0, NB, stream);
       launch_cg_update(va, NB, stream);
@@ -406,9 +429,9 @@ struct admm_ctx {
           pa.src = d_v;
           pa.src_per_scen = 1;
           pa.objpart = nullptr;
-          launch_pass(PASS_CG, pa, 0, T, stream);
+          pass_launch(PASS_CG, pa, 0, T);
           check(hipEventRecord(e0, stream), "hipEventRecord");
-          for (int r = 0; r < reps; ++r) launch_pass(PASS_CG, pa, 0, T, stream);
+          for (int r = 0; r < reps; ++r) pass_launch(PASS_CG, pa, 0, T);
           check(hipEventRecord(e1, stream), "hipEventRecord");
           check(hipEventSynchronize(e1), "hipEventSynchronize");
           float ms = 0.0f;
@@ -467,7 +490,7 @@ struct admm_ctx {
     PassArgs pa = pass_args(mat32);
     pa.src = d_pvec;
     pa.src_per_scen = 0;
-    launch_pass(grad_dev ? PASS_GRAD : PASS_OBJ, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, stream);
+    pass_launch(grad_dev ? PASS_GRAD : PASS_OBJ, pa, pt.tile_begin, pt.tile_end - pt.tile_begin);
     if (grad_dev)
       launch_gsum(d_scen, d_pat, d_pblk, d_tiles, d_part, pt.blk_begin, pt.nblk, 2.0f, grad_dev, stream);
     launch_objsum(d_tiles, d_objpart, pt.tile_begin, pt.tile_end - pt.tile_begin, d_scratch, stream);
@@ -870,7 +893,7 @@ admm_status admm_warm_start(admm_ctx* ctx, int32_t patient, const double* z0, do
     PassArgs pa = ctx->pass_args(ctx->mat32);
     pa.src = ctx->d_z;
     pa.src_per_scen = 0;
-    launch_pass(PASS_GRAD, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, ctx->stream);
+    ctx->pass_launch(PASS_GRAD, pa, pt.tile_begin, pt.tile_end - pt.tile_begin);
     VecArgs va = ctx->vec_args(0);
     const Scen& s0 = ctx->H.scen[pt.scen_begin];
     const Scen& s1 = ctx->H.scen[pt.scen_begin + pt.num_scen - 1];
@@ -908,7 +931,7 @@ admm_status admm_spot_features(admm_ctx* ctx, int32_t patient, const uint8_t* vo
         PassArgs pa = ctx->pass_args(ctx->mat32);
         pa.tin = d_ind + static_cast<size_t>(c) * m;
         pa.objpart = nullptr;
-        launch_pass(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+        ctx->pass_launch(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
         VecArgs va = ctx->vec_args(0);
         va.out = ctx->d_pvec2 + pt.zvec_base;
         launch_reduce(RED_RMAT, va, sc.blk_begin, sc.nblk, ctx->stream);
@@ -1106,7 +1129,7 @@ admm_status admm_matvec(admm_ctx* ctx, int32_t patient, int32_t scen, const floa
   pa.src_per_scen = 0;
   pa.tout = ctx->d_mvec;
   pa.objpart = nullptr;
-  launch_pass(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+  ctx->pass_launch(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
   check(hipMemcpyAsync(out, ctx->d_mvec, sizeof(float) * pt.m, hipMemcpyDeviceToHost, ctx->stream), "D2H");
   check(hipStreamSynchronize(ctx->stream), "sync");
   return ADMM_OK;
@@ -1160,7 +1183,7 @@ admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, con
       pa.src_per_scen = 0;
       pa.tout = ctx->d_mvec;
       pa.objpart = nullptr;
-      launch_pass(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+      ctx->pass_launch(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
       launch_dose_hist(ctx->d_mvec, d_grp, m, G, nbins, inv_w, d_cnt + per * s, d_sum + static_cast<size_t>(G) * s,
                        d_key + static_cast<size_t>(G) * s, ctx->stream);
       if (dose_out)
@@ -1205,7 +1228,7 @@ admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const flo
   PassArgs pa = ctx->pass_args(ctx->mat32);
   pa.tin = ctx->d_mvec;
   pa.objpart = nullptr;
-  launch_pass(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+  ctx->pass_launch(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
   VecArgs va = ctx->vec_args(0);
   va.out = ctx->d_pvec2 + pt.zvec_base;
   launch_reduce(RED_RMAT, va, sc.blk_begin, sc.nblk, ctx->stream);
@@ -1232,7 +1255,7 @@ admm_status admm_normal_apply(admm_ctx* ctx, int32_t patient, int32_t scen, int3
   pa.src = ctx->d_v;
   pa.src_per_scen = 1;
   pa.objpart = nullptr;
-  launch_pass(PASS_CG, pa, sc.tile_begin, sc.tile_end - sc.tile_begin, ctx->stream);
+  ctx->pass_launch(PASS_CG, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
   VecArgs va = ctx->vec_args(0);
   va.out = ctx->d_pvec2 + pt.zvec_base;
   va.rho_out = ctx->rho[patient];
@@ -1273,7 +1296,7 @@ admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, 
       pa.src = ctx->d_pvec3;
       pa.src_per_scen = 0;
       pa.objpart = nullptr;
-      launch_pass(PASS_CG, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, s);
+      ctx->pass_launch(PASS_CG, pa, pt.tile_begin, pt.tile_end - pt.tile_begin);
       launch_gsum(ctx->d_scen, ctx->d_pat, ctx->d_pblk, ctx->d_tiles, ctx->d_part, pt.blk_begin, pt.nblk, 2.0f, g, s);
       check(hipMemcpyAsync(v.data(), g, sizeof(float) * n, hipMemcpyDeviceToHost, s), "D2H");
       check(hipStreamSynchronize(s), "sync");
@@ -1308,7 +1331,7 @@ admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, 
       pa.src = ctx->d_pvec3;
       pa.src_per_scen = 0;
       pa.part = nullptr;  // objective only
-      launch_pass(PASS_OBJ, pa, pt.tile_begin, pt.tile_end - pt.tile_begin, s);
+      ctx->pass_launch(PASS_OBJ, pa, pt.tile_begin, pt.tile_end - pt.tile_begin);
       launch_objsum(ctx->d_tiles, ctx->d_objpart, pt.tile_begin, pt.tile_end - pt.tile_begin, ctx->d_scratch, s);
       check(hipMemcpyAsync(ctx->h_scr, ctx->d_scratch, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
       check(hipStreamSynchronize(s), "sync");
@@ -1463,9 +1486,9 @@ admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms
   check(hipEventCreate(&e1), "hipEventCreate");
   float ms = 0.0f;
   try {
-    launch_pass(mode, pa, 0, ctx->T, ctx->stream);  // warm
+    ctx->pass_launch(mode, pa, 0, ctx->T);  // warm
     check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-    for (int r = 0; r < reps; ++r) launch_pass(mode, pa, 0, ctx->T, ctx->stream);
+    for (int r = 0; r < reps; ++r) ctx->pass_launch(mode, pa, 0, ctx->T);
     check(hipEventRecord(e1, ctx->stream), "hipEventRecord");
     check(hipEventSynchronize(e1), "hipEventSynchronize");
     check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");

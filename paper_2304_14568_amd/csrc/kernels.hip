@@ -426,8 +426,8 @@ static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStrea
       (void)hipGetLastError();
     attr_done = true;
   }
-  if (e0 != nullptr)
-    // events stamped by the dispatch itself: kernel start and end
+  if (e0 != nullptr || e1 != nullptr)
+    // events stamped by the dispatch itself: kernel start and / or end
     hipExtLaunchKernelGGL(kern, dim3(tile_count), dim3(NT), smem, st, e0, e1, 0, a, tile_begin);
   else
     hipLaunchKernelGGL(kern, dim3(tile_count), dim3(NT), smem, st, a, tile_begin);

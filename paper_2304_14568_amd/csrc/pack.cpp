@@ -85,7 +85,16 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
   int64_t nnz_all = 0;
   for (int p = 0; p < num_patients; ++p)
     for (int s = 0; s < probs[p].num_scen; ++s) nnz_all += probs[p].A[s].nnz;
-  int64_t tile_nnz = o.tile_nnz > 0 ? o.tile_nnz : nnz_all / (256 * 8);
+  // about 2048 tiles (8 workgroups per CU) for every patient: the passes are
+  // launched per patient, so a small patient in a batch must not get a few
+  // huge tiles sized for the whole batch
+  int64_t nnz_min_pat = nnz_all;
+  for (int p = 0; p < num_patients; ++p) {
+    int64_t np = 0;
+    for (int s = 0; s < probs[p].num_scen; ++s) np += probs[p].A[s].nnz;
+    nnz_min_pat = std::min(nnz_min_pat, np);
+  }
+  int64_t tile_nnz = o.tile_nnz > 0 ? o.tile_nnz : nnz_min_pat / (256 * 8);
   tile_nnz = std::max<int64_t>(8192, std::min<int64_t>(tile_nnz, 1 << 22));
   const int64_t tile_chunks = std::max<int64_t>(1, tile_nnz / 4);
 

@@ -177,13 +177,20 @@ def cmd_batch(args):
     checks = []
     for k, P in enumerate(Ps):
         S1 = Solver(P, xupdate="cg", precision="fp32", max_iter=args.max_iter, stream=stream)
+        _sync()
+        t0 = time.perf_counter()
         z1, i1, _ = S1.solve()
+        _sync()
+        t_single = time.perf_counter() - t0
         f_batch = S1.objective(zs[k])
         checks.append(dict(obj_single_fp32=i1[0]["obj"], obj_batch_at_fp32=f_batch,
-                           rel_diff=(f_batch - i1[0]["obj"]) / i1[0]["obj"]))
+                           rel_diff=(f_batch - i1[0]["obj"]) / i1[0]["obj"], single_fp32_cg_solve_s=t_single,
+                           single_iters=i1[0]["iter"]))
         S1.close()
         print(f"[batch] patient {k}: batch {f_batch:.6f} vs single fp32 {i1[0]['obj']:.6f}", flush=True)
     res["cross_check"] = checks
+    res["sum_single_fp32_cg_solve_s"] = float(sum(c["single_fp32_cg_solve_s"] for c in checks))
+    res["batched_over_single_fp32_time_ratio"] = res["solve_s"] / res["sum_single_fp32_cg_solve_s"]
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)
@@ -221,16 +228,30 @@ def cmd_precision(args):
             _sync()
             dt = time.perf_counter() - t0
             z = zs[0]
+            k_hit = next((t["iter"] for t in S.trace() if (t["obj"] - fstar) / fstar <= 1e-5), None)
+            t_hit = None
+            if k_hit is not None:
+                S.reset()
+                _sync()
+                t0 = time.perf_counter()
+                S.iterate(k_hit)
+                _sync()
+                t_hit = time.perf_counter() - t0
             ev = evaluate(S, P, z)
             f = S.objective(z)
         tmax = float(np.nanmax(ev["metrics"]["Dmax"][:, tg]))
         omax = float(np.nanmax(ev["metrics"]["Dmax"][:, og]))
-        row = dict(precision=prec, iters=info[0]["iter"], solve_s=dt, obj_rel_err=(f - fstar) / fstar,
+        row = {"precision": prec, "iters": info[0]["iter"], "solve_s": dt, "iters_to_1e-5": k_hit,
+               "time_to_1e-5_s": t_hit}
+        row.update(obj_rel_err=(f - fstar) / fstar,
                    z_rel_err_l2=float(np.linalg.norm(z - xstar) / np.linalg.norm(xstar)),
                    max_target_dose_rel_err=(tmax - ref_tmax) / ref_tmax,
                    max_oar_dose_rel_err=(omax - ref_omax) / ref_omax)
         rows.append(row)
         print(f"[precision] {json.dumps(row)}", flush=True)
+    t32 = rows[0]["time_to_1e-5_s"]
+    for r in rows:
+        r["time_to_1e-5_ratio_vs_fp32"] = (r["time_to_1e-5_s"] / t32) if (t32 and r["time_to_1e-5_s"]) else None
     res = dict(workload=f"hn_full({args.seed})", reference="oracle x*, f* (tests/golden)",
                ref_max_target_dose=ref_tmax, ref_max_oar_dose=ref_omax, rows=rows)
     if args.out:
