@@ -153,7 +153,9 @@ typedef struct {
 admm_status admm_default_options(admm_options* opts);
 admm_status pgd_default_options(pgd_options* popts);
 
-/* Validate the problem on the host, copy it to the device (length-sorted CSR,
+/* Validate the problem on the host (n <= 13 600 spots per patient: the sparse
+ * pass keeps an n-vector and n column accumulators in the LDS of a workgroup),
+ * copy it to the device (length-sorted CSR,
  * optional bf16/fp16 copy of the values with per-row scales), and prepare the
  * ADMM state at z = P(0), y = 0.  On failure *out = NULL and nothing leaks. */
 admm_status admm_setup(const admm_problem* prob, const admm_options* opts, admm_ctx** out);

@@ -608,6 +608,13 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     st = validate_problem(&probs[p], &msg);
     if (st != ADMM_OK) return set_err(nullptr, st, "patient " + std::to_string(p) + ": " + msg);
   }
+  // the sparse pass keeps v (n floats) and one 64-bit column accumulator per
+  // spot of a patient in the 160 KiB of LDS of a workgroup
+  for (int p = 0; p < num_patients; ++p)
+    if (pass_smem_bytes(probs[p].n, ACC_FIX64) > 163840)
+      return set_err(nullptr, ADMM_E_ARG,
+                     "patient " + std::to_string(p) + ": n = " + std::to_string(probs[p].n) +
+                         " spots exceeds the 13 600 the sparse pass holds in LDS");
   std::unique_ptr<admm_ctx> c;
   try {
     c.reset(new admm_ctx());

@@ -164,3 +164,16 @@ def test_default_options_documented_values():
     assert o.bb == 1 and o.z_mode == 0 and o.bb_clamp == 0.0
     assert o.cg_max == 8 and o.max_iter == 1000
     assert o.xupdate == -1  # automatic choice between the dense and the CG x-update
+
+
+def test_too_many_spots_for_the_sparse_pass_rejected():
+    import paper_2304_14568_amd as A
+    from tests._helpers import problem_from_dense
+    n = 13700
+    D = np.zeros((2, n))
+    D[0, 0] = 1.0
+    D[1, 1] = 1.0
+    P = problem_from_dense([D], w=[1.0, 1.0], p=[1.0, 1.0])
+    with pytest.raises(A.AdmmError) as e:
+        A.Solver(P)
+    assert e.value.code == -1 and "13 600" in str(e.value)
