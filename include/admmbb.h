@@ -147,6 +147,10 @@ typedef struct {
   double obj_rel_tol;        /* stop when |f_k - f_{k+1}| <= tol |f_k|; default 1e-5 */
   int32_t max_iter;          /* default 10000 */
   int32_t max_trials;        /* backtracking trials per iteration; default 60 */
+  int32_t dense;             /* -1 (default): the dense form when the context holds the dense
+                                x-update's matrices, else the sparse passes; 0: sparse passes;
+                                1: dense form (ADMM_E_ARG when the context has no dense matrices) */
+  int32_t reserved;          /* 0 */
 } pgd_options;
 
 /* Fill opts / popts with the defaults documented above. */
@@ -188,7 +192,14 @@ admm_status admm_iterate(admm_ctx* ctx, int32_t k, admm_info* info);
 admm_status admm_solve(admm_ctx* ctx, double* z_out, admm_info* info);
 
 /* Projected gradient descent with Armijo backtracking for one patient, from
- * P(x0) (x0 NULL: 0); x_out: n doubles. */
+ * P(x0) (x0 NULL: 0); x_out: n doubles.
+ * Sparse form: x in fp32, one objective pass over the A_s per trial step, host
+ * loop.  Dense form: f(x) = x^T (sum_s G_s) x - g0^T x + const from the packed
+ * fp64 sum of the Gram matrices, x in fp64, the whole iteration on the device:
+ * 8 trial steps per round share one read of sum_s G_s, which also yields the
+ * gradient at the accepted point; the accepted step is the first (largest) one
+ * that passes the test, as in the sequential backtracking.
+ * info: iter = accepted steps, obj = f(x), tau = initial step alpha, status. */
 admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, const double* x0, double* x_out,
                       admm_info* info);
 

@@ -74,7 +74,8 @@ class InfoC(ctypes.Structure):
 
 class PgdOptionsC(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("obj_rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_trials", ctypes.c_int32)]
+                ("obj_rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_trials", ctypes.c_int32),
+                ("dense", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _load():
@@ -300,6 +301,8 @@ class Solver:
         o = PgdOptionsC()
         lib.pgd_default_options(ctypes.byref(o))
         for k, v in kw.items():
+            if k == "dense" and isinstance(v, str):
+                v = {"auto": -1, "sparse": 0, "dense": 1}[v]
             setattr(o, k, v)
         x = np.zeros(self.n[patient])
         x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)

@@ -89,6 +89,9 @@ struct admm_ctx {
   std::vector<double> factored_rho;  // per patient: penalty of the cached inverse
   std::vector<int> chunk_scen;       // per patient: scenarios per set-up chunk
   double factor_ms = 0.0;            // time of the last set-up of the cached inverses
+  // dense PGD work buffers, sized for the largest patient on first use
+  double* d_pgd = nullptr;
+  PgdDevState* d_pgdst = nullptr;
 
   template <class T>
   T* alloc(size_t count) {
@@ -578,6 +581,8 @@ admm_status pgd_default_options(pgd_options* o) {
   o->obj_rel_tol = 1e-5;
   o->max_iter = 10000;
   o->max_trials = 60;
+  o->dense = -1;
+  o->reserved = 0;
   return ADMM_OK;
 }
 
@@ -1273,6 +1278,100 @@ admm_status admm_normal_apply(admm_ctx* ctx, int32_t patient, int32_t scen, int3
   GUARD_END(ctx)
 }
 
+namespace {
+
+// PGD on the packed fp64 sum of the Gram matrices, every iteration on the device.
+admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, const double* x0, double* x_out,
+                      admm_info* info) {
+  const Pat& pt = ctx->H.pat[patient];
+  const int n = pt.n;
+  hipStream_t s = ctx->stream;
+  if (!ctx->d_pgd) {
+    int64_t words = 0;
+    for (const Pat& q : ctx->H.pat) {
+      const int64_t nj = q.fobj_end - q.fobj_begin, nbl = (q.npad + 255) / 256;
+      words = std::max(words, (2 + 2 * kPgdK) * static_cast<int64_t>(q.npad) + nj * kPgdK * 128 + q.nbk * kPgdK +
+                                  nbl * kPgdK);
+    }
+    ctx->d_pgd = ctx->alloc<double>(static_cast<size_t>(words));
+    ctx->d_pgdst = ctx->alloc<PgdDevState>(1);
+  }
+  PgdArgs a{};
+  a.Gp = ctx->d_Gp + pt.gpack_off;
+  a.g0 = ctx->d_g0 + pt.zvec_base;
+  a.lb = ctx->d_lb + pt.zvec_base;
+  a.ub = ctx->d_ub + pt.zvec_base;
+  a.jobs = ctx->d_fjobs + pt.fobj_begin;
+  a.njobs = pt.fobj_end - pt.fobj_begin;
+  a.nb = pt.nbk;
+  a.n = n;
+  a.np = pt.npad;
+  a.nblocks = (a.np + 255) / 256;
+  a.x = ctx->d_pgd;
+  a.g = a.x + a.np;
+  a.xc = a.g + a.np;
+  a.u = a.xc + static_cast<int64_t>(kPgdK) * a.np;
+  a.part = a.u + static_cast<int64_t>(kPgdK) * a.np;
+  a.fpart = a.part + static_cast<int64_t>(a.njobs) * kPgdK * 128;
+  a.gdpart = a.fpart + static_cast<int64_t>(a.nb) * kPgdK;
+  a.st = ctx->d_pgdst;
+  a.fconst = pt.fconst;
+  a.beta = o.beta;
+  a.gamma = o.gamma;
+  a.tol = o.obj_rel_tol;
+  a.max_iter = o.max_iter;
+  a.max_trials = o.max_trials;
+
+  // host sources stay alive and unchanged until the final synchronisation
+  PgdDevState h0{}, h{};
+  h0.alpha = o.alpha > 0 ? o.alpha : 1.0;
+  check(hipMemcpyAsync(a.st, &h0, sizeof(h0), hipMemcpyHostToDevice, s), "H2D");
+  std::vector<double> pv, hv(n);
+  launch_fill_f64(a.x, 0.0, 2 * static_cast<int64_t>(a.np), s);  // x and g, with their zero padding
+  if (!(o.alpha > 0)) {
+    // alpha = 10 / lambda_max(H), H = 2 sum_s G_s, 30 power iterations
+    pv.assign(n, 1.0 / std::sqrt(static_cast<double>(n)));
+    check(hipMemcpyAsync(a.x, pv.data(), sizeof(double) * n, hipMemcpyHostToDevice, s), "H2D");
+    for (int it = 0; it < 30; ++it) launch_pgd_power(a, a.x, s);
+  }
+  for (int j = 0; j < n; ++j) {
+    const double v = x0 ? x0[j] : 0.0;
+    hv[j] = std::min(std::max(v, static_cast<double>(ctx->H.lb[pt.zvec_base + j])),
+                     static_cast<double>(ctx->H.ub[pt.zvec_base + j]));
+  }
+  check(hipMemcpyAsync(a.x, hv.data(), sizeof(double) * n, hipMemcpyHostToDevice, s), "H2D");
+  launch_fill_f64(a.g, 0.0, n, s);
+  static_assert(kPgdK % 2 == 0, "sub-buffers of the PGD work area stay 16-byte aligned");
+  launch_pgd_round(a, 1, s);
+  // every round either accepts a step or rejects kPgdK trial steps, so the
+  // device state reaches done within this many rounds
+  const int64_t max_rounds =
+      1 + static_cast<int64_t>(o.max_iter) * ((o.max_trials + kPgdK - 1) / kPgdK);
+  constexpr int kChunk = 16;
+  for (int64_t r = 1; r <= max_rounds; r += kChunk) {
+    const int64_t c = std::min<int64_t>(kChunk, max_rounds - r + 1);
+    for (int64_t k = 0; k < c; ++k) launch_pgd_round(a, 0, s);
+    check(hipGetLastError(), "PGD launch");
+    check(hipMemcpyAsync(&h, a.st, sizeof(h), hipMemcpyDeviceToHost, s), "D2H");
+    check(hipStreamSynchronize(s), "sync");
+    if (h.done) break;
+  }
+  check(hipMemcpyAsync(&h, a.st, sizeof(h), hipMemcpyDeviceToHost, s), "D2H");
+  if (x_out) check(hipMemcpyAsync(x_out, a.x, sizeof(double) * n, hipMemcpyDeviceToHost, s), "D2H");
+  check(hipStreamSynchronize(s), "sync");
+  const bool converged = h.done && h.status == 1;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->iter = h.iter;
+    info->obj = h.f;
+    info->tau = h.alpha;
+    info->status = converged ? ADMM_OK : ADMM_MAX_ITER;
+  }
+  return converged ? ADMM_OK : ADMM_MAX_ITER;
+}
+
+}  // namespace
+
 admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, const double* x0, double* x_out,
                       admm_info* info) {
   admm_status st = check_patient(ctx, patient);
@@ -1281,8 +1380,15 @@ admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, 
   pgd_default_options(&o);
   if (popts) o = *popts;
   if (!(o.beta > 0 && o.beta < 1) || !(o.gamma > 0 && o.gamma < 1) || o.max_trials < 1 || o.max_iter < 0 ||
-      !(o.obj_rel_tol >= 0) || !std::isfinite(o.alpha))
+      !(o.obj_rel_tol >= 0) || !std::isfinite(o.alpha) || o.dense < -1 || o.dense > 1)
     return set_err(ctx, ADMM_E_ARG, "invalid PGD options");
+  if (o.dense == 1 && !ctx->dense)
+    return set_err(ctx, ADMM_E_ARG, "dense PGD needs a context set up with the dense x-update");
+  if (o.dense != 0 && ctx->dense) {
+    GUARD_BEGIN
+    return pgd_dense(ctx, o, patient, x0, x_out, info);
+    GUARD_END(ctx)
+  }
   GUARD_BEGIN
   const Pat& pt = ctx->H.pat[patient];
   const int n = pt.n;

@@ -44,12 +44,6 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-__device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // ---------------------------------------------------------------------------
 // Gram matrix
 // ---------------------------------------------------------------------------

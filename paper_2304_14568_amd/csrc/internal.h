@@ -255,4 +255,42 @@ void launch_fobj(const FactorArgs& f, const float* z, int njobs, hipStream_t st)
 void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
                       double* sums, uint32_t* maxkey, hipStream_t st);
 
+// ---- dense PGD (pgd_dense.hip) ----
+constexpr int kPgdK = 8;  // backtracking steps evaluated per round
+
+struct PgdDevState {
+  double f;       // objective at x
+  double t_base;  // step of the first trial point of the next round
+  double alpha;   // initial step of every iteration
+  int32_t iter;   // accepted steps
+  int32_t trials; // rejected trial steps at the current x
+  int32_t done;
+  int32_t status; // 1 converged, 2 no step accepted within max_trials, 3 iteration limit
+  int32_t pick;   // trial point accepted by the last round, -1 none
+  int32_t pad;
+};
+
+struct PgdArgs {
+  const double* Gp;  // sum_s G_s of the patient, packed upper tiles, fp64
+  const double* g0;  // 2 sum_s A_s^T c_s W p of the patient, fp64
+  const float* lb;
+  const float* ub;
+  const XJob* jobs;  // the patient's packed tiles in packed order
+  int32_t njobs, nb, n, nblocks;  // tiles, block rows, spots, 256-spot blocks of np
+  int32_t np, pad;   // n rounded up to whole 64-blocks: length of every vector below
+  double* x;         // np, zero beyond n
+  double* g;         // np, gradient at x
+  double* xc;        // kPgdK x np trial points, zero beyond n
+  double* u;         // kPgdK x np: S x_k
+  double* part;      // per tile and trial point: 64 row and 64 column products
+  double* fpart;     // [k][block row]
+  double* gdpart;    // [k][block]
+  PgdDevState* st;
+  double fconst, beta, gamma, tol;
+  int32_t max_iter, max_trials;
+};
+
+void launch_pgd_power(const PgdArgs& a, double* v, hipStream_t st);
+void launch_pgd_round(const PgdArgs& a, int first, hipStream_t st);
+
 }  // namespace admmbb
