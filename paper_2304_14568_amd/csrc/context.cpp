@@ -1325,6 +1325,7 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
   // host sources stay alive and unchanged until the final synchronisation
   PgdDevState h0{}, h{};
   h0.alpha = o.alpha > 0 ? o.alpha : 1.0;
+  h0.pick = -1;
   check(hipMemcpyAsync(a.st, &h0, sizeof(h0), hipMemcpyHostToDevice, s), "H2D");
   std::vector<double> pv, hv(n);
   launch_fill_f64(a.x, 0.0, 2 * static_cast<int64_t>(a.np), s);  // x and g, with their zero padding
@@ -1342,6 +1343,7 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
   check(hipMemcpyAsync(a.x, hv.data(), sizeof(double) * n, hipMemcpyHostToDevice, s), "H2D");
   launch_fill_f64(a.g, 0.0, n, s);
   static_assert(kPgdK % 2 == 0, "sub-buffers of the PGD work area stay 16-byte aligned");
+  launch_pgd_cand(a, s);  // t_base = 0: every trial point is x
   launch_pgd_round(a, 1, s);
   // every round either accepts a step or rejects kPgdK trial steps, so the
   // device state reaches done within this many rounds

@@ -291,6 +291,7 @@ struct PgdArgs {
 };
 
 void launch_pgd_power(const PgdArgs& a, double* v, hipStream_t st);
+void launch_pgd_cand(const PgdArgs& a, hipStream_t st);
 void launch_pgd_round(const PgdArgs& a, int first, hipStream_t st);
 
 }  // namespace admmbb

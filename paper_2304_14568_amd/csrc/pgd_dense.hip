@@ -4,14 +4,13 @@
 // With S = sum_s G_s (packed upper 64 x 64 tiles, fp64) the objective and its
 // gradient are f(x) = x^T S x - g0^T x + const and grad f(x) = 2 S x - g0.
 // One round evaluates kPgdK backtracking steps at once:
-//   k_pgd_cand    trial points x_k = P(x - t_k g), t_k = t_base gamma^k, and the
-//                 partial sums of g^T (x_k - x)
 //   k_pgd_tiles   for every tile T of S and every k: T x_k,J and T^T x_k,I,
 //                 one read of S for all kPgdK trial points
 //   k_pgd_rows    u_k = S x_k from the tile products, and f(x_k) partial sums
 //   k_pgd_select  the first k (largest step) with
-//                 f(x_k) <= f(x) + beta g^T (x_k - x) becomes x, with gradient
-//                 2 u_k - g0; stopping tests
+//                 f(x_k) <= f(x) + beta g^T (x_k - x) is accepted; stopping tests
+//   k_pgd_cand    x = x_k with gradient 2 u_k - g0, and the next round's trial
+//                 points x_k = P(x - t_k g), t_k = t_base gamma^k
 // so an iteration whose step is found within kPgdK trials reads S once.
 // A round that accepts nothing retries from the same x with the next kPgdK
 // steps.  The host launches rounds in chunks and reads the state in between.
@@ -39,22 +38,32 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// K trial points and g^T (x_k - x) partial sums, gdpart[k * nblocks + block]
+// Applies the step the last selection accepted (x = x_p, grad f(x) = 2 S x_p - g0,
+// idempotent, also after the stopping test), then, while running, writes the
+// next round's trial points x_k = P(x - t_k g), t_k = t_base gamma^k, and the
+// partial sums of g^T (x_k - x), gdpart[k * nblocks + block].  Vectors are
+// zero beyond n up to np.
 __global__ __launch_bounds__(256) void k_pgd_cand(PgdArgs a) {
-  if (a.st->done) return;
+  const PgdDevState* st = a.st;
   __shared__ double red[4][kPgdK];
   const int j = static_cast<int>(blockIdx.x) * 256 + threadIdx.x;
-  double loc[kPgdK];
-  if (j >= a.n) {
-    // zero padding up to whole 64-blocks (read by the tile products)
-    if (j < a.np)
-#pragma unroll
-      for (int k = 0; k < kPgdK; ++k) a.xc[static_cast<int64_t>(k) * a.np + j] = 0.0;
+  const bool in = j < a.n;
+  // loads that do not depend on the state go out together with it
+  double xj = in ? a.x[j] : 0.0, gj = in ? a.g[j] : 0.0;
+  const double g0j = in ? a.g0[j] : 0.0;
+  const double lo = in ? a.lb[j] : 0.0, hi = in ? a.ub[j] : 0.0;
+  const int p = st->pick;
+  const bool run = !st->done;
+  if (in && p >= 0) {
+    xj = a.xc[static_cast<int64_t>(p) * a.np + j];
+    gj = 2.0 * a.u[static_cast<int64_t>(p) * a.np + j] - g0j;
+    a.x[j] = xj;
+    a.g[j] = gj;
   }
-  if (j < a.n) {
-    const double xj = a.x[j], gj = a.g[j];
-    const double lo = a.lb[j], hi = a.ub[j];
-    double t = a.st->t_base;
+  if (!run) return;
+  double loc[kPgdK];
+  if (in) {
+    double t = st->t_base;
 #pragma unroll
     for (int k = 0; k < kPgdK; ++k) {
       const double v = fmin(fmax(xj - t * gj, lo), hi);
@@ -64,7 +73,10 @@ __global__ __launch_bounds__(256) void k_pgd_cand(PgdArgs a) {
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < kPgdK; ++k) loc[k] = 0.0;
+    for (int k = 0; k < kPgdK; ++k) {
+      if (j < a.np) a.xc[static_cast<int64_t>(k) * a.np + j] = 0.0;
+      loc[k] = 0.0;
+    }
   }
 #pragma unroll
   for (int k = 0; k < kPgdK; ++k) {
@@ -78,42 +90,69 @@ __global__ __launch_bounds__(256) void k_pgd_cand(PgdArgs a) {
   }
 }
 
-// One tile T = S_IJ (I <= J) per workgroup; wave w takes rows 16w..16w+15 of
-// T for T v_k,J and columns 16w..16w+15 for T^T v_k,I, both as products
-// (16 x 64 trial-point rows, zero beyond KC) x (64 x 16 slice of T) on the
-// fp64 16x16x4 MFMA: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of
-// each step and receives D[l / 16 + 4 r][l % 16] in item r.  The k index of
-// the 16 steps is a free permutation of the 64 tile columns (rows), chosen so
-// that every lane loads contiguous doubles.  v_k = v + k * vstride, vstride and
-// the vectors padded with zeros to whole 64-blocks.
+// One tile T = S_IJ (I <= J) per workgroup, staged once through LDS (32 KB,
+// five workgroups per CU) with coalesced 16-byte loads; element (r, c) sits at
+// r * 64 + (c ^ sw(r)), an even swizzle that keeps column pairs together and
+// spreads both read patterns below over distinct banks.
+// Wave w takes rows 16w..16w+15 of T for T v_k,J and columns 16w..16w+15 for
+// T^T v_k,I, both as products (16 x 64 trial-point rows, zero beyond KC) x
+// (64 x 16 slice of T) on the fp64 16x16x4 MFMA: lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16] of each step and receives D[l / 16 + 4 r][l % 16] in
+// item r.  The k index of the 16 steps is a free permutation of the 64 tile
+// columns (rows), chosen so that every lane reads contiguous doubles of the
+// trial points.  v_k = v + k * vstride, vstride and the vectors padded with
+// zeros to whole 64-blocks.
 // part[(t * KC + k) * 128 + i]      = (T v_k,J)_i
 // part[(t * KC + k) * 128 + 64 + i] = (T^T v_k,I)_i   (off-diagonal tiles)
+__device__ __forceinline__ int sw(int r) { return ((2 * r) & 30) ^ (r & 16); }
+
 template <int KC>
 __global__ __launch_bounds__(256) void k_pgd_tiles(PgdArgs a, const double* __restrict__ v, int64_t vstride) {
-  if (a.st->done) return;
+  __shared__ double tl[kT * kT];
+  const int64_t t = blockIdx.x;  // jobs are the tiles in packed order
+  const int tid = threadIdx.x;
+  {
+    // the tile's loads go out first (in bounds whatever the state), so their
+    // latency overlaps that of the state and job reads
+    const double2* T = reinterpret_cast<const double2*>(a.Gp + t * kT * kT);
+    double2 g[8];
+#pragma unroll
+    for (int it = 0; it < 8; ++it) g[it] = T[it * 256 + tid];
+    if (a.st->done) return;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int e = 2 * (it * 256 + tid), r = e / kT, c = e % kT;
+      *reinterpret_cast<double2*>(&tl[r * kT + (c ^ sw(r))]) = g[it];
+    }
+  }
   const XJob job = a.jobs[blockIdx.x];
   const int I = job.ij >> 16, J = job.ij & 0xffff;
-  const int64_t t = blockIdx.x;  // jobs are the tiles in packed order
-  const double* T = a.Gp + t * kT * kT;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = tid & 63, w = tid >> 6;
   const int m = lane & 15, kk = lane >> 4;
   const bool live = m < KC;
   double* out = a.part + t * (KC * 2 * kT);
-  // T v_J: step (s, h) uses tile column 8 s + 2 kk + h
+  // trial-point operands (global, cached): columns of block J, rows of block I
+  double2 vaJ[8], vaI[8];
   {
-    const double2* Tr = reinterpret_cast<const double2*>(T + (16 * w + m) * kT + 2 * kk);
-    const double2* vr = reinterpret_cast<const double2*>(v + m * vstride + J * kT + 2 * kk);
-    double2 tb[8], va[8];
+    const double2* vJ = reinterpret_cast<const double2*>(v + m * vstride + J * kT + 2 * kk);
+    const double2* vI = reinterpret_cast<const double2*>(v + m * vstride + I * kT + 16 * kk);
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      tb[s] = Tr[4 * s];
-      va[s] = live ? vr[4 * s] : make_double2(0.0, 0.0);
+      vaJ[s] = live ? vJ[4 * s] : make_double2(0.0, 0.0);
+      vaI[s] = live ? vI[s] : make_double2(0.0, 0.0);
     }
+  }
+  __syncthreads();
+  // T v_J: step (s, h) uses tile column 8 s + 2 kk + h
+  {
+    const int r = 16 * w + m;
+    const double* Tr = &tl[r * kT];
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[s].x, tb[s].x, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[s].y, tb[s].y, acc, 0, 0, 0);
+      const double2 b = *reinterpret_cast<const double2*>(Tr + ((8 * s + 2 * kk) ^ sw(r)));
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vaJ[s].x, b.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vaJ[s].y, b.y, acc, 0, 0, 0);
     }
     // item r: trial point kk + 4 r, tile row 16 w + m
 #pragma unroll
@@ -123,19 +162,13 @@ __global__ __launch_bounds__(256) void k_pgd_tiles(PgdArgs a, const double* __re
   if (I == J) return;
   // T^T v_I: step s uses tile row 16 kk + s
   {
-    const double* Tc = T + (16 * kk) * kT + 16 * w + m;
-    const double2* vr = reinterpret_cast<const double2*>(v + m * vstride + I * kT + 16 * kk);
-    double tb[16];
-    double2 va[8];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) tb[s] = Tc[s * kT];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) va[s] = live ? vr[s] : make_double2(0.0, 0.0);
+    const int c = 16 * w + m;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[s].x, tb[2 * s], acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[s].y, tb[2 * s + 1], acc, 0, 0, 0);
+      const int r0 = 16 * kk + 2 * s, r1 = r0 + 1;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vaI[s].x, tl[r0 * kT + (c ^ sw(r0))], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vaI[s].y, tl[r1 * kT + (c ^ sw(r1))], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -148,15 +181,22 @@ __global__ __launch_bounds__(256) void k_pgd_tiles(PgdArgs a, const double* __re
 // Four waves take every fourth tile of the block row; fixed summation order.
 template <int KC>
 __global__ __launch_bounds__(256) void k_pgd_rows(PgdArgs a, const double* __restrict__ v, int64_t vstride) {
-  if (a.st->done) return;
   __shared__ double red[4][kT];
   const int I = static_cast<int>(blockIdx.x), k = static_cast<int>(blockIdx.y);
   const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // four independent loads in flight per lane, then a fixed-order sum
   double s = 0.0;
-  for (int J = w; J < a.nb; J += 4) {
-    const int64_t t = J < I ? ptile(J, I, a.nb) : ptile(I, J, a.nb);
-    s += a.part[(t * KC + k) * (2 * kT) + (J < I ? kT : 0) + i];
+  for (int J0 = w; J0 < a.nb; J0 += 16) {
+    double e[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int J = J0 + 4 * q;
+      const int64_t t = J < I ? ptile(J, I, a.nb) : ptile(I, J, a.nb);
+      e[q] = J < a.nb ? a.part[(t * KC + k) * (2 * kT) + (J < I ? kT : 0) + i] : 0.0;
+    }
+    s += (e[0] + e[1]) + (e[2] + e[3]);
   }
+  if (a.st->done) return;  // checked after the (in-bounds) loads are under way
   red[w][i] = s;
   __syncthreads();
   if (w != 0) return;
@@ -171,14 +211,13 @@ __global__ __launch_bounds__(256) void k_pgd_rows(PgdArgs a, const double* __res
   if (i == 0) a.fpart[static_cast<int64_t>(k) * a.nb + I] = d;
 }
 
-// Acceptance, step update and stopping tests, then x and grad f(x) = 2 S x - g0
-// of the accepted point; 2 waves per trial point for the sums.
+// Acceptance, step update and stopping tests (the accepted point is applied by
+// the next k_pgd_cand); 2 waves per trial point for the sums.
 __global__ __launch_bounds__(128 * kPgdK) void k_pgd_select(PgdArgs a, int first) {
   PgdDevState* st = a.st;
   if (st->done) return;
   __shared__ double rf[2 * kPgdK], rd[2 * kPgdK];
   __shared__ double fk[kPgdK], gd[kPgdK];
-  __shared__ int pick;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int k = w >> 1, h = w & 1;
   double f = 0.0, d = 0.0;
@@ -240,16 +279,6 @@ __global__ __launch_bounds__(128 * kPgdK) void k_pgd_select(PgdArgs a, int first
     }
     if (stop) st->done = 1;
     st->pick = p;
-    pick = p;
-  }
-  __syncthreads();
-  const int p = pick;
-  if (p < 0) return;
-  const double* xp = a.xc + static_cast<int64_t>(p) * a.np;
-  const double* up = a.u + static_cast<int64_t>(p) * a.np;
-  for (int j = tid; j < a.n; j += blockDim.x) {
-    a.x[j] = xp[j];
-    a.g[j] = 2.0 * up[j] - a.g0[j];
   }
 }
 
@@ -289,13 +318,17 @@ void launch_pgd_power(const PgdArgs& a, double* v, hipStream_t st) {
   hipLaunchKernelGGL(k_pgd_normalize, dim3(1), dim3(1024), 0, st, a, v);
 }
 
+void launch_pgd_cand(const PgdArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_pgd_cand, dim3(a.nblocks), dim3(256), 0, st, a);
+}
+
 void launch_pgd_round(const PgdArgs& a, int first, hipStream_t st) {
   const double* xc = a.xc;
   const int64_t n = a.np;
-  hipLaunchKernelGGL(k_pgd_cand, dim3(a.nblocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_pgd_tiles<kPgdK>, dim3(a.njobs), dim3(256), 0, st, a, xc, n);
   hipLaunchKernelGGL(k_pgd_rows<kPgdK>, dim3(a.nb, kPgdK), dim3(256), 0, st, a, xc, n);
   hipLaunchKernelGGL(k_pgd_select, dim3(1), dim3(128 * kPgdK), 0, st, a, first);
+  hipLaunchKernelGGL(k_pgd_cand, dim3(a.nblocks), dim3(256), 0, st, a);
 }
 
 }  // namespace admmbb
