@@ -260,8 +260,7 @@ struct admm_ctx {
   void launch_head(int stop_enabled, int cg_setup) {
     if (dense) {
       VecArgs va = vec_args(stop_enabled);
-      launch_fhead(va, NB, stream);
-      launch_fobj(fargs(), d_z, n_fjobs, stream);
+      launch_fheadobj(fargs(), va, n_fjobs, NB, stream);
       launch_head_scalars(va, G, 0, stream);
       return;
     }

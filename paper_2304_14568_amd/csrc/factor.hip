@@ -16,8 +16,9 @@
 //        A_:K = U, A_K: = U^T, A_KK = -P;
 //     after the last block A = -B_s^-1.  The sweep matrix stays symmetric, so
 //     only its upper 64 x 64 tiles are updated (half the work).  k_sweep_store writes M_s = B_s^-1 in fp32.
-//  4. every iteration: k_fhead (pending dual update, right-hand side c_s),
-//     k_fobj (objective at z from the quadratic form), k_xsym + k_xsym_reduce
+//  4. every iteration: k_fheadobj (pending dual update and right-hand sides
+//     c_s, and the objective at z from the quadratic form, in one launch),
+//     k_xsym + k_xsym_reduce
 //     (x_s = M_s c_s).
 // The symmetric matrices used in every iteration (M_s and sum_s G_s) are stored
 // as their upper 64 x 64 tiles only, which halves the bytes each iteration reads.
@@ -382,15 +383,15 @@ __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __rest
 
 // completion of the pending dual update and the right-hand side
 // c_s = b_s + rho/2 z - y_s/2 (one scenario column block of 64 per workgroup)
-__global__ __launch_bounds__(kColBlock) void k_fhead(VecArgs a) {
-  const int bi = static_cast<int>(blockIdx.x);
+// one wave: column block bi of one scenario, lane = column within the block
+__device__ __forceinline__ void fhead_block(const VecArgs& a, int bi, int lane) {
   const Blk bk = a.blk[bi];
   const int g = bk.owner;
   const Scen sc = a.scen[g];
   const Pat pt = a.pat[sc.patient];
   const PatState* ps = a.ps + sc.patient;
   if (ps->stopped) return;
-  const int j = bk.col0 + static_cast<int>(threadIdx.x);
+  const int j = bk.col0 + lane;
   double yy = 0.0;
   if (j < sc.n) {
     const int64_t vi = sc.vec_base + j;
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(kColBlock) void k_fhead(VecArgs a) {
     yy = static_cast<double>(yv) * yv;
   }
   yy = wave_sum_d(yy);
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     double* bp = a.bpart + static_cast<int64_t>(bi) * 8;
     bp[0] = 0.0;
     bp[1] = 0.0;
@@ -414,9 +415,9 @@ __global__ __launch_bounds__(kColBlock) void k_fhead(VecArgs a) {
 
 // objective partial of one packed tile T of sum_s G_s: z_I^T T z_J, doubled off
 // the diagonal; a diagonal tile also carries -g0_I^T z_I.  fp64.
-__global__ __launch_bounds__(256) void k_fobj(FactorArgs f, const float* __restrict__ z) {
+__device__ __forceinline__ void fobj_tile(const FactorArgs& f, const float* __restrict__ z, int jb) {
   __shared__ double zI[kFb], zJ[kFb], red[4];
-  const XJob job = f.fjobs[blockIdx.x];
+  const XJob job = f.fjobs[jb];
   const Pat pt = f.pat[job.g];
   if (f.ps[job.g].stopped) return;
   const int I = job.ij >> 16, J = job.ij & 0xffff;
@@ -451,7 +452,20 @@ __global__ __launch_bounds__(256) void k_fobj(FactorArgs f, const float* __restr
   v = wave_sum_d(v);
   if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
-  if (tid == 0) f.fpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (tid == 0) f.fpart[jb] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// The head of a dense iteration in one launch: workgroups [0, nfobj) take the
+// objective tiles, the rest four column blocks each of the pending dual update
+// and right-hand sides (the two parts are independent).
+__global__ __launch_bounds__(256) void k_fheadobj(FactorArgs f, VecArgs a, int nfobj, int nblk) {
+  const int b = static_cast<int>(blockIdx.x);
+  if (b < nfobj) {
+    fobj_tile(f, a.z, b);
+    return;
+  }
+  const int bi = 4 * (b - nfobj) + static_cast<int>(threadIdx.x >> 6);
+  if (bi < nblk) fhead_block(a, bi, threadIdx.x & 63);
 }
 
 }  // namespace
@@ -501,14 +515,10 @@ void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st
   hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(256), 0, st, f, x);
 }
 
-void launch_fhead(const VecArgs& a, int nblk, hipStream_t st) {
-  if (nblk <= 0) return;
-  hipLaunchKernelGGL(k_fhead, dim3(nblk), dim3(kColBlock), 0, st, a);
-}
-
-void launch_fobj(const FactorArgs& f, const float* z, int njobs, hipStream_t st) {
-  if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_fobj, dim3(njobs), dim3(256), 0, st, f, z);
+void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st) {
+  const int grid = nfobj + (nblk + 3) / 4;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL(k_fheadobj, dim3(grid), dim3(256), 0, st, f, a, nfobj, nblk);
 }
 
 }  // namespace admmbb

@@ -250,8 +250,7 @@ void launch_sweep_store(FactorArgs f, int patient, int scen_begin, int nscen, in
 void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st);
-void launch_fhead(const VecArgs& a, int nblk, hipStream_t st);
-void launch_fobj(const FactorArgs& f, const float* z, int njobs, hipStream_t st);
+void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st);
 void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
                       double* sums, uint32_t* maxkey, hipStream_t st);
 

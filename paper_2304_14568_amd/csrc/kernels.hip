@@ -86,7 +86,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
 template <class F>
 __device__ __forceinline__ double block_list_sum(int count, F item, double* sh) {
   double v[1] = {0.0};
-  for (int i = threadIdx.x; i < count; i += kThreads) v[0] += item(i);
+  // four independent loads in flight, added in the same order as one at a time
+  int i = threadIdx.x;
+  for (; i + 3 * kThreads < count; i += 4 * kThreads) {
+    const double e0 = item(i), e1 = item(i + kThreads), e2 = item(i + 2 * kThreads), e3 = item(i + 3 * kThreads);
+    v[0] += e0;
+    v[0] += e1;
+    v[0] += e2;
+    v[0] += e3;
+  }
+  for (; i < count; i += kThreads) v[0] += item(i);
   block_sum<1>(v, sh);
   return v[0];
 }
