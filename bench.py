@@ -113,8 +113,8 @@ def cpu_baseline(P, seconds_budget: float = 25.0) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--cg-max", type=int, default=8)
     ap.add_argument("--xupdate", default="auto", choices=["auto", "cg", "dense"],

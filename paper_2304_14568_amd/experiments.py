@@ -7,6 +7,7 @@
             objective gap against the oracle's exact minimum where stored.
   precision bf16 / fp16 values inside CG against fp32 and the oracle minimum
   plans     plan quality of ADMM-BB and PGD (Table 2 style criteria, DVH bands)
+  pgd       the dense PGD alone on one patient (paper stop, fixed budget)
   batch     several patients of uneven size in one context (one launch per
             phase for all of them), bf16 values inside CG, a shift-lattice
             scenario set; each patient cross-checked against its own fp32
@@ -329,6 +330,27 @@ def cmd_plans(args):
             json.dump(out, fh, indent=1)
 
 
+def cmd_pgd(args):
+    """The dense PGD on one patient: the paper's stop rule, then a fixed budget
+    of iterations (the form the scaling study times), with the per-iteration rate."""
+    import torch
+    import synth
+    stream = torch.cuda.Stream()
+    P = synth.hn_full(args.seed)
+    with Solver(P, xupdate="dense", stream=stream) as S:
+        S.pgd(0, obj_rel_tol=0.0, max_iter=10)  # warm-up
+        _sync()
+        t0 = time.perf_counter()
+        x, info, st = S.pgd(0)
+        t_stop = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        x, info2, st2 = S.pgd(0, obj_rel_tol=0.0, max_iter=args.iters)
+        t_fix = time.perf_counter() - t0
+    out = dict(n=P.n, scenarios=P.num_scen, paper_stop=dict(iters=info["iter"], obj=info["obj"], s=t_stop),
+               fixed=dict(iters=info2["iter"], obj=info2["obj"], s=t_fix, us_per_iter=1e6 * t_fix / max(1, info2["iter"])))
+    print(json.dumps(out), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2304_14568_amd.experiments")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -338,6 +360,9 @@ def main(argv=None):
     a.add_argument("--no-pgd", action="store_true")
     a.add_argument("--sparse-pgd", action="store_true", help="also time PGD over the sparse matrices")
     a.add_argument("--out", default="")
+    a = sub.add_parser("pgd")
+    a.add_argument("--seed", type=int, default=0)
+    a.add_argument("--iters", type=int, default=1000)
     a = sub.add_parser("plans")
     a.add_argument("--seed", type=int, default=0)
     a.add_argument("--pgd-iters", type=int, default=2048)
@@ -355,7 +380,8 @@ def main(argv=None):
     a.add_argument("--max-iter", type=int, default=1000)
     a.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    {"scaling": cmd_scaling, "batch": cmd_batch, "precision": cmd_precision, "plans": cmd_plans}[args.cmd](args)
+    {"scaling": cmd_scaling, "batch": cmd_batch, "precision": cmd_precision, "plans": cmd_plans,
+     "pgd": cmd_pgd}[args.cmd](args)
 
 
 if __name__ == "__main__":
