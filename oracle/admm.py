@@ -27,8 +27,12 @@ scalar is global over the stacked vectors; at the first iteration, or when
 the combined stop is an AND; the objective is evaluated at the feasible z.
 
 Parity: the end point is pinned by brute force, closed forms and the active-set
-polish (tests); the iterates themselves are not pinned by anything the paper
-prints.
+polish; the paper prints no iterate, so the iterates are pinned by what its
+statement fixes (tests/test_oracle_iterates.py): every x_s minimises the
+subproblem of Sec. 2.2, every z minimises the augmented Lagrangian over the
+box, every BB step is the least-squares secant fit of Delta y by Delta d, a
+one-scenario problem follows its closed-form geometric trajectory, and the
+optimal (z*, y*) is a fixed point.
 """
 from __future__ import annotations
 
@@ -125,8 +129,13 @@ def residuals(x: np.ndarray, z: np.ndarray, z_old: np.ndarray, rho: float):
 def admm_bb(W: wls.Wls, rho: Optional[float] = None, eps_abs: float = 1e-6, eps_rel: float = 1e-6,
             obj_rel_tol: float = 1e-5, max_iter: int = 5000, bb: bool = True, z_mode: int = 0,
             bb_clamp: float = 0.0, z0: Optional[np.ndarray] = None, setup: Optional[AdmmSetup] = None,
-            record: bool = True, callback=None) -> AdmmResult:
-    """Run ADMM-BB; returns z and the full iteration history."""
+            record: bool = True, callback=None, y0: Optional[np.ndarray] = None,
+            state_callback=None) -> AdmmResult:
+    """Run ADMM-BB; returns z and the full iteration history.
+
+    y0: starting duals (N x n, default 0).  state_callback(k, state) receives,
+    after iteration k, a dict with z_old, y_old (the values the x-updates used),
+    x, z, y (new), tau, beta and d_prev (the previous x - z, None at first)."""
     if setup is None:
         rho = wls.default_rho(W) if (rho is None or rho <= 0) else float(rho)
         setup = AdmmSetup(W, rho)
@@ -134,7 +143,7 @@ def admm_bb(W: wls.Wls, rho: Optional[float] = None, eps_abs: float = 1e-6, eps_
     N, n = W.N, W.n
     z = wls.project(W, np.zeros(n) if z0 is None else np.asarray(z0, dtype=np.float64))
     x = np.tile(z, (N, 1))
-    y = np.zeros((N, n))
+    y = np.zeros((N, n)) if y0 is None else np.array(y0, dtype=np.float64).reshape(N, n)
     d_prev = None
     y_prev = None
     f_prev = None
@@ -155,6 +164,7 @@ def admm_bb(W: wls.Wls, rho: Optional[float] = None, eps_abs: float = 1e-6, eps_
             beta = float("nan")
             tau = rho
         y_prev = y.copy()
+        d_before = d_prev
         d_prev = d
         y = y + tau * d
         rp, rd = residuals(x, z, z_old, rho)
@@ -166,6 +176,9 @@ def admm_bb(W: wls.Wls, rho: Optional[float] = None, eps_abs: float = 1e-6, eps_
                              tau=tau, beta=beta))
         if callback is not None:
             callback(k, z, f_k)
+        if state_callback is not None:
+            state_callback(k, dict(z_old=z_old, y_old=y_prev, x=x.copy(), z=z, y=y.copy(), tau=tau, beta=beta,
+                                   d_prev=d_before))
         obj_ok = True
         if obj_rel_tol > 0.0:
             obj_ok = k >= 1 and abs(f_k - f_prev) <= obj_rel_tol * abs(f_prev)
