@@ -26,14 +26,18 @@ import synth
 from oracle import admm, exact, wls
 
 
-@pytest.fixture(scope="module")
-def tiny():
+def tiny_problem():
     """The tiny workload with unequal scenario probabilities c_s (Sec. 2.1),
     so that every place c_s enters is exercised."""
     P = synth.make_tiny(2)
     W = wls.from_problem(P)
     c = np.linspace(0.5, 1.5, W.N)
     return dataclasses.replace(W, c=c / c.sum())
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return tiny_problem()
 
 
 def _run_states(W, iters, **kw):

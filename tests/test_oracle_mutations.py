@@ -2,7 +2,8 @@
 
 Each case monkeypatches one oracle function with a plausible slip (a dropped
 term, a flipped sign, a wrong index or factor) and checks that at least one
-pin of tests/test_oracle.py fails.  All on the CPU.
+pin of tests/test_oracle.py or tests/test_oracle_iterates.py fails.  All on
+the CPU.
 """
 from __future__ import annotations
 
@@ -13,6 +14,7 @@ import pytest
 
 from oracle import admm, wls
 from tests import test_oracle as T
+from tests import test_oracle_iterates as TI
 
 
 def _must_fail(fn, *args):
@@ -75,3 +77,57 @@ def test_residual_dual_without_sqrt_n(monkeypatch):
         return float(np.linalg.norm(x - z[None, :])), rho * float(np.linalg.norm(z - z_old))
     monkeypatch.setattr(admm, "residuals", res)
     _must_fail(T.test_residuals_and_tolerances_hand_values)
+
+
+# ---- pins of the ADMM-BB iterates (tests/test_oracle_iterates.py) ----
+
+@pytest.fixture(scope="module")
+def tiny_w():
+    return TI.tiny_problem()
+
+
+def test_full_rho_in_rhs_breaks_subproblem_minimality(monkeypatch, tiny_w):
+    def rhs(self, s, z, y_s):
+        return self.b[s] + self.rho * (z - y_s / self.rho)
+    monkeypatch.setattr(admm.AdmmSetup, "rhs", rhs)
+    _must_fail(TI.test_every_x_update_minimises_its_subproblem, tiny_w, False)
+
+
+def test_rhs_without_scenario_probability_breaks_subproblem_minimality(monkeypatch, tiny_w):
+    def rhs(self, s, z, y_s):
+        return self.b[s] / self.W.c[s] + 0.5 * self.rho * (z - y_s / self.rho)
+    monkeypatch.setattr(admm.AdmmSetup, "rhs", rhs)
+    _must_fail(TI.test_every_x_update_minimises_its_subproblem, tiny_w, False)
+
+
+def test_z_update_without_dual_term_breaks_dual_feasibility(monkeypatch, tiny_w):
+    # z itself barely moves (sum_s y_s vanishes off the active bounds, where the
+    # two forms agree); the duals it leaves behind leave the normal cone
+    monkeypatch.setattr(admm, "z_update", lambda W, x, y, rho, z_mode=0: wls.project(W, np.mean(x, axis=0)))
+    _must_fail(TI.test_fixed_step_duals_are_dual_feasible_for_the_z_step, tiny_w)
+
+
+def test_z_update_with_dual_times_rho_breaks_dual_feasibility(monkeypatch, tiny_w):
+    monkeypatch.setattr(admm, "z_update",
+                        lambda W, x, y, rho, z_mode=0: wls.project(W, np.mean(x + y * rho, axis=0)))
+    _must_fail(TI.test_fixed_step_duals_are_dual_feasible_for_the_z_step, tiny_w)
+
+
+def test_step_always_rho_breaks_the_sign_rule(monkeypatch, tiny_w):
+    monkeypatch.setattr(admm, "choose_tau", lambda beta, rho, bb_clamp=0.0: rho)
+    _must_fail(TI.test_bb_value_is_the_least_squares_secant_fit_and_follows_the_sign_rule, tiny_w)
+
+
+def test_bb_with_swapped_dual_difference_breaks_the_secant_fit(monkeypatch, tiny_w):
+    orig = admm.bb_step
+    monkeypatch.setattr(admm, "bb_step", lambda d, dp, y, yp: orig(d, dp, yp, y))
+    _must_fail(TI.test_bb_value_is_the_least_squares_secant_fit_and_follows_the_sign_rule, tiny_w)
+
+
+def test_dual_sign_flip_moves_the_fixed_point(monkeypatch, tiny_w):
+    # y_s enters the right-hand side with the wrong sign: the optimum with its
+    # duals is no longer a fixed point
+    def rhs(self, s, z, y_s):
+        return self.b[s] + 0.5 * self.rho * (z + y_s / self.rho)
+    monkeypatch.setattr(admm.AdmmSetup, "rhs", rhs)
+    _must_fail(TI.test_the_optimum_with_its_duals_is_a_fixed_point, tiny_w, 0)
