@@ -247,6 +247,23 @@ def main():
         "obj_after_steps": info[0]["obj"],
     }
 
+    # what the memory system delivers for one streaming read at the sizes that
+    # matter here: the dense iteration's working set (inverses + sum of Gram
+    # matrices + partials, re-read every iteration) and a stream well beyond the
+    # 256 MB last-level cache
+    if xmode == "dense":
+        # packed inverses + packed fp64 sum of the Gram matrices + fp64 tile partials
+        ws_bytes = int(bytes_per_launch + tiles * 64 * 64 * 8 + P.num_scen * tiles * 128 * 8)
+    else:
+        ws_bytes = int(pass_bytes(P, args.precision).sum())
+    probe = {}
+    for label, nb in (("working_set", ws_bytes), ("1GiB", 1 << 30)):
+        if nb >= (1 << 20):
+            probe[label] = {"bytes": nb, "GB/s": A.stream_probe(nb, reps=10)}
+    result["stream_probe"] = probe
+    if "working_set" in probe:
+        roof["frac_of_stream_probe"] = roof["achieved"] / probe["working_set"]["GB/s"]
+
     # the sparse products on their own (dense and CG x-updates alike use them for
     # the objective, gradients, features and the CG operator)
     sb = spmv_bytes(P)

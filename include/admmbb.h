@@ -246,6 +246,15 @@ admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, con
  * CG step.  Changes no solver state. */
 admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms_out);
 
+/* Measurement aid, no context: the rate (GB/s, 1e9 bytes) at which the current
+ * device streams a buffer of `bytes` (1 MiB .. 16 GiB) through one read pass
+ * (16 KiB per workgroup, 1 KiB contiguous per wave load, four loads in flight
+ * per lane), averaged over `reps` passes after one warm-up.  The
+ * buffer is allocated, filled and freed inside the call on a stream of its
+ * own.  ADMM_E_ARG for sizes out of range or reps < 1, ADMM_E_OOM when the
+ * buffer does not fit, ADMM_E_HIP on a runtime failure. */
+admm_status admm_stream_probe(int64_t bytes, int32_t reps, double* gbs_out);
+
 /* Dose-derived per-spot features for the learned warm start, computed on the GPU
  * from A_s^T applied to voxel indicator vectors.  voxel_class[m]: 0 other,
  * 1 target, 2 organ at risk.  feat: n x ADMM_NUM_DOSE_FEATURES floats, row-major:

@@ -28,6 +28,7 @@ EXPORTS = [
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
     "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
     "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate", "admm_time_pass",
+    "admm_stream_probe",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
     "mlp_loss_grad", "mlp_adam_step", "mlp_last_error",
 ]
@@ -81,7 +82,7 @@ class PgdOptionsC(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
-                          f"python -m paper_2304_14568_amd.build")
+                          f"python paper_2304_14568_amd/build.py")
     # With PyTorch installed, its HIP runtime is loaded first so that torch and
     # the library share one runtime in the process (a torch stream can then be
     # handed to the library, and neither initialises the device behind the other).
@@ -102,6 +103,7 @@ def _load():
         "admm_dose_stats": [P, i32, P, P, i32, i32, dbl, P, P, P, P],
         "admm_get_xupdate": [P, P, P],
         "admm_time_pass": [P, i32, i32, P],
+        "admm_stream_probe": [i64, i32, P],
         "mlp_create": [i32, i32, ctypes.c_uint64, P, ctypes.POINTER(P)],
         "mlp_get_params": [P, P],
         "mlp_set_params": [P, P],
@@ -185,6 +187,16 @@ def _check(ctx, code: int):
     if code < 0:
         raise AdmmError(code, lib.admm_last_error(ctx).decode(errors="replace"))
     return code
+
+
+def stream_probe(nbytes: int, reps: int = 10) -> float:
+    """GB/s of one streaming read pass over a device buffer of nbytes;
+    see admm_stream_probe."""
+    gbs = ctypes.c_double()
+    code = lib.admm_stream_probe(int(nbytes), int(reps), ctypes.byref(gbs))
+    if code < 0:
+        raise AdmmError(code, "admm_stream_probe failed")
+    return gbs.value
 
 
 def default_options(**kw) -> OptionsC:
