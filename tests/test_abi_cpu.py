@@ -177,3 +177,12 @@ def test_too_many_spots_for_the_sparse_pass_rejected():
     with pytest.raises(A.AdmmError) as e:
         A.Solver(P)
     assert e.value.code == -1 and "13 600" in str(e.value)
+
+
+def test_stream_probe_rejects_bad_arguments_before_device_work():
+    import paper_2304_14568_amd as A
+    gbs = ctypes.c_double()
+    assert A.lib.admm_stream_probe(0, 1, ctypes.byref(gbs)) == A.E_ARG          # below 1 MiB
+    assert A.lib.admm_stream_probe(1 << 30, 0, ctypes.byref(gbs)) == A.E_ARG    # no passes
+    assert A.lib.admm_stream_probe(17 << 30, 1, ctypes.byref(gbs)) == A.E_ARG   # above 16 GiB
+    assert A.lib.admm_stream_probe(1 << 30, 1, None) == A.E_ARG

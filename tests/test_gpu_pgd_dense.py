@@ -101,3 +101,9 @@ def test_dense_pgd_from_a_start_point_and_in_a_batch(probs):
     with A.Solver([P0, P1], xupdate="dense") as S:
         x, info, st = S.pgd(1, x0=x0, obj_rel_tol=0.0, max_iter=10)
     assert np.linalg.norm(x - q.x) <= 1e-9 * np.linalg.norm(q.x)
+
+
+def test_stream_probe_reports_a_plausible_rate():
+    import paper_2304_14568_amd as A
+    gbs = A.stream_probe(64 << 20, reps=5)
+    assert 100.0 < gbs < 20000.0, gbs
