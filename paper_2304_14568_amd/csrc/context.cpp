@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -102,8 +104,8 @@ struct admm_ctx {
     allocs.push_back(p);
     return static_cast<T*>(p);
   }
-  template <class T>
-  T* upload(const std::vector<T>& v) {
+  template <class T, class Alloc>
+  T* upload(const std::vector<T, Alloc>& v) {
     T* p = alloc<T>(v.size());
     if (!v.empty()) check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
     return p;
@@ -597,8 +599,26 @@ const char* admm_last_error(const admm_ctx* ctx) {
   return ctx->err.c_str();
 }
 
+namespace {
+
+// Wall-clock phases of admm_setup, printed to stderr when ADMMBB_SETUP_TIMING is set.
+struct SetupClock {
+  bool on = std::getenv("ADMMBB_SETUP_TIMING") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[admm_setup] %-28s %8.1f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
+
+}  // namespace
+
 admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, const admm_options* opts,
                              admm_ctx** out) {
+  SetupClock clk;
   if (!out) return set_err(nullptr, ADMM_E_ARG, "out is NULL");
   *out = nullptr;
   if (!probs || num_patients <= 0) return set_err(nullptr, ADMM_E_ARG, "no problems given");
@@ -626,8 +646,10 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     return set_err(nullptr, ADMM_E_OOM, "host allocation failed");
   }
   c->opts = o;
+  clk.mark("validate");
   st = pack_problems(probs, num_patients, o, &c->H, &msg);
   if (st != ADMM_OK) return set_err(nullptr, st, msg);
+  clk.mark("pack");
   try {
     int ndev = 0;
     (void)hipGetLastError();  // report only this call's errors
@@ -763,16 +785,16 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     const int32_t* d_rorig = c->upload(H.rorig);
     c->mat32 = MatDev{d_rp, d_col, c->upload(H.val), nullptr, d_rw, d_rpres, d_rorig, H.col16_used ? 1 : 0, VAL_F32};
     // the host copies of the largest arrays are not needed after upload
-    std::vector<float>().swap(H.val);
+    decltype(H.val)().swap(H.val);
     if (o.precision != ADMM_PREC_FP32) {
       c->matlp = MatDev{d_rp, d_col, c->upload(H.val_lp), c->upload(H.rscale), d_rw, d_rpres, d_rorig,
                         H.col16_used ? 1 : 0, o.precision == ADMM_PREC_BF16 ? VAL_BF16 : VAL_F16};
-      std::vector<uint16_t>().swap(H.val_lp);
+      decltype(H.val_lp)().swap(H.val_lp);
     }
-    std::vector<uint16_t>().swap(H.col16);
-    std::vector<int32_t>().swap(H.col32);
-    std::vector<uint32_t>().swap(H.rp);
-    std::vector<double>().swap(H.rw64);
+    decltype(H.col16)().swap(H.col16);
+    decltype(H.col32)().swap(H.col32);
+    decltype(H.rp)().swap(H.rp);
+    decltype(H.rw64)().swap(H.rw64);
 
     const size_t V = static_cast<size_t>(H.vec_total);
     c->d_x = c->alloc<float>(V);
@@ -814,6 +836,8 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     launch_fill_f64(c->d_rz, 0.0, static_cast<int64_t>(c->G) * kRing, c->stream);
     check(hipMemsetAsync(c->d_cgcount, 0, sizeof(int32_t) * c->G, c->stream), "memset");
     check(hipMemsetAsync(c->d_cgtotal, 0, sizeof(int64_t) * c->G, c->stream), "memset");
+    check(hipStreamSynchronize(c->stream), "setup sync");
+    clk.mark("device tables and uploads");
     if (c->dense) {
       hipEvent_t f0, f1;
       check(hipEventCreate(&f0), "hipEventCreate");
@@ -832,10 +856,12 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     for (int p = 0; p < num_patients; ++p) c->reset_patient(p, nullptr, 0.0);
     if (o.pass_threads) c->pass_threads = o.pass_threads;
     if (o.pass_unroll) c->pass_unroll = o.pass_unroll;
+    clk.mark("cached inverses");
     if (!c->dense) c->autotune();  // the dense x-update does not run the CG pass per iteration
     check(hipEventCreate(&c->ev_a), "hipEventCreate");
     check(hipEventCreate(&c->ev_b), "hipEventCreate");
     check(hipStreamSynchronize(c->stream), "setup sync");
+    clk.mark("autotune and state");
   } catch (const HipError& e) {
     std::string m = std::string(e.what) + ": " + hipGetErrorString(e.code);
     return set_err(nullptr, e.code == hipErrorOutOfMemory ? ADMM_E_OOM : ADMM_E_HIP, m);

@@ -2,13 +2,38 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/admmbb.h"
 #include "internal.h"
 
 namespace admmbb {
+
+// Allocator whose value-less construct leaves elements uninitialised: for the
+// large packed arrays, every element of which the (parallel) packing writes,
+// so that growing them costs no single-threaded zero fill.
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) {}
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    if constexpr (sizeof...(Args) == 0)
+      ::new (static_cast<void*>(p)) U;
+    else
+      ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <class T>
+using RawVec = std::vector<T, NoInit<T>>;
 
 admm_status validate_problem(const admm_problem* p, std::string* msg);
 admm_status validate_options(const admm_options* o, std::string* msg);
@@ -20,15 +45,15 @@ struct Packed {
   std::vector<Pat> pat;
   std::vector<Tile> tiles;
   std::vector<Blk> blk, pblk;
-  std::vector<uint32_t> rp;
-  std::vector<uint16_t> col16;
-  std::vector<int32_t> col32;
-  std::vector<float> val;
-  std::vector<uint16_t> val_lp;   // bf16 or fp16 bits
-  std::vector<float> rscale;
-  std::vector<float> rw, rpres;
-  std::vector<double> rw64;       // c_s w_i per sorted row in fp64 (Gram matrices of the dense x-update)
-  std::vector<int32_t> rorig;
+  RawVec<uint32_t> rp;
+  RawVec<uint16_t> col16;
+  RawVec<int32_t> col32;
+  RawVec<float> val;
+  RawVec<uint16_t> val_lp;        // bf16 or fp16 bits
+  RawVec<float> rscale;
+  RawVec<float> rw, rpres;
+  RawVec<double> rw64;            // c_s w_i per sorted row in fp64 (Gram matrices of the dense x-update)
+  RawVec<int32_t> rorig;
   std::vector<float> b;           // A_s^T c_s W p per scenario (stacked)
   std::vector<double> b64;        // the same in fp64 (dense x-update right-hand sides)
   std::vector<float> dinv;        // Jacobi inverse diagonal (stacked), filled when requested

@@ -140,14 +140,22 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       row_base += so[k].rows;
       rp_base += so[k].rows + 1;
     }
-    const size_t ntot = static_cast<size_t>(nnz_base + 4 * 256);  // trailing zero chunks
-    P.val.assign(ntot, 0.0f);
-    if (P.col16_used)
-      P.col16.assign(ntot, 0);
-    else
-      P.col32.assign(ntot, 0);
+    // the scenarios' ranges tile [0, nnz_base) and are written in full below;
+    // only the trailing zero chunks are cleared here
+    const size_t ntot = static_cast<size_t>(nnz_base + 4 * 256);
+    const size_t tail = static_cast<size_t>(nnz_base);
+    P.val.resize(ntot);
+    std::fill(P.val.begin() + tail, P.val.end(), 0.0f);
+    if (P.col16_used) {
+      P.col16.resize(ntot);
+      std::fill(P.col16.begin() + tail, P.col16.end(), uint16_t{0});
+    } else {
+      P.col32.resize(ntot);
+      std::fill(P.col32.begin() + tail, P.col32.end(), 0);
+    }
     if (lp) {
-      P.val_lp.assign(ntot, 0);
+      P.val_lp.resize(ntot);
+      std::fill(P.val_lp.begin() + tail, P.val_lp.end(), uint16_t{0});
       P.rscale.resize(static_cast<size_t>(row_base));
     }
     P.rw.resize(static_cast<size_t>(row_base));
@@ -189,13 +197,47 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       }
       r.b.assign(n, 0.0);
       r.gdiag.assign(n, 0.0);
-      std::vector<double> row_w(static_cast<size_t>(r.rows)), row_p(static_cast<size_t>(r.rows));
       uint32_t* rpp = P.rp.data() + r.rp_base;
       rpp[0] = 0;
       uint32_t off = 0;
+      // tiles: consecutive rows of one lanes-per-row width, ~tile_chunks chunks
+      // each (a row whose width differs, or a full tile, starts the next one);
+      // their accumulator bounds are gathered in the same pass
+      std::vector<double> colsum(n, 0.0);
+      std::vector<int32_t> touched;
+      auto round_up = [](double x) { return static_cast<float>(x * (1.0 + 1e-6)); };
+      int64_t t_begin = 0, t_chunks = 0;
+      int t_lanes = -1;
+      double wm = 0.0, pm = 0.0;
+      auto close_tile = [&](int64_t t_end) {
+        double cm = 0.0;
+        for (int32_t j : touched) {
+          cm = std::max(cm, colsum[j]);
+          colsum[j] = 0.0;
+        }
+        touched.clear();
+        Tile t{};
+        t.scen = k;  // global scenario index = job index
+        t.row_begin = static_cast<int32_t>(t_begin);
+        t.row_end = static_cast<int32_t>(t_end);
+        t.lanes = t_lanes;
+        t.wmax = round_up(wm);
+        t.pmax = round_up(pm);
+        t.cmax = round_up(cm);
+        r.tiles.push_back(t);
+      };
       for (int64_t q = 0; q < r.rows; ++q) {
         const int i = order[static_cast<size_t>(q)];
         const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
+        const int64_t len = e - b, len4 = (len + 3) & ~int64_t(3);
+        const int lanes = lanes_for(len4 / 4);
+        if (q > 0 && (lanes != t_lanes || t_chunks >= tile_chunks)) {
+          close_tile(q);
+          t_begin = q;
+          t_chunks = 0;
+          wm = pm = 0.0;
+        }
+        t_lanes = lanes;
         const double wi = pr.struct_weight[pr.struct_id[i]];
         const double cwi = c * wi;
         float rmax = 0.0f;
@@ -204,11 +246,10 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
           rsum += A.val[t];
           rmax = std::max(rmax, A.val[t]);
         }
-        row_w[static_cast<size_t>(q)] = cwi * rsum;
-        row_p[static_cast<size_t>(q)] = cwi * pr.presc[i];
+        wm = std::max(wm, cwi * rsum);
+        pm = std::max(pm, cwi * pr.presc[i]);
         const int64_t dst = r.nnz_base + 4 * static_cast<int64_t>(off);
         const float scl = rmax > 0.0f ? rmax : 1.0f;
-        const int64_t len = e - b, len4 = (len + 3) & ~int64_t(3);
         for (int64_t t = 0; t < len4; ++t) {
           // pad the row to whole 4-element chunks: value 0, column = the row's last column
           const int64_t src = t < len ? b + t : e - 1;
@@ -227,6 +268,8 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
           if (t < len) {
             r.b[j] += cwi * pr.presc[i] * static_cast<double>(v);
             r.gdiag[j] += cwi * static_cast<double>(v) * static_cast<double>(v);
+            if (colsum[j] == 0.0) touched.push_back(j);
+            colsum[j] += v;
           }
         }
         const int64_t ro = r.row_base + q;
@@ -237,47 +280,9 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         P.rorig[static_cast<size_t>(ro)] = i;
         off += static_cast<uint32_t>(len4 / 4);
         rpp[q + 1] = off;
+        t_chunks += len4 / 4;
       }
-      // tiles: consecutive rows with one lanes-per-row width, ~tile_nnz nonzeros each
-      std::vector<double> colsum(n, 0.0);
-      std::vector<int32_t> touched;
-      auto round_up = [](double x) { return static_cast<float>(x * (1.0 + 1e-6)); };
-      int64_t q = 0;
-      while (q < r.rows) {
-        const int L = lanes_for(rpp[q + 1] - rpp[q]);
-        int64_t q1 = q;
-        int64_t nz = 0;
-        while (q1 < r.rows && lanes_for(rpp[q1 + 1] - rpp[q1]) == L && (nz < tile_chunks || q1 == q)) {
-          nz += rpp[q1 + 1] - rpp[q1];
-          ++q1;
-        }
-        Tile t{};
-        t.scen = k;  // global scenario index = job index
-        t.row_begin = static_cast<int32_t>(q);
-        t.row_end = static_cast<int32_t>(q1);
-        t.lanes = L;
-        double wm = 0.0, pm = 0.0, cm = 0.0;
-        for (int64_t rr = q; rr < q1; ++rr) {
-          wm = std::max(wm, row_w[static_cast<size_t>(rr)]);
-          pm = std::max(pm, row_p[static_cast<size_t>(rr)]);
-          for (int64_t e = r.nnz_base + 4 * static_cast<int64_t>(rpp[rr]);
-               e < r.nnz_base + 4 * static_cast<int64_t>(rpp[rr + 1]); ++e) {
-            const int32_t j = P.col16_used ? P.col16[static_cast<size_t>(e)] : P.col32[static_cast<size_t>(e)];
-            if (colsum[j] == 0.0) touched.push_back(j);
-            colsum[j] += P.val[static_cast<size_t>(e)];
-          }
-        }
-        for (int32_t j : touched) {
-          cm = std::max(cm, colsum[j]);
-          colsum[j] = 0.0;
-        }
-        touched.clear();
-        t.wmax = round_up(wm);
-        t.pmax = round_up(pm);
-        t.cmax = round_up(cm);
-        r.tiles.push_back(t);
-        q = q1;
-      }
+      if (r.rows > 0) close_tile(r.rows);
     });
 
     // merge in (patient, scenario) order
