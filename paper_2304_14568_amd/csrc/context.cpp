@@ -12,6 +12,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host.h"
@@ -104,10 +105,35 @@ struct admm_ctx {
     allocs.push_back(p);
     return static_cast<T*>(p);
   }
+  // Copies of more than 64 MiB are split over host threads: a copy from
+  // pageable memory is staged through pinned buffers by the calling thread, so
+  // several threads keep more of the link busy.
   template <class T, class Alloc>
   T* upload(const std::vector<T, Alloc>& v) {
     T* p = alloc<T>(v.size());
-    if (!v.empty()) check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+    const size_t bytes = v.size() * sizeof(T);
+    if (bytes == 0) return p;
+    constexpr size_t kSplit = size_t{64} << 20;
+    if (bytes <= kSplit) {
+      check(hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy H2D");
+      return p;
+    }
+    int dev = 0;
+    check(hipGetDevice(&dev), "hipGetDevice");
+    const int parts = 8;
+    const size_t per = (v.size() + parts - 1) / parts;
+    std::vector<hipError_t> rc(parts, hipSuccess);
+    std::vector<std::thread> th;
+    for (int k = 0; k < parts; ++k) {
+      const size_t b = std::min(v.size(), k * per), e = std::min(v.size(), b + per);
+      if (e <= b) break;
+      th.emplace_back([&, k, b, e] {
+        rc[k] = hipSetDevice(dev);
+        if (rc[k] == hipSuccess) rc[k] = hipMemcpy(p + b, v.data() + b, (e - b) * sizeof(T), hipMemcpyHostToDevice);
+      });
+    }
+    for (auto& t : th) t.join();
+    for (hipError_t e : rc) check(e, "hipMemcpy H2D");
     return p;
   }
   ~admm_ctx() {
