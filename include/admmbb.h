@@ -112,7 +112,8 @@ typedef struct {
   int32_t lds_acc;     /* column accumulators of the fused pass in LDS: 0 fp32 atomics, 1 fp64 atomics,
                           2 64-bit fixed point (integer atomics: exact, order-independent sums);
                           -1 = chosen by the set-up autotuner among 1 and 2 */
-  int32_t tile_nnz;    /* target nonzeros per workgroup tile; 0 = automatic */
+  int32_t tile_nnz;    /* target nonzeros per workgroup tile; 0 = automatic, per patient
+                          (about 2048 tiles each, 8192 .. 4M nonzeros) */
   int32_t pass_threads; /* fused-pass workgroup size 256 or 512; 0 = chosen by the set-up autotuner */
   int32_t pass_unroll;  /* 1: row data loaded when the row starts; 2: next row's data in flight during the
                            current row (software pipelined); 0 = chosen by the autotuner */

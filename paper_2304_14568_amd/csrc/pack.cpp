@@ -86,17 +86,18 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
   for (int p = 0; p < num_patients; ++p)
     for (int s = 0; s < probs[p].num_scen; ++s) nnz_all += probs[p].A[s].nnz;
   // about 2048 tiles (8 workgroups per CU) for every patient: the passes are
-  // launched per patient, so a small patient in a batch must not get a few
-  // huge tiles sized for the whole batch
-  int64_t nnz_min_pat = nnz_all;
+  // launched per patient, so each patient's tiles are sized for its own
+  // nonzeros (a small patient in a batch must not get a few huge tiles, nor a
+  // large one thousands of tiny ones)
+  (void)nnz_all;
+  std::vector<int64_t> tile_chunks_of(num_patients);
   for (int p = 0; p < num_patients; ++p) {
     int64_t np = 0;
     for (int s = 0; s < probs[p].num_scen; ++s) np += probs[p].A[s].nnz;
-    nnz_min_pat = std::min(nnz_min_pat, np);
+    int64_t tile_nnz = o.tile_nnz > 0 ? o.tile_nnz : np / (256 * 8);
+    tile_nnz = std::max<int64_t>(8192, std::min<int64_t>(tile_nnz, 1 << 22));
+    tile_chunks_of[p] = std::max<int64_t>(1, tile_nnz / 4);
   }
-  int64_t tile_nnz = o.tile_nnz > 0 ? o.tile_nnz : nnz_min_pat / (256 * 8);
-  tile_nnz = std::max<int64_t>(8192, std::min<int64_t>(tile_nnz, 1 << 22));
-  const int64_t tile_chunks = std::max<int64_t>(1, tile_nnz / 4);
 
   P.col16_used = true;
   for (int p = 0; p < num_patients; ++p) {
@@ -169,6 +170,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       const admm_problem& pr = probs[job_p[k]];
       const admm_csr& A = pr.A[job_s[k]];
       const int n = pr.n, m = pr.m;
+      const int64_t tile_chunks = tile_chunks_of[job_p[k]];
       ScenOut& r = so[k];
       const double c = A.prob == 0.0 ? 1.0 : A.prob;
       // counting sort of the nonzero rows by decreasing length (stable)
