@@ -12,6 +12,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -124,13 +125,18 @@ struct admm_ctx {
     const size_t per = (v.size() + parts - 1) / parts;
     std::vector<hipError_t> rc(parts, hipSuccess);
     std::vector<std::thread> th;
+    auto copy_part = [&](int k, size_t b, size_t e) {
+      rc[k] = hipSetDevice(dev);
+      if (rc[k] == hipSuccess) rc[k] = hipMemcpy(p + b, v.data() + b, (e - b) * sizeof(T), hipMemcpyHostToDevice);
+    };
     for (int k = 0; k < parts; ++k) {
       const size_t b = std::min(v.size(), k * per), e = std::min(v.size(), b + per);
       if (e <= b) break;
-      th.emplace_back([&, k, b, e] {
-        rc[k] = hipSetDevice(dev);
-        if (rc[k] == hipSuccess) rc[k] = hipMemcpy(p + b, v.data() + b, (e - b) * sizeof(T), hipMemcpyHostToDevice);
-      });
+      try {
+        th.emplace_back(copy_part, k, b, e);
+      } catch (const std::system_error&) {
+        copy_part(k, b, e);  // no thread: copy this part here
+      }
     }
     for (auto& t : th) t.join();
     for (hipError_t e : rc) check(e, "hipMemcpy H2D");
@@ -673,7 +679,13 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
   }
   c->opts = o;
   clk.mark("validate");
-  st = pack_problems(probs, num_patients, o, &c->H, &msg);
+  try {
+    st = pack_problems(probs, num_patients, o, &c->H, &msg);
+  } catch (const std::bad_alloc&) {
+    return set_err(nullptr, ADMM_E_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_err(nullptr, ADMM_E_HIP, std::string("packing failed: ") + e.what());
+  }
   if (st != ADMM_OK) return set_err(nullptr, st, msg);
   clk.mark("pack");
   try {
@@ -893,6 +905,8 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     return set_err(nullptr, e.code == hipErrorOutOfMemory ? ADMM_E_OOM : ADMM_E_HIP, m);
   } catch (const std::bad_alloc&) {
     return set_err(nullptr, ADMM_E_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_err(nullptr, ADMM_E_HIP, std::string("set-up failed: ") + e.what());
   }
   *out = c.release();
   return ADMM_OK;

@@ -14,6 +14,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <system_error>
 #include <thread>
 
 #include "host.h"
@@ -71,7 +72,13 @@ void parallel_for(int count, F&& fn) {
     }
   };
   std::vector<std::thread> th;
-  for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+  for (int t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(worker);
+    } catch (const std::system_error&) {
+      break;  // fewer threads: the calling thread takes the remaining jobs
+    }
+  }
   worker();
   for (auto& t : th) t.join();
   if (oom) throw std::bad_alloc();

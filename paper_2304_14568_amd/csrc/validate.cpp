@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -88,10 +89,23 @@ admm_status validate_problem(const admm_problem* p, std::string* msg) {
   const int nt = static_cast<int>(std::min<unsigned>(hw, static_cast<unsigned>(N)));
   std::atomic<int> next{0};
   auto worker = [&]() {
-    for (int s = next++; s < N; s = next++) st[s] = check_scen(s);
+    for (int s = next++; s < N; s = next++) {
+      try {
+        st[s] = check_scen(s);
+      } catch (...) {  // nothing may leave a worker thread
+        st[s] = ADMM_E_OOM;
+        ms[s] = "host allocation failed while validating";
+      }
+    }
   };
   std::vector<std::thread> th;
-  for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+  for (int t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(worker);
+    } catch (const std::system_error&) {
+      break;  // fewer threads: the calling thread checks the remaining scenarios
+    }
+  }
   worker();
   for (auto& t : th) t.join();
   for (int s = 0; s < N; ++s)
