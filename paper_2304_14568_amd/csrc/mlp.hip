@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
 #include <vector>
@@ -352,6 +353,9 @@ admm_status mlp_create(int32_t nin, int32_t hidden, uint64_t seed, void* stream,
   } catch (const HipErr& e) {
     delete n;
     return mlp_fail(nullptr, "mlp_create", e.e);
+  } catch (const std::exception&) {
+    delete n;
+    return mlp_fail(nullptr, "mlp_create", hipErrorOutOfMemory);
   }
   *out = n;
   return ADMM_OK;
@@ -368,6 +372,8 @@ admm_status mlp_get_params(admm_mlp* n, float* out) {
     ck(hipMemcpy(out, n->th, sizeof(float) * n->np, hipMemcpyDeviceToHost));
   } catch (const HipErr& e) {
     return mlp_fail(n, "mlp_get_params", e.e);
+  } catch (const std::exception&) {  // host allocation: nothing crosses the C boundary
+    return mlp_fail(n, "mlp_get_params", hipErrorOutOfMemory);
   }
   return ADMM_OK;
 }
@@ -387,6 +393,8 @@ admm_status mlp_set_params(admm_mlp* n, const float* in) {
     n->step = 0;
   } catch (const HipErr& e) {
     return mlp_fail(n, "mlp_set_params", e.e);
+  } catch (const std::exception&) {  // host allocation: nothing crosses the C boundary
+    return mlp_fail(n, "mlp_set_params", hipErrorOutOfMemory);
   }
   return ADMM_OK;
 }
@@ -407,6 +415,8 @@ admm_status mlp_forward(admm_mlp* n, const float* X, int32_t rows, int32_t preci
     if (log_rho_out) *log_rho_out = static_cast<float>(n->h_sc[0]);
   } catch (const HipErr& e) {
     return mlp_fail(n, "mlp_forward", e.e);
+  } catch (const std::exception&) {  // host allocation: nothing crosses the C boundary
+    return mlp_fail(n, "mlp_forward", hipErrorOutOfMemory);
   }
   return ADMM_OK;
 }
@@ -443,6 +453,8 @@ admm_status mlp_loss_grad(admm_mlp* n, const float* X, const float* target, int3
     if (loss_out) *loss_out = n->h_sc[1];
   } catch (const HipErr& e) {
     return mlp_fail(n, "mlp_loss_grad", e.e);
+  } catch (const std::exception&) {  // host allocation: nothing crosses the C boundary
+    return mlp_fail(n, "mlp_loss_grad", hipErrorOutOfMemory);
   }
   return ADMM_OK;
 }
@@ -460,6 +472,8 @@ admm_status mlp_adam_step(admm_mlp* n, float lr, float beta1, float beta2, float
     ck(hipStreamSynchronize(n->stream));
   } catch (const HipErr& e) {
     return mlp_fail(n, "mlp_adam_step", e.e);
+  } catch (const std::exception&) {  // host allocation: nothing crosses the C boundary
+    return mlp_fail(n, "mlp_adam_step", hipErrorOutOfMemory);
   }
   return ADMM_OK;
 }
