@@ -128,3 +128,36 @@ def test_dense_setup_in_scenario_chunks_matches_one_chunk(probs, monkeypatch):
         z_chunked = S.z()
     # the Gram matrices sum with fp64 atomics (order-dependent in the last bits)
     assert np.linalg.norm(z_chunked - z_one) <= 1e-6 * np.linalg.norm(z_one)
+
+
+def test_dense_x_update_near_its_size_limit():
+    """n = 7 895 spots (124 blocks of 64, the limit is 127): the first x-update
+    from z = 0, y = 0 solves B_s x_s = b_s (checked with the fp64 operator of
+    the oracle, to the fp32 rounding of the cached inverse amplified by the
+    conditioning of B_s), and the dense and CG x-updates reach the same
+    objective."""
+    import paper_2304_14568_amd as A
+    P = synth.make_hn(seed=7, grid=(72, 72, 48), body_semi_vox=(30, 24, 18), target_size=1.1, num_layers=11,
+                      spot_spacing=2.5, num_scen=2)
+    assert 7800 < P.n <= 8128
+    W = wls.from_problem(P)
+    with A.Solver(P, xupdate="dense", max_iter=3000) as S:
+        rho = S.rho()
+        S.iterate(1)
+        st = S.get_state()
+        z = st["z"]
+        d = np.asarray(st["d"]).reshape(P.num_scen, P.n)
+        for s in range(P.num_scen):
+            x = d[s] + z
+            b = W.A[s].T @ (W.c[s] * W.w * W.p)
+            r = wls.normal_apply(W, s, x, rho) - b
+            assert np.linalg.norm(r) <= 2e-4 * np.linalg.norm(b), np.linalg.norm(r) / np.linalg.norm(b)
+        S.reset()
+        zs, info, stt = S.solve()
+        assert stt == 0, info
+        f_dense = wls.objective(W, zs[0])
+    with A.Solver(P, xupdate="cg", max_iter=3000) as S:
+        zc, infoc, stc = S.solve()
+        assert stc == 0, infoc
+        f_cg = wls.objective(W, zc[0])
+    assert abs(f_dense - f_cg) <= 1e-5 * f_cg, (f_dense, f_cg)
