@@ -89,6 +89,8 @@ def test_dense_pgd_needs_the_dense_context(probs):
     with A.Solver(P, xupdate="cg") as S:
         with pytest.raises(A.AdmmError):
             S.pgd(0, dense=1)
+        with pytest.raises(A.AdmmError):
+            S.pgd(0, dense=2)                      # not -1, 0 or 1
         x, info, st = S.pgd(0)                     # default falls back to the sparse form
         assert info["iter"] > 0
 
