@@ -1356,10 +1356,10 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
     for (const Pat& q : ctx->H.pat) {
       const int64_t nj = q.fobj_end - q.fobj_begin, nbl = (q.npad + 255) / 256;
       words = std::max(words, (2 + 2 * kPgdK) * static_cast<int64_t>(q.npad) + nj * kPgdK * 128 + q.nbk * kPgdK +
-                                  nbl * kPgdK);
+                                  2 * nbl * kPgdK);
     }
     ctx->d_pgd = ctx->alloc<double>(static_cast<size_t>(words));
-    ctx->d_pgdst = ctx->alloc<PgdDevState>(1);
+    ctx->d_pgdst = ctx->alloc<PgdDevState>(2);
   }
   PgdArgs a{};
   a.Gp = ctx->d_Gp + pt.gpack_off;
@@ -1388,10 +1388,12 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
   a.max_trials = o.max_trials;
 
   // host sources stay alive and unchanged until the final synchronisation
-  PgdDevState h0{}, h{};
-  h0.alpha = o.alpha > 0 ? o.alpha : 1.0;
-  h0.pick = -1;
-  check(hipMemcpyAsync(a.st, &h0, sizeof(h0), hipMemcpyHostToDevice, s), "H2D");
+  PgdDevState h0[2] = {}, h{};
+  for (PgdDevState& e : h0) {
+    e.alpha = o.alpha > 0 ? o.alpha : 1.0;
+    e.pick = -1;
+  }
+  check(hipMemcpyAsync(a.st, h0, sizeof(h0), hipMemcpyHostToDevice, s), "H2D");
   std::vector<double> pv, hv(n);
   launch_fill_f64(a.x, 0.0, 2 * static_cast<int64_t>(a.np), s);  // x and g, with their zero padding
   if (!(o.alpha > 0)) {
@@ -1408,8 +1410,13 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
   check(hipMemcpyAsync(a.x, hv.data(), sizeof(double) * n, hipMemcpyHostToDevice, s), "H2D");
   launch_fill_f64(a.g, 0.0, n, s);
   static_assert(kPgdK % 2 == 0, "sub-buffers of the PGD work area stay 16-byte aligned");
-  launch_pgd_cand(a, s);  // t_base = 0: every trial point is x
-  launch_pgd_round(a, 1, s);
+  // state slot 0 carries alpha from the power iteration; every launch of the
+  // step kernel reads slot par and writes slot par ^ 1
+  int par = 0;
+  launch_pgd_prime(a, par, s);  // t_base = 0: every trial point is x
+  par ^= 1;
+  launch_pgd_round(a, 1, par, s);
+  par ^= 1;
   // every round either accepts a step or rejects kPgdK trial steps, so the
   // device state reaches done within this many rounds
   const int64_t max_rounds =
@@ -1417,13 +1424,16 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
   constexpr int kChunk = 16;
   for (int64_t r = 1; r <= max_rounds; r += kChunk) {
     const int64_t c = std::min<int64_t>(kChunk, max_rounds - r + 1);
-    for (int64_t k = 0; k < c; ++k) launch_pgd_round(a, 0, s);
+    for (int64_t k = 0; k < c; ++k) {
+      launch_pgd_round(a, 0, par, s);
+      par ^= 1;
+    }
     check(hipGetLastError(), "PGD launch");
-    check(hipMemcpyAsync(&h, a.st, sizeof(h), hipMemcpyDeviceToHost, s), "D2H");
+    check(hipMemcpyAsync(&h, a.st + par, sizeof(h), hipMemcpyDeviceToHost, s), "D2H");
     check(hipStreamSynchronize(s), "sync");
     if (h.done) break;
   }
-  check(hipMemcpyAsync(&h, a.st, sizeof(h), hipMemcpyDeviceToHost, s), "D2H");
+  check(hipMemcpyAsync(&h, a.st + par, sizeof(h), hipMemcpyDeviceToHost, s), "D2H");
   if (x_out) check(hipMemcpyAsync(x_out, a.x, sizeof(double) * n, hipMemcpyDeviceToHost, s), "D2H");
   check(hipStreamSynchronize(s), "sync");
   const bool converged = h.done && h.status == 1;

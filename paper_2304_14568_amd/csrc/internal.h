@@ -283,14 +283,14 @@ struct PgdArgs {
   double* u;         // kPgdK x np: S x_k
   double* part;      // per tile and trial point: 64 row and 64 column products
   double* fpart;     // [k][block row]
-  double* gdpart;    // [k][block]
-  PgdDevState* st;
+  double* gdpart;    // [2][k][block]: double-buffered by round parity
+  PgdDevState* st;   // [2]: read slot par, write slot par ^ 1
   double fconst, beta, gamma, tol;
   int32_t max_iter, max_trials;
 };
 
 void launch_pgd_power(const PgdArgs& a, double* v, hipStream_t st);
-void launch_pgd_cand(const PgdArgs& a, hipStream_t st);
-void launch_pgd_round(const PgdArgs& a, int first, hipStream_t st);
+void launch_pgd_prime(const PgdArgs& a, int par, hipStream_t st);
+void launch_pgd_round(const PgdArgs& a, int first, int par, hipStream_t st);
 
 }  // namespace admmbb

@@ -7,10 +7,10 @@
 //   k_pgd_tiles   for every tile T of S and every k: T x_k,J and T^T x_k,I,
 //                 one read of S for all kPgdK trial points
 //   k_pgd_rows    u_k = S x_k from the tile products, and f(x_k) partial sums
-//   k_pgd_select  the first k (largest step) with
-//                 f(x_k) <= f(x) + beta g^T (x_k - x) is accepted; stopping tests
-//   k_pgd_cand    x = x_k with gradient 2 u_k - g0, and the next round's trial
-//                 points x_k = P(x - t_k g), t_k = t_base gamma^k
+//   k_pgd_step    the first k (largest step) with
+//                 f(x_k) <= f(x) + beta g^T (x_k - x) is accepted (stopping
+//                 tests), x = x_k with gradient 2 u_k - g0, and the next round's
+//                 trial points x_k = P(x - t_k g), t_k = t_base gamma^k
 // so an iteration whose step is found within kPgdK trials reads S once.
 // A round that accepts nothing retries from the same x with the next kPgdK
 // steps.  The host launches rounds in chunks and reads the state in between.
@@ -38,32 +38,101 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// Applies the step the last selection accepted (x = x_p, grad f(x) = 2 S x_p - g0,
-// idempotent, also after the stopping test), then, while running, writes the
-// next round's trial points x_k = P(x - t_k g), t_k = t_base gamma^k, and the
-// partial sums of g^T (x_k - x), gdpart[k * nblocks + block].  Vectors are
-// zero beyond n up to np.
-__global__ __launch_bounds__(256) void k_pgd_cand(PgdArgs a) {
-  const PgdDevState* st = a.st;
+// The step of a round (one thread per spot, every workgroup taking the same
+// decision from the same sums in the same order):
+//   decision  from f(x_k) (tile sums) and g^T (x_k - x) of this round's trial
+//             points: the first k (largest step) with sufficient decrease is
+//             accepted, else the next kPgdK steps are tried from the same x;
+//             stopping tests; workgroup 0 writes the next state
+//   apply     x = x_p, grad f(x) = 2 u_p - g0
+//   propose   the next trial points x_k = P(x - t_k g), t_k = t_base gamma^k, and
+//             the partial sums of g^T (x_k - x) (next buffer)
+// State and partial sums are double-buffered by the round's parity: this
+// launch reads slot par and writes slot par ^ 1.  mode 0: a round; 1: the first
+// round (every trial point is x: record f(x), take its gradient); 2: prime
+// (no decision: propose trial points at t_base from x and g).
+__global__ __launch_bounds__(256) void k_pgd_step(PgdArgs a, int mode, int par) {
   __shared__ double red[4][kPgdK];
-  const int j = static_cast<int>(blockIdx.x) * 256 + threadIdx.x;
+  __shared__ double fk[kPgdK], gd[kPgdK];
+  const PgdDevState cur = a.st[par];
+  PgdDevState nxt = cur;
+  const int tid = threadIdx.x;
+  const int j = static_cast<int>(blockIdx.x) * 256 + tid;
   const bool in = j < a.n;
-  // loads that do not depend on the state go out together with it
+  const double* gdin = a.gdpart + static_cast<int64_t>(par) * kPgdK * a.nblocks;
+  double* gdout = a.gdpart + static_cast<int64_t>(par ^ 1) * kPgdK * a.nblocks;
+  // loads that do not depend on the decision go out first
   double xj = in ? a.x[j] : 0.0, gj = in ? a.g[j] : 0.0;
   const double g0j = in ? a.g0[j] : 0.0;
   const double lo = in ? a.lb[j] : 0.0, hi = in ? a.ub[j] : 0.0;
-  const int p = st->pick;
-  const bool run = !st->done;
+  int p = -1;
+  if (!cur.done && mode != 2) {
+    // f(x_k) and g^T (x_k - x): wave w sums k = w and w + 4, fixed order
+    const int w = tid >> 6, lane = tid & 63;
+    for (int k = w; k < kPgdK; k += 4) {
+      double fs = 0.0, ds = 0.0;
+      for (int b = lane; b < a.nb; b += 64) fs += a.fpart[static_cast<int64_t>(k) * a.nb + b];
+      for (int b = lane; b < a.nblocks; b += 64) ds += gdin[static_cast<int64_t>(k) * a.nblocks + b];
+      fs = wsum(fs);
+      ds = wsum(ds);
+      if (lane == 0) {
+        fk[k] = a.fconst + fs;
+        gd[k] = ds;
+      }
+    }
+    __syncthreads();
+    bool stop = false;
+    if (mode == 1) {
+      p = 0;
+      nxt.f = fk[0];
+      nxt.t_base = cur.alpha;
+      if (a.max_iter <= 0) {
+        stop = true;
+        nxt.status = 3;
+      }
+    } else {
+      for (int kk = 0; kk < kPgdK; ++kk)
+        if (cur.trials + kk < a.max_trials && fk[kk] <= cur.f + a.beta * gd[kk]) {
+          p = kk;
+          break;
+        }
+      if (p >= 0) {
+        nxt.f = fk[p];
+        nxt.iter = cur.iter + 1;
+        nxt.trials = 0;
+        nxt.t_base = cur.alpha;
+        if (fabs(cur.f - fk[p]) <= a.tol * fabs(cur.f)) {
+          stop = true;
+          nxt.status = 1;
+        } else if (nxt.iter >= a.max_iter) {
+          stop = true;
+          nxt.status = 3;
+        }
+      } else {
+        nxt.trials = cur.trials + kPgdK;
+        double t = cur.t_base;
+        for (int kk = 0; kk < kPgdK; ++kk) t *= a.gamma;
+        nxt.t_base = t;
+        if (nxt.trials >= a.max_trials) {
+          stop = true;
+          nxt.status = 2;
+        }
+      }
+    }
+    if (stop) nxt.done = 1;
+  }
+  nxt.pick = p;
+  if (blockIdx.x == 0 && tid == 0) a.st[par ^ 1] = nxt;
   if (in && p >= 0) {
     xj = a.xc[static_cast<int64_t>(p) * a.np + j];
     gj = 2.0 * a.u[static_cast<int64_t>(p) * a.np + j] - g0j;
     a.x[j] = xj;
     a.g[j] = gj;
   }
-  if (!run) return;
+  if (nxt.done) return;
   double loc[kPgdK];
   if (in) {
-    double t = st->t_base;
+    double t = nxt.t_base;
 #pragma unroll
     for (int k = 0; k < kPgdK; ++k) {
       const double v = fmin(fmax(xj - t * gj, lo), hi);
@@ -80,14 +149,12 @@ __global__ __launch_bounds__(256) void k_pgd_cand(PgdArgs a) {
   }
 #pragma unroll
   for (int k = 0; k < kPgdK; ++k) {
-    const double s = wsum(loc[k]);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = s;
+    const double sum = wsum(loc[k]);
+    if ((tid & 63) == 0) red[tid >> 6][k] = sum;
   }
   __syncthreads();
-  if (threadIdx.x < kPgdK) {
-    const int k = threadIdx.x;
-    a.gdpart[static_cast<int64_t>(k) * a.nblocks + blockIdx.x] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
-  }
+  if (tid < kPgdK)
+    gdout[static_cast<int64_t>(tid) * a.nblocks + blockIdx.x] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // One tile T = S_IJ (I <= J) per workgroup, staged once through LDS (32 KB,
@@ -107,7 +174,8 @@ __global__ __launch_bounds__(256) void k_pgd_cand(PgdArgs a) {
 __device__ __forceinline__ int sw(int r) { return ((2 * r) & 30) ^ (r & 16); }
 
 template <int KC>
-__global__ __launch_bounds__(256) void k_pgd_tiles(PgdArgs a, const double* __restrict__ v, int64_t vstride) {
+__global__ __launch_bounds__(256) void k_pgd_tiles(PgdArgs a, const double* __restrict__ v, int64_t vstride,
+                                                   int par) {
   __shared__ double tl[kT * kT];
   const int64_t t = blockIdx.x;  // jobs are the tiles in packed order
   const int tid = threadIdx.x;
@@ -118,7 +186,7 @@ __global__ __launch_bounds__(256) void k_pgd_tiles(PgdArgs a, const double* __re
     double2 g[8];
 #pragma unroll
     for (int it = 0; it < 8; ++it) g[it] = T[it * 256 + tid];
-    if (a.st->done) return;
+    if (a.st[par].done) return;
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
       const int e = 2 * (it * 256 + tid), r = e / kT, c = e % kT;
@@ -180,7 +248,8 @@ __global__ __launch_bounds__(256) void k_pgd_tiles(PgdArgs a, const double* __re
 // fpart[k * nb + I] = sum over the block's rows of v_k (u_k - g0).
 // Four waves take every fourth tile of the block row; fixed summation order.
 template <int KC>
-__global__ __launch_bounds__(256) void k_pgd_rows(PgdArgs a, const double* __restrict__ v, int64_t vstride) {
+__global__ __launch_bounds__(256) void k_pgd_rows(PgdArgs a, const double* __restrict__ v, int64_t vstride,
+                                                  int par) {
   __shared__ double red[4][kT];
   const int I = static_cast<int>(blockIdx.x), k = static_cast<int>(blockIdx.y);
   const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -196,7 +265,7 @@ __global__ __launch_bounds__(256) void k_pgd_rows(PgdArgs a, const double* __res
     }
     s += (e[0] + e[1]) + (e[2] + e[3]);
   }
-  if (a.st->done) return;  // checked after the (in-bounds) loads are under way
+  if (a.st[par].done) return;  // checked after the (in-bounds) loads are under way
   red[w][i] = s;
   __syncthreads();
   if (w != 0) return;
@@ -209,77 +278,6 @@ __global__ __launch_bounds__(256) void k_pgd_rows(PgdArgs a, const double* __res
   }
   d = wsum(d);
   if (i == 0) a.fpart[static_cast<int64_t>(k) * a.nb + I] = d;
-}
-
-// Acceptance, step update and stopping tests (the accepted point is applied by
-// the next k_pgd_cand); 2 waves per trial point for the sums.
-__global__ __launch_bounds__(128 * kPgdK) void k_pgd_select(PgdArgs a, int first) {
-  PgdDevState* st = a.st;
-  if (st->done) return;
-  __shared__ double rf[2 * kPgdK], rd[2 * kPgdK];
-  __shared__ double fk[kPgdK], gd[kPgdK];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int k = w >> 1, h = w & 1;
-  double f = 0.0, d = 0.0;
-  for (int b = h * 64 + lane; b < a.nb; b += 128) f += a.fpart[static_cast<int64_t>(k) * a.nb + b];
-  for (int b = h * 64 + lane; b < a.nblocks; b += 128) d += a.gdpart[static_cast<int64_t>(k) * a.nblocks + b];
-  f = wsum(f);
-  d = wsum(d);
-  if (lane == 0) {
-    rf[w] = f;
-    rd[w] = d;
-  }
-  __syncthreads();
-  if (tid < kPgdK) {
-    fk[tid] = a.fconst + (rf[2 * tid] + rf[2 * tid + 1]);
-    gd[tid] = rd[2 * tid] + rd[2 * tid + 1];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int p = -1;
-    bool stop = false;
-    if (first) {
-      // every trial point is x itself (t_base = 0): record f(x), take its gradient
-      p = 0;
-      st->f = fk[0];
-      st->t_base = st->alpha;
-      if (a.max_iter <= 0) {
-        stop = true;
-        st->status = 3;
-      }
-    } else {
-      for (int kk = 0; kk < kPgdK; ++kk)
-        if (st->trials + kk < a.max_trials && fk[kk] <= st->f + a.beta * gd[kk]) {
-          p = kk;
-          break;
-        }
-      if (p >= 0) {
-        const double f_old = st->f, f_new = fk[p];
-        st->f = f_new;
-        st->iter += 1;
-        st->trials = 0;
-        st->t_base = st->alpha;
-        if (fabs(f_old - f_new) <= a.tol * fabs(f_old)) {
-          stop = true;
-          st->status = 1;
-        } else if (st->iter >= a.max_iter) {
-          stop = true;
-          st->status = 3;
-        }
-      } else {
-        st->trials += kPgdK;
-        double t = st->t_base;
-        for (int kk = 0; kk < kPgdK; ++kk) t *= a.gamma;
-        st->t_base = t;
-        if (st->trials >= a.max_trials) {
-          stop = true;
-          st->status = 2;
-        }
-      }
-    }
-    if (stop) st->done = 1;
-    st->pick = p;
-  }
 }
 
 // Power iteration step: v = u / ||u|| with u = 2 S v_old (rows of u[0]),
@@ -300,35 +298,35 @@ __global__ __launch_bounds__(1024) void k_pgd_normalize(PgdArgs a, double* __res
   for (int w = 0; w < 16; ++w) tot += red[w];
   const double nrm = sqrt(tot);
   if (!(nrm > 0)) {
-    if (tid == 0) a.st->alpha = 1.0;
+    if (tid == 0) a.st[0].alpha = 1.0;
     return;
   }
   for (int j = tid; j < a.n; j += 1024) v[j] = 2.0 * a.u[j] / nrm;
-  if (tid == 0) a.st->alpha = 10.0 / nrm;
+  if (tid == 0) a.st[0].alpha = 10.0 / nrm;
 }
 
 }  // namespace
 
 // One power-iteration step on H = 2 S; v is replaced by the next unit vector.
-// The state must have done = 0.
+// Slot 0 of the state must have done = 0.
 void launch_pgd_power(const PgdArgs& a, double* v, hipStream_t st) {
   hipLaunchKernelGGL(k_pgd_tiles<1>, dim3(a.njobs), dim3(256), 0, st, a, static_cast<const double*>(v),
-                     int64_t{0});
-  hipLaunchKernelGGL(k_pgd_rows<1>, dim3(a.nb, 1), dim3(256), 0, st, a, static_cast<const double*>(v), int64_t{0});
+                     int64_t{0}, 0);
+  hipLaunchKernelGGL(k_pgd_rows<1>, dim3(a.nb, 1), dim3(256), 0, st, a, static_cast<const double*>(v), int64_t{0},
+                     0);
   hipLaunchKernelGGL(k_pgd_normalize, dim3(1), dim3(1024), 0, st, a, v);
 }
 
-void launch_pgd_cand(const PgdArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_pgd_cand, dim3(a.nblocks), dim3(256), 0, st, a);
+void launch_pgd_prime(const PgdArgs& a, int par, hipStream_t st) {
+  hipLaunchKernelGGL(k_pgd_step, dim3(a.nblocks), dim3(256), 0, st, a, 2, par);
 }
 
-void launch_pgd_round(const PgdArgs& a, int first, hipStream_t st) {
+void launch_pgd_round(const PgdArgs& a, int first, int par, hipStream_t st) {
   const double* xc = a.xc;
   const int64_t n = a.np;
-  hipLaunchKernelGGL(k_pgd_tiles<kPgdK>, dim3(a.njobs), dim3(256), 0, st, a, xc, n);
-  hipLaunchKernelGGL(k_pgd_rows<kPgdK>, dim3(a.nb, kPgdK), dim3(256), 0, st, a, xc, n);
-  hipLaunchKernelGGL(k_pgd_select, dim3(1), dim3(128 * kPgdK), 0, st, a, first);
-  hipLaunchKernelGGL(k_pgd_cand, dim3(a.nblocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_pgd_tiles<kPgdK>, dim3(a.njobs), dim3(256), 0, st, a, xc, n, par);
+  hipLaunchKernelGGL(k_pgd_rows<kPgdK>, dim3(a.nb, kPgdK), dim3(256), 0, st, a, xc, n, par);
+  hipLaunchKernelGGL(k_pgd_step, dim3(a.nblocks), dim3(256), 0, st, a, first ? 1 : 0, par);
 }
 
 }  // namespace admmbb
