@@ -33,6 +33,17 @@ inline void check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw HipError{e, what};
 }
 
+// Waits for a stream when it goes out of scope: declared after the host
+// buffers that queued copies read or write, it keeps them alive until the
+// copies are done, also when a failed call leaves the scope by an exception.
+struct StreamDrain {
+  hipStream_t s;
+  explicit StreamDrain(hipStream_t st) : s(st) {}
+  StreamDrain(const StreamDrain&) = delete;
+  StreamDrain& operator=(const StreamDrain&) = delete;
+  ~StreamDrain() { (void)hipStreamSynchronize(s); }
+};
+
 }  // namespace
 
 struct admm_ctx {
@@ -490,6 +501,7 @@ struct admm_ctx {
   void reset_patient(int p, const double* z0, double new_rho) {
     const Pat& pt = H.pat[p];
     std::vector<float> z(pt.n);
+    StreamDrain drain{stream};
     for (int j = 0; j < pt.n; ++j) {
       double v = z0 ? z0[j] : 0.0;
       v = std::min(std::max(v, static_cast<double>(H.lb[pt.zvec_base + j])), static_cast<double>(H.ub[pt.zvec_base + j]));
@@ -515,6 +527,7 @@ struct admm_ctx {
   void upload_pvec(int p, const double* x, float* dst) {
     const Pat& pt = H.pat[p];
     std::vector<float> v(pt.n);
+    StreamDrain drain{stream};
     for (int j = 0; j < pt.n; ++j) v[j] = static_cast<float>(x[j]);
     check(hipMemcpyAsync(dst + pt.zvec_base, v.data(), sizeof(float) * pt.n, hipMemcpyHostToDevice, stream), "H2D");
     check(hipStreamSynchronize(stream), "sync");
@@ -551,6 +564,14 @@ admm_status from_hip(admm_ctx* c, const HipError& e) {
   return set_err(c, e.code == hipErrorOutOfMemory ? ADMM_E_OOM : ADMM_E_HIP, m);
 }
 
+// A failed entry point waits for the work it already queued before it
+// returns, so that no copy into a caller's buffer is still pending once the
+// caller sees the error.
+void drain_after_error(admm_ctx* c) {
+  if (c) (void)hipStreamSynchronize(c->stream);
+  (void)hipGetLastError();
+}
+
 // every entry reports only its own HIP errors: a stale last-error left by an
 // earlier call of the thread is cleared first
 #define GUARD_BEGIN      \
@@ -559,12 +580,16 @@ admm_status from_hip(admm_ctx* c, const HipError& e) {
 #define GUARD_END(ctx)                                              \
   }                                                                 \
   catch (const HipError& e) {                                       \
-    return from_hip(ctx, e);                                        \
+    const admm_status guard_st = from_hip(ctx, e);                  \
+    drain_after_error(ctx);                                         \
+    return guard_st;                                                \
   }                                                                 \
   catch (const std::bad_alloc&) {                                   \
+    drain_after_error(ctx);                                         \
     return set_err(ctx, ADMM_E_OOM, "host allocation failed");      \
   }                                                                 \
   catch (...) {                                                     \
+    drain_after_error(ctx);                                         \
     return set_err(ctx, ADMM_E_HIP, "unexpected exception");        \
   }
 
@@ -1387,14 +1412,16 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
   a.max_iter = o.max_iter;
   a.max_trials = o.max_trials;
 
-  // host sources stay alive and unchanged until the final synchronisation
+  // host sources stay alive and unchanged until the final synchronisation,
+  // also when a failed call below leaves the function by an exception
   PgdDevState h0[2] = {}, h{};
+  std::vector<double> pv, hv(n);
+  StreamDrain drain{s};
   for (PgdDevState& e : h0) {
     e.alpha = o.alpha > 0 ? o.alpha : 1.0;
     e.pick = -1;
   }
   check(hipMemcpyAsync(a.st, h0, sizeof(h0), hipMemcpyHostToDevice, s), "H2D");
-  std::vector<double> pv, hv(n);
   launch_fill_f64(a.x, 0.0, 2 * static_cast<int64_t>(a.np), s);  // x and g, with their zero padding
   if (!(o.alpha > 0)) {
     // alpha = 10 / lambda_max(H), H = 2 sum_s G_s, 30 power iterations
@@ -1479,6 +1506,7 @@ admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, 
   if (!(alpha > 0)) {
     // largest eigenvalue of H = 2 sum_s A_s^T c_s W A_s by power iteration
     std::vector<float> v(n, static_cast<float>(1.0 / std::sqrt(static_cast<double>(n))));
+    StreamDrain drain{s};
     double lam = 0.0;
     for (int it = 0; it < 30; ++it) {
       check(hipMemcpyAsync(xt, v.data(), sizeof(float) * n, hipMemcpyHostToDevice, s), "H2D");
@@ -1548,7 +1576,8 @@ admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, 
   }
   if (x_out) {
     std::vector<float> xv(n);
-    check(hipMemcpy(xv.data(), x, sizeof(float) * n, hipMemcpyDeviceToHost), "D2H");
+    check(hipMemcpyAsync(xv.data(), x, sizeof(float) * n, hipMemcpyDeviceToHost, s), "D2H");
+    check(hipStreamSynchronize(s), "sync");
     for (int j = 0; j < n; ++j) x_out[j] = xv[j];
   }
   if (info) {
