@@ -277,6 +277,52 @@ struct admm_ctx {
     return f;
   }
 
+  // Gram matrices G_s of the scenarios [g0, g0 + cs) of patient pt into the
+  // chunk buffer (the upper tiles are what the next steps read): per-tile row
+  // lists and one LDS accumulation per tile; where the lists do not fit in
+  // device memory, one fp64 atomic per product (also taken when the
+  // environment sets ADMMBB_GRAM_ATOMIC, which tests use to compare the two).
+  void gram_chunk(const Pat& pt, int g0, int cs, int64_t nn) {
+    struct DevBuf {
+      void* p = nullptr;
+      ~DevBuf() {
+        if (p) (void)hipFree(p);
+      }
+    } bc, bo, bl;
+    const int nb = pt.nbk;
+    const int64_t ntl = static_cast<int64_t>(nb) * (nb + 1) / 2, nt = ntl * cs;
+    bool lists = std::getenv("ADMMBB_GRAM_ATOMIC") == nullptr &&
+                 hipMalloc(&bc.p, sizeof(int32_t) * 2 * nt) == hipSuccess &&
+                 hipMalloc(&bo.p, sizeof(int64_t) * (nt + 1)) == hipSuccess;
+    if (lists) {
+      int32_t* cnt = static_cast<int32_t*>(bc.p);
+      int32_t* cur = cnt + nt;
+      int64_t* off = static_cast<int64_t*>(bo.p);
+      launch_fill_f32(reinterpret_cast<float*>(cnt), 0.0f, 2 * nt, stream);  // counts and cursors
+      for (int s = 0; s < cs; ++s) launch_gram_rows(mat32, H.scen[g0 + s], nb, cnt + s * ntl, nullptr, nullptr, stream);
+      launch_gram_scan(cnt, nt, off, stream);
+      check(hipMemcpyAsync(h_scr, off + nt, sizeof(int64_t), hipMemcpyDeviceToHost, stream), "D2H");
+      check(hipStreamSynchronize(stream), "sync");
+      int64_t total = 0;
+      std::memcpy(&total, h_scr, sizeof(total));
+      lists = total >= 0 && hipMalloc(&bl.p, sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(total, 1))) ==
+                                hipSuccess;
+      if (lists) {
+        int32_t* list = static_cast<int32_t*>(bl.p);
+        for (int s = 0; s < cs; ++s)
+          launch_gram_rows(mat32, H.scen[g0 + s], nb, cur + s * ntl, off + s * ntl, list, stream);
+        launch_gram_tiles(mat32, d_rw64, d_scen, g0, cs, nb, off, list, d_G, pt.npad, stream);
+      }
+    }
+    if (!lists) {
+      (void)hipGetLastError();  // the failed allocation
+      launch_fill_f64(d_G, 0.0, nn * cs, stream);
+      for (int s = 0; s < cs; ++s) launch_gram(mat32, d_rw64, H.scen[g0 + s], d_G + s * nn, pt.npad, stream);
+    }
+    check(hipGetLastError(), "Gram launch");
+    check(hipStreamSynchronize(stream), "sync");  // before the lists are freed
+  }
+
   // (Re)build the cached inverses of patient p at its current penalty, a
   // chunk of scenarios at a time: Gram matrices, B_s = G_s + rho/2 I swept in
   // place, packed fp32 inverses.  With accumulate_gsum (the first time) the
@@ -290,8 +336,7 @@ struct admm_ctx {
     for (int c0 = 0; c0 < pt.num_scen; c0 += chunk) {
       const int cs = std::min(chunk, pt.num_scen - c0);
       const int g0 = pt.scen_begin + c0;
-      launch_fill_f64(d_G, 0.0, nn * cs, stream);
-      for (int s = 0; s < cs; ++s) launch_gram(mat32, d_rw64, H.scen[g0 + s], d_G + s * nn, npad, stream);
+      gram_chunk(pt, g0, cs, nn);
       launch_gram_finish(f, p, g0, cs, npad, pt.n, rho[p], accumulate_gsum ? 1 : 0, stream);
       for (int k0 = 0; k0 < npad; k0 += 64) launch_sweep_step(f, g0, cs, npad, k0, stream);
       launch_sweep_store(f, p, g0, cs, npad, stream);

@@ -83,6 +83,178 @@ __global__ __launch_bounds__(256) void k_gram(MatDev mat, const double* __restri
   }
 }
 
+// Gram matrix by output tiles.  Every stored row adds w_i a_i a_i^T to the
+// 64 x 64 tiles (I, J), I <= J, of the blocks its nonzeros fall in.  Lists of
+// the rows that reach each tile are built first (count, scan, fill); one
+// workgroup per tile then adds its rows' products in LDS and writes the tile
+// once, instead of one global fp64 atomic per product.
+
+template <bool C16>
+__device__ __forceinline__ int col_at(const MatDev& mat, int64_t e) {
+  if constexpr (C16)
+    return static_cast<const uint16_t*>(mat.col)[e];
+  else
+    return static_cast<const int32_t*>(mat.col)[e];
+}
+
+// LDS written by some lanes of a wave and then read by others of the same wave
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kMaxBlocks = 128;  // 64-column blocks of a patient (n <= 8192)
+
+// FILL = false: count[t] += 1 for every tile t = (b_p, b_q), p <= q, of the
+// distinct blocks b_1 < ... < b_r of each row; FILL = true: the row's index at
+// off[t] + (a slot taken from cur[t]).  One wave per stored row.
+template <bool C16, bool FILL>
+__global__ __launch_bounds__(256) void k_gram_rows(MatDev mat, Scen sc, int nb, int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ off, int32_t* __restrict__ list) {
+  __shared__ int bl[4][kMaxBlocks];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = static_cast<int>(blockIdx.x) * 4 + w;
+  if (row >= sc.rows) return;  // no workgroup barrier below
+  const uint32_t c0 = mat.rp[sc.rp_base + row], c1 = mat.rp[sc.rp_base + row + 1];
+  const int64_t e0 = sc.nnz_base + 4 * static_cast<int64_t>(c0);
+  const int k = 4 * static_cast<int>(c1 - c0);
+  int r = 0;
+  for (int base = 0; base < k; base += 64) {
+    const int kk = base + lane;
+    int b = -1, bp = -1;
+    if (kk < k) {
+      b = col_at<C16>(mat, e0 + kk) >> 6;
+      if (kk > 0) bp = col_at<C16>(mat, e0 + kk - 1) >> 6;
+    }
+    const bool start = kk < k && b != bp;  // columns are non-decreasing along a row
+    const uint64_t m = __ballot(start);
+    const int at = r + __popcll(m & ((uint64_t{1} << lane) - 1));
+    if (start && at < kMaxBlocks) bl[w][at] = b;
+    r += __popcll(m);
+  }
+  if (r > kMaxBlocks) r = kMaxBlocks;  // cannot happen for n <= 8192
+  wave_lds_sync();
+  for (int t = lane; t < r * r; t += 64) {
+    const int p = t / r, q = t - p * r;
+    if (p > q) continue;
+    const int64_t ti = tile_index(bl[w][p], bl[w][q], nb);
+    if constexpr (FILL)
+      list[off[ti] + atomicAdd(&cnt[ti], 1)] = row;
+    else
+      atomicAdd(&cnt[ti], 1);
+  }
+}
+
+// off[i] = cnt[0] + ... + cnt[i - 1] for i <= nt (one workgroup)
+__global__ __launch_bounds__(1024) void k_gram_scan(const int32_t* __restrict__ cnt, int64_t nt,
+                                                    int64_t* __restrict__ off) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (nt + 1023) / 1024;
+  const int64_t b = t * per < nt ? t * per : nt, e = b + per < nt ? b + per : nt;
+  int64_t sum = 0;
+  for (int64_t i = b; i < e; ++i) sum += cnt[i];
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int64_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    off[nt] = run;
+  }
+  __syncthreads();
+  int64_t run = part[t];
+  for (int64_t i = b; i < e; ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+}
+
+// One workgroup per tile (I, J) of scenario g0 + blockIdx.y: the rows of its
+// list add c_s w_i a_ij a_ik for j in block I, k in block J (j <= k inside a
+// diagonal tile) to an fp64 LDS tile, which is then written to G (upper part).
+// A row's nonzeros in one block are contiguous and number at most 64 (plus
+// padding of value 0), so one wave holds both segments and forms the products
+// through lane shuffles.
+template <bool C16>
+__global__ __launch_bounds__(256) void k_gram_tiles(MatDev mat, const double* __restrict__ rw64,
+                                                    const Scen* __restrict__ scen, int g0, int nb,
+                                                    const int64_t* __restrict__ off, const int32_t* __restrict__ list,
+                                                    double* __restrict__ G, int ld) {
+  __shared__ double acc[kFb * kFb];
+  const int64_t ntiles = static_cast<int64_t>(nb) * (nb + 1) / 2;
+  const int64_t t = blockIdx.x;
+  const int s = static_cast<int>(blockIdx.y);
+  int I = 0;
+  int64_t rem = t;
+  while (rem >= nb - I) {
+    rem -= nb - I;
+    ++I;
+  }
+  const int J = I + static_cast<int>(rem);
+  for (int e = threadIdx.x; e < kFb * kFb; e += 256) acc[e] = 0.0;
+  __syncthreads();
+  const Scen sc = scen[g0 + s];
+  const float* val = static_cast<const float*>(mat.val);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t lb = off[s * ntiles + t], le = off[s * ntiles + t + 1];
+  for (int64_t li = lb + w; li < le; li += 4) {
+    const int row = list[li];
+    const uint32_t c0 = mat.rp[sc.rp_base + row], c1 = mat.rp[sc.rp_base + row + 1];
+    const int64_t e0 = sc.nnz_base + 4 * static_cast<int64_t>(c0);
+    const int k = 4 * static_cast<int>(c1 - c0);
+    int fI = 0, nI = 0, fJ = 0, nJ = 0;
+    for (int base = 0; base < k; base += 64) {
+      const int kk = base + lane;
+      const int b = kk < k ? (col_at<C16>(mat, e0 + kk) >> 6) : -1;
+      const uint64_t mI = __ballot(b == I), mJ = __ballot(b == J);
+      if (nI == 0 && mI) fI = base + __ffsll(static_cast<unsigned long long>(mI)) - 1;
+      if (nJ == 0 && mJ) fJ = base + __ffsll(static_cast<unsigned long long>(mJ)) - 1;
+      nI += __popcll(mI);
+      nJ += __popcll(mJ);
+    }
+    const double rw = rw64[sc.row_base + row];
+    for (int a0 = 0; a0 < nI; a0 += 64) {
+      const int na = nI - a0 < 64 ? nI - a0 : 64;
+      int ci = 0;
+      double vi = 0.0;
+      if (lane < na) {
+        ci = col_at<C16>(mat, e0 + fI + a0 + lane) & (kFb - 1);
+        vi = rw * static_cast<double>(val[e0 + fI + a0 + lane]);
+      }
+      for (int b0 = 0; b0 < nJ; b0 += 64) {
+        const int nq = nJ - b0 < 64 ? nJ - b0 : 64;
+        int cj = 0;
+        double vj = 0.0;
+        if (lane < nq) {
+          cj = col_at<C16>(mat, e0 + fJ + b0 + lane) & (kFb - 1);
+          vj = static_cast<double>(val[e0 + fJ + b0 + lane]);
+        }
+        const int np = na * nq;
+        for (int p0 = 0; p0 < np; p0 += 64) {
+          const int p = p0 + lane;
+          const bool in = p < np;
+          const int a = in ? p / nq : 0, q = in ? p - (p / nq) * nq : 0;
+          const double va = __shfl(vi, a, 64), vb = __shfl(vj, q, 64);
+          const int ca = __shfl(ci, a, 64), cb = __shfl(cj, q, 64);
+          const double prod = va * vb;
+          if (in && (I != J || a0 + a <= b0 + q) && prod != 0.0) unsafeAtomicAdd(&acc[ca * kFb + cb], prod);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double* Gs = G + static_cast<int64_t>(s) * ld * ld;
+  for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
+    const int r = e / kFb, c = e % kFb;
+    if (I != J || r <= c) Gs[static_cast<int64_t>(I * kFb + r) * ld + J * kFb + c] = acc[e];
+  }
+}
+
 // For the chunk of scenarios [scen_begin, scen_begin + nscen) of one patient
 // (chunk buffers, npad x npad per scenario, upper triangle of G accumulated):
 // the upper tiles of A = G + rho/2 I (identity on the padding; inside a
@@ -477,6 +649,38 @@ void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G,
     hipLaunchKernelGGL(k_gram<true>, dim3(nb), dim3(256), 0, st, m, rw64, sc, G, ld);
   else
     hipLaunchKernelGGL(k_gram<false>, dim3(nb), dim3(256), 0, st, m, rw64, sc, G, ld);
+}
+
+void launch_gram_rows(const MatDev& m, const Scen& sc, int nb, int32_t* cnt, const int64_t* off, int32_t* list,
+                      hipStream_t st) {
+  if (sc.rows <= 0) return;
+  const unsigned g = static_cast<unsigned>((sc.rows + 3) / 4);
+  if (m.col16) {
+    if (list)
+      hipLaunchKernelGGL((k_gram_rows<true, true>), dim3(g), dim3(256), 0, st, m, sc, nb, cnt, off, list);
+    else
+      hipLaunchKernelGGL((k_gram_rows<true, false>), dim3(g), dim3(256), 0, st, m, sc, nb, cnt, off, list);
+  } else {
+    if (list)
+      hipLaunchKernelGGL((k_gram_rows<false, true>), dim3(g), dim3(256), 0, st, m, sc, nb, cnt, off, list);
+    else
+      hipLaunchKernelGGL((k_gram_rows<false, false>), dim3(g), dim3(256), 0, st, m, sc, nb, cnt, off, list);
+  }
+}
+
+void launch_gram_scan(const int32_t* cnt, int64_t nt, int64_t* off, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_scan, dim3(1), dim3(1024), 0, st, cnt, nt, off);
+}
+
+void launch_gram_tiles(const MatDev& m, const double* rw64, const Scen* scen, int g0, int nscen, int nb,
+                       const int64_t* off, const int32_t* list, double* G, int ld, hipStream_t st) {
+  const unsigned nt = static_cast<unsigned>(static_cast<int64_t>(nb) * (nb + 1) / 2);
+  if (m.col16)
+    hipLaunchKernelGGL(k_gram_tiles<true>, dim3(nt, static_cast<unsigned>(nscen)), dim3(256), 0, st, m, rw64, scen,
+                       g0, nb, off, list, G, ld);
+  else
+    hipLaunchKernelGGL(k_gram_tiles<false>, dim3(nt, static_cast<unsigned>(nscen)), dim3(256), 0, st, m, rw64, scen,
+                       g0, nb, off, list, G, ld);
 }
 
 void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, int npad, int n, double rho,

@@ -4,6 +4,8 @@ also solves every subproblem exactly (Cholesky): the iterates themselves must
 agree, not only the final objective."""
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -161,3 +163,59 @@ def test_dense_x_update_near_its_size_limit():
         assert stc == 0, infoc
         f_cg = wls.objective(W, zc[0])
     assert abs(f_dense - f_cg) <= 1e-5 * f_cg, (f_dense, f_cg)
+
+
+def _long_segment_problem():
+    """n = 130 spots (64-column blocks of 64, 64 and 2 columns) with three rows
+    planted in scenario 0: columns {0} and 64..127 (65 nonzeros; the stored row
+    is padded to a multiple of 4 by repeating column 127, so block 1 holds 67
+    entries), every column (130) and columns 0..127 (128, no padding).  Their
+    values exceed every other entry, so a lost or doubled product shows."""
+    P = synth.make_tiny(3, spots=(10, 13), num_scen=2)
+    assert P.n == 130
+    a = P.A[0]
+    rng = np.random.default_rng(11)
+    rows = [(a.col[a.row_ptr[i]:a.row_ptr[i + 1]], a.val[a.row_ptr[i]:a.row_ptr[i + 1]]) for i in range(P.m)]
+    planted = [np.concatenate([[0], np.arange(64, 128)]), np.arange(130), np.arange(128)]
+    vmax = float(a.val.max())
+    for r, cols in zip(np.flatnonzero(P.struct_id == 1)[:3], planted):
+        rows[r] = (cols.astype(np.int32), (vmax * rng.uniform(1.0, 2.0, cols.size)).astype(np.float32))
+    lens = np.array([c.size for c, _ in rows])
+    A0 = synth.Csr(row_ptr=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64),
+                   col=np.concatenate([c for c, _ in rows]).astype(np.int32),
+                   val=np.concatenate([v for _, v in rows]).astype(np.float32))
+    return dataclasses.replace(P, A=[A0, P.A[1]])
+
+
+def _first_x_update(P, monkeypatch, atomic):
+    """x_s after one iteration from z = 0, y = 0 (the solutions of B_s x_s = b_s),
+    with the Gram matrices formed by per-tile lists or by global atomics."""
+    import paper_2304_14568_amd as A
+    if atomic:
+        monkeypatch.setenv("ADMMBB_GRAM_ATOMIC", "1")
+    else:
+        monkeypatch.delenv("ADMMBB_GRAM_ATOMIC", raising=False)
+    with A.Solver(P, xupdate="dense") as S:
+        assert S.xupdate()[0] == "dense"
+        rho = S.rho()
+        S.iterate(1)
+        st = S.get_state()
+    monkeypatch.delenv("ADMMBB_GRAM_ATOMIC", raising=False)
+    z = np.asarray(st["z"])
+    d = np.asarray(st["d"]).reshape(P.num_scen, P.n)
+    return rho, d + z[None, :]
+
+
+@pytest.mark.parametrize("which", ["planted", "hn_small"])
+def test_tile_gram_matches_the_normal_equations_and_the_atomic_gram(which, monkeypatch):
+    P = _long_segment_problem() if which == "planted" else synth.hn_small(6)
+    W = wls.from_problem(P)
+    rho, x_tile = _first_x_update(P, monkeypatch, atomic=False)
+    rho_a, x_atom = _first_x_update(P, monkeypatch, atomic=True)
+    assert rho == rho_a
+    for s in range(P.num_scen):
+        b = W.A[s].T @ (W.c[s] * W.w * W.p)
+        r = wls.normal_apply(W, s, x_tile[s], rho) - b
+        assert np.linalg.norm(r) <= 1e-4 * np.linalg.norm(b), np.linalg.norm(r) / np.linalg.norm(b)
+        # both Gram paths give the same inverse up to its fp32 rounding
+        assert np.linalg.norm(x_tile[s] - x_atom[s]) <= 1e-6 * np.linalg.norm(x_atom[s])
