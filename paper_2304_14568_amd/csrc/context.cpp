@@ -305,10 +305,10 @@ struct admm_ctx {
       check(hipStreamSynchronize(stream), "sync");
       int64_t total = 0;
       std::memcpy(&total, h_scr, sizeof(total));
-      lists = total >= 0 && hipMalloc(&bl.p, sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(total, 1))) ==
+      lists = total >= 0 && hipMalloc(&bl.p, sizeof(GramEntry) * static_cast<size_t>(std::max<int64_t>(total, 1))) ==
                                 hipSuccess;
       if (lists) {
-        int32_t* list = static_cast<int32_t*>(bl.p);
+        GramEntry* list = static_cast<GramEntry*>(bl.p);
         for (int s = 0; s < cs; ++s)
           launch_gram_rows(mat32, H.scen[g0 + s], nb, cur + s * ntl, off + s * ntl, list, stream);
         launch_gram_tiles(mat32, d_rw64, d_scen, g0, cs, nb, off, list, d_G, pt.npad, stream);

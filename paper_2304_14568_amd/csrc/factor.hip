@@ -107,11 +107,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int kMaxBlocks = 128;  // 64-column blocks of a patient (n <= 8192)
 
 // FILL = false: count[t] += 1 for every tile t = (b_p, b_q), p <= q, of the
-// distinct blocks b_1 < ... < b_r of each row; FILL = true: the row's index at
-// off[t] + (a slot taken from cur[t]).  One wave per stored row.
+// distinct blocks b_1 < ... < b_r of each row; FILL = true: the row and its
+// extent at off[t] + (a slot taken from cur[t]).  One wave per stored row.
 template <bool C16, bool FILL>
 __global__ __launch_bounds__(256) void k_gram_rows(MatDev mat, Scen sc, int nb, int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ off, int32_t* __restrict__ list) {
+                                                   const int64_t* __restrict__ off, GramEntry* __restrict__ list) {
   __shared__ int bl[4][kMaxBlocks];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = static_cast<int>(blockIdx.x) * 4 + w;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_gram_rows(MatDev mat, Scen sc, int nb, 
     if (p > q) continue;
     const int64_t ti = tile_index(bl[w][p], bl[w][q], nb);
     if constexpr (FILL)
-      list[off[ti] + atomicAdd(&cnt[ti], 1)] = row;
+      list[off[ti] + atomicAdd(&cnt[ti], 1)] = GramEntry{row, c0, c1, 0};
     else
       atomicAdd(&cnt[ti], 1);
   }
@@ -177,15 +177,23 @@ __global__ __launch_bounds__(1024) void k_gram_scan(const int32_t* __restrict__ 
 // One workgroup per tile (I, J) of scenario g0 + blockIdx.y: the rows of its
 // list add c_s w_i a_ij a_ik for j in block I, k in block J (j <= k inside a
 // diagonal tile) to an fp64 LDS tile, which is then written to G (upper part).
-// A row's nonzeros in one block are contiguous and number at most 64 (plus
-// padding of value 0), so one wave holds both segments and forms the products
-// through lane shuffles.
+// A row's nonzeros in one block are contiguous (at most 64, plus padding of
+// value 0).  Each wave takes one listed row at a time: its columns and values
+// are read once (with the next list entry already in flight) and staged in the
+// wave's LDS area, from which the products are formed; rows longer than the
+// staging area are read from memory instead.
+constexpr int kGramWaves = 8;
+constexpr int kGramStage = 320;
+
 template <bool C16>
-__global__ __launch_bounds__(256) void k_gram_tiles(MatDev mat, const double* __restrict__ rw64,
-                                                    const Scen* __restrict__ scen, int g0, int nb,
-                                                    const int64_t* __restrict__ off, const int32_t* __restrict__ list,
-                                                    double* __restrict__ G, int ld) {
+__global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, const double* __restrict__ rw64,
+                                                                const Scen* __restrict__ scen, int g0, int nb,
+                                                                const int64_t* __restrict__ off,
+                                                                const GramEntry* __restrict__ list,
+                                                                double* __restrict__ G, int ld) {
   __shared__ double acc[kFb * kFb];
+  __shared__ float sval[kGramWaves][kGramStage];
+  __shared__ uint8_t scol[kGramWaves][kGramStage];
   const int64_t ntiles = static_cast<int64_t>(nb) * (nb + 1) / 2;
   const int64_t t = blockIdx.x;
   const int s = static_cast<int>(blockIdx.y);
@@ -196,60 +204,70 @@ __global__ __launch_bounds__(256) void k_gram_tiles(MatDev mat, const double* __
     ++I;
   }
   const int J = I + static_cast<int>(rem);
-  for (int e = threadIdx.x; e < kFb * kFb; e += 256) acc[e] = 0.0;
+  for (int e = threadIdx.x; e < kFb * kFb; e += 64 * kGramWaves) acc[e] = 0.0;
   __syncthreads();
   const Scen sc = scen[g0 + s];
   const float* val = static_cast<const float*>(mat.val);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t lb = off[s * ntiles + t], le = off[s * ntiles + t + 1];
-  for (int64_t li = lb + w; li < le; li += 4) {
-    const int row = list[li];
-    const uint32_t c0 = mat.rp[sc.rp_base + row], c1 = mat.rp[sc.rp_base + row + 1];
-    const int64_t e0 = sc.nnz_base + 4 * static_cast<int64_t>(c0);
-    const int k = 4 * static_cast<int>(c1 - c0);
+  float* sv = sval[w];
+  uint8_t* scl = scol[w];
+  const int64_t le = off[s * ntiles + t + 1];
+  int64_t li = off[s * ntiles + t] + w;
+  GramEntry cur{};
+  if (li < le) cur = list[li];
+  for (; li < le; li += kGramWaves) {
+    GramEntry nxt{};
+    if (li + kGramWaves < le) nxt = list[li + kGramWaves];
+    const int64_t e0 = sc.nnz_base + 4 * static_cast<int64_t>(cur.c0);
+    const int k = 4 * static_cast<int>(cur.c1 - cur.c0);
+    const bool staged = k <= kGramStage;
+    const double rw = rw64[sc.row_base + cur.row];
     int fI = 0, nI = 0, fJ = 0, nJ = 0;
     for (int base = 0; base < k; base += 64) {
       const int kk = base + lane;
-      const int b = kk < k ? (col_at<C16>(mat, e0 + kk) >> 6) : -1;
+      int b = -1;
+      if (kk < k) {
+        const int c = col_at<C16>(mat, e0 + kk);
+        b = c >> 6;
+        if (staged) {
+          sv[kk] = val[e0 + kk];
+          scl[kk] = static_cast<uint8_t>(c & (kFb - 1));
+        }
+      }
       const uint64_t mI = __ballot(b == I), mJ = __ballot(b == J);
       if (nI == 0 && mI) fI = base + __ffsll(static_cast<unsigned long long>(mI)) - 1;
       if (nJ == 0 && mJ) fJ = base + __ffsll(static_cast<unsigned long long>(mJ)) - 1;
       nI += __popcll(mI);
       nJ += __popcll(mJ);
     }
-    const double rw = rw64[sc.row_base + row];
-    for (int a0 = 0; a0 < nI; a0 += 64) {
-      const int na = nI - a0 < 64 ? nI - a0 : 64;
-      int ci = 0;
-      double vi = 0.0;
-      if (lane < na) {
-        ci = col_at<C16>(mat, e0 + fI + a0 + lane) & (kFb - 1);
-        vi = rw * static_cast<double>(val[e0 + fI + a0 + lane]);
+    wave_lds_sync();
+    const int np = nI * nJ;
+    for (int p = lane; p < np; p += 64) {
+      const int a = p / nJ, q = p - a * nJ;
+      if (I == J && a > q) continue;
+      const int pa = fI + a, pb = fJ + q;
+      double va, vb;
+      int ca, cb;
+      if (staged) {
+        va = sv[pa];
+        vb = sv[pb];
+        ca = scl[pa];
+        cb = scl[pb];
+      } else {
+        va = val[e0 + pa];
+        vb = val[e0 + pb];
+        ca = col_at<C16>(mat, e0 + pa) & (kFb - 1);
+        cb = col_at<C16>(mat, e0 + pb) & (kFb - 1);
       }
-      for (int b0 = 0; b0 < nJ; b0 += 64) {
-        const int nq = nJ - b0 < 64 ? nJ - b0 : 64;
-        int cj = 0;
-        double vj = 0.0;
-        if (lane < nq) {
-          cj = col_at<C16>(mat, e0 + fJ + b0 + lane) & (kFb - 1);
-          vj = static_cast<double>(val[e0 + fJ + b0 + lane]);
-        }
-        const int np = na * nq;
-        for (int p0 = 0; p0 < np; p0 += 64) {
-          const int p = p0 + lane;
-          const bool in = p < np;
-          const int a = in ? p / nq : 0, q = in ? p - (p / nq) * nq : 0;
-          const double va = __shfl(vi, a, 64), vb = __shfl(vj, q, 64);
-          const int ca = __shfl(ci, a, 64), cb = __shfl(cj, q, 64);
-          const double prod = va * vb;
-          if (in && (I != J || a0 + a <= b0 + q) && prod != 0.0) unsafeAtomicAdd(&acc[ca * kFb + cb], prod);
-        }
-      }
+      const double prod = (rw * va) * vb;
+      if (prod != 0.0) unsafeAtomicAdd(&acc[ca * kFb + cb], prod);
     }
+    wave_lds_sync();  // the next row overwrites the staging area
+    cur = nxt;
   }
   __syncthreads();
   double* Gs = G + static_cast<int64_t>(s) * ld * ld;
-  for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
+  for (int e = threadIdx.x; e < kFb * kFb; e += 64 * kGramWaves) {
     const int r = e / kFb, c = e % kFb;
     if (I != J || r <= c) Gs[static_cast<int64_t>(I * kFb + r) * ld + J * kFb + c] = acc[e];
   }
@@ -651,7 +669,7 @@ void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G,
     hipLaunchKernelGGL(k_gram<false>, dim3(nb), dim3(256), 0, st, m, rw64, sc, G, ld);
 }
 
-void launch_gram_rows(const MatDev& m, const Scen& sc, int nb, int32_t* cnt, const int64_t* off, int32_t* list,
+void launch_gram_rows(const MatDev& m, const Scen& sc, int nb, int32_t* cnt, const int64_t* off, GramEntry* list,
                       hipStream_t st) {
   if (sc.rows <= 0) return;
   const unsigned g = static_cast<unsigned>((sc.rows + 3) / 4);
@@ -673,14 +691,13 @@ void launch_gram_scan(const int32_t* cnt, int64_t nt, int64_t* off, hipStream_t 
 }
 
 void launch_gram_tiles(const MatDev& m, const double* rw64, const Scen* scen, int g0, int nscen, int nb,
-                       const int64_t* off, const int32_t* list, double* G, int ld, hipStream_t st) {
+                       const int64_t* off, const GramEntry* list, double* G, int ld, hipStream_t st) {
   const unsigned nt = static_cast<unsigned>(static_cast<int64_t>(nb) * (nb + 1) / 2);
+  const dim3 grid(nt, static_cast<unsigned>(nscen)), block(64 * kGramWaves);
   if (m.col16)
-    hipLaunchKernelGGL(k_gram_tiles<true>, dim3(nt, static_cast<unsigned>(nscen)), dim3(256), 0, st, m, rw64, scen,
-                       g0, nb, off, list, G, ld);
+    hipLaunchKernelGGL(k_gram_tiles<true>, grid, block, 0, st, m, rw64, scen, g0, nb, off, list, G, ld);
   else
-    hipLaunchKernelGGL(k_gram_tiles<false>, dim3(nt, static_cast<unsigned>(nscen)), dim3(256), 0, st, m, rw64, scen,
-                       g0, nb, off, list, G, ld);
+    hipLaunchKernelGGL(k_gram_tiles<false>, grid, block, 0, st, m, rw64, scen, g0, nb, off, list, G, ld);
 }
 
 void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, int npad, int n, double rho,

@@ -245,11 +245,16 @@ int dose_hist_smem_bytes(int G, int nbins);
 void launch_gram(const MatDev& m, const double* rw64, const Scen& sc, double* G, int ld, hipStream_t st);
 // Gram matrix by output tiles: per-tile row lists (count with list == nullptr,
 // then fill), their offsets, and one workgroup per tile and scenario
-void launch_gram_rows(const MatDev& m, const Scen& sc, int nb, int32_t* cnt, const int64_t* off, int32_t* list,
+struct GramEntry {  // one stored row in a tile's list: its index and its extent in 4-element chunks
+  int32_t row;
+  uint32_t c0, c1;
+  int32_t pad;
+};
+void launch_gram_rows(const MatDev& m, const Scen& sc, int nb, int32_t* cnt, const int64_t* off, GramEntry* list,
                       hipStream_t st);
 void launch_gram_scan(const int32_t* cnt, int64_t nt, int64_t* off, hipStream_t st);
 void launch_gram_tiles(const MatDev& m, const double* rw64, const Scen* scen, int g0, int nscen, int nb,
-                       const int64_t* off, const int32_t* list, double* G, int ld, hipStream_t st);
+                       const int64_t* off, const GramEntry* list, double* G, int ld, hipStream_t st);
 void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, int npad, int n, double rho,
                         int accumulate_gsum, hipStream_t st);
 void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st);
