@@ -3,8 +3,11 @@
 // + rho/2 I once and reuses the factor in every iteration; here the factor is
 // the inverse itself, so that each x-update is one bandwidth-bound GEMV).
 //
-//  1. k_gram: G_s = A_s^T diag(c_s w) A_s, upper triangle, fp64 atomics (one
-//     wave per stored row: every pair j <= k of its nonzeros).
+//  1. G_s = A_s^T diag(c_s w) A_s, upper 64 x 64 tiles: lists of the rows
+//     that reach each tile (k_gram_rows, k_gram_scan), then one workgroup per
+//     tile adds its rows' products in LDS (k_gram_tiles).  k_gram (one fp64
+//     atomic per product, one wave per stored row) is the fallback when the
+//     lists do not fit in device memory.
 //  2. k_gram_finish: the upper tiles of the sweep work matrix
 //     A = G_s + rho/2 I (identity on the padding to npad) and sum_s G_s.
 //     Steps 1-3 run on chunks of scenarios, so that only a chunk's fp64
