@@ -156,6 +156,10 @@ def main():
     ref, xstar = load_ref(f"hn_full_s{args.seed}")
     fstar = ref["f_star"] if (ref is not None and ref["digest"] == digest) else None
 
+    # the process's GPU runtime start-up (paid once per process, by whatever
+    # touches the device first) stays outside the solver's set-up time
+    torch.zeros(1, device=dev).add_(1.0)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = A.Solver(P, precision=args.precision, cg_max=args.cg_max, max_iter=2000, stream=stream,
                  use_graph=1 if args.graph else 0, xupdate=args.xupdate)

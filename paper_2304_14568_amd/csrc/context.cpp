@@ -880,6 +880,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       c->d_rw64 = c->upload(H.rw64);
       c->factored_rho.assign(num_patients, 0.0);
     }
+    clk.mark("dense buffers and tables");
     c->d_scen = c->upload(H.scen);
     c->d_pat = c->upload(H.pat);
     c->d_tiles = c->upload(H.tiles);
@@ -892,6 +893,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     const float* d_rpres = c->upload(H.rpres);
     const int32_t* d_rorig = c->upload(H.rorig);
     c->mat32 = MatDev{d_rp, d_col, c->upload(H.val), nullptr, d_rw, d_rpres, d_rorig, H.col16_used ? 1 : 0, VAL_F32};
+    clk.mark("sparse matrix upload");
     // the host copies of the largest arrays are not needed after upload
     decltype(H.val)().swap(H.val);
     if (o.precision != ADMM_PREC_FP32) {
@@ -945,7 +947,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     check(hipMemsetAsync(c->d_cgcount, 0, sizeof(int32_t) * c->G, c->stream), "memset");
     check(hipMemsetAsync(c->d_cgtotal, 0, sizeof(int64_t) * c->G, c->stream), "memset");
     check(hipStreamSynchronize(c->stream), "setup sync");
-    clk.mark("device tables and uploads");
+    clk.mark("other buffers and uploads");
     if (c->dense) {
       hipEvent_t f0, f1;
       check(hipEventCreate(&f0), "hipEventCreate");
