@@ -309,46 +309,49 @@ __global__ __launch_bounds__(256) void k_gram_finish(FactorArgs f, int patient, 
 // block sweep
 // ---------------------------------------------------------------------------
 
-// P = A_KK^-1 by the scalar sweep in LDS (one workgroup per scenario)
+// P = A_KK^-1 by the scalar sweep (one workgroup per scenario)
 __global__ __launch_bounds__(256) void k_sweep_pivot(FactorArgs f, int scen_begin, int npad, int k0) {
-  __shared__ double a[kFb][kFb + 1];
+  // thread (i0, j) keeps rows i0, i0 + 4, ..., i0 + 60 of column j in
+  // registers; each step publishes only the pivot row and column (their values
+  // before the step) through LDS
+  __shared__ double prow[kFb], pcol[kFb];
   const int g = scen_begin + static_cast<int>(blockIdx.x);
   const double* A = f.A + static_cast<int64_t>(blockIdx.x) * npad * npad;  // chunk buffer
-  for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
-    const int i = e / kFb, j = e % kFb;
-    a[i][j] = A[static_cast<int64_t>(k0 + i) * npad + k0 + j];
-  }
-  __syncthreads();
-  double nv[16];
+  const int j = threadIdx.x & (kFb - 1), i0 = threadIdx.x >> 6;
+  double r[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) r[q] = A[static_cast<int64_t>(k0 + i0 + 4 * q) * npad + k0 + j];
+#pragma unroll
   for (int t = 0; t < kFb; ++t) {
-    const double d = a[t][t];
-    const double inv = 1.0 / d;
+    if (i0 == (t & 3)) prow[j] = r[t >> 2];
+    if (j == t) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) pcol[i0 + 4 * q] = r[q];
+    }
+    __syncthreads();
+    const double inv = 1.0 / prow[t];
+    const double atj = prow[j];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + q * 256;
-      const int i = e / kFb, j = e % kFb;
+      const int i = i0 + 4 * q;
+      const double ait = pcol[i];
       double v;
       if (i == t && j == t)
         v = -inv;
       else if (i == t)
-        v = a[t][j] * inv;
+        v = atj * inv;
       else if (j == t)
-        v = a[i][t] * inv;
+        v = ait * inv;
       else
-        v = a[i][j] - a[i][t] * a[t][j] * inv;
-      nv[q] = v;
+        v = r[q] - ait * atj * inv;
+      r[q] = v;
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + q * 256;
-      a[e / kFb][e % kFb] = nv[q];
-    }
-    __syncthreads();
+    __syncthreads();  // the next step overwrites the pivot row and column
   }
   // the swept block is -A_KK^-1
   double* P = f.P + static_cast<int64_t>(g) * kFb * kFb;
-  for (int e = threadIdx.x; e < kFb * kFb; e += 256) P[e] = -a[e / kFb][e % kFb];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) P[(i0 + 4 * q) * kFb + j] = -r[q];
 }
 
 // U_I = A_IK P (64 x 64 per workgroup) and R tile = A_K,I (old row panel copy).
