@@ -435,20 +435,37 @@ __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_beg
     }
     return;
   }
-  for (int e = threadIdx.x; e < kFb * kFb; e += 256) {
+  // thread (ti, tj) updates rows 4 ti .. 4 ti + 3 and columns tj, tj + 16,
+  // tj + 32, tj + 48 of the tile; its old values and both panels are all
+  // requested before the first use
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  double a_old[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a_old[q][r] = A[static_cast<int64_t>(i0 + 4 * ti + q) * npad + j0 + tj + 16 * r];
+  double us[16], rr[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = threadIdx.x + 256 * k;
     const int t = e / kFb, c = e % kFb;
-    ut[t][c] = Ut[static_cast<int64_t>(t) * npad + i0 + c];
-    rs[t][c] = R[static_cast<int64_t>(t) * npad + j0 + c];
+    us[k] = Ut[static_cast<int64_t>(t) * npad + i0 + c];
+    rr[k] = R[static_cast<int64_t>(t) * npad + j0 + c];
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    ut[e / kFb][e % kFb] = us[k];
+    rs[e / kFb][e % kFb] = rr[k];
   }
   __syncthreads();
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
   double acc[4][4] = {};
   for (int t = 0; t < kFb; ++t) {
     double uv[4], rv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       uv[q] = ut[t][4 * ti + q];
-      rv[q] = rs[t][4 * tj + q];
+      rv[q] = rs[t][tj + 16 * q];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -458,10 +475,8 @@ __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_beg
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t o = static_cast<int64_t>(i0 + 4 * ti + q) * npad + j0 + 4 * tj + r;
-      A[o] -= acc[q][r];
-    }
+    for (int r = 0; r < 4; ++r)
+      A[static_cast<int64_t>(i0 + 4 * ti + q) * npad + j0 + tj + 16 * r] = a_old[q][r] - acc[q][r];
 }
 
 // packed M = -A (upper tiles) in fp32, for the chunk of scenarios starting at scen_begin
