@@ -194,7 +194,9 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
                                                                 const int64_t* __restrict__ off,
                                                                 const GramEntry* __restrict__ list,
                                                                 double* __restrict__ G, int ld) {
-  __shared__ double acc[kFb * kFb];
+  // row stride kFb + 1: the lanes of one atomic instruction mostly share a
+  // column and differ in the row, so rows must fall in different banks
+  __shared__ double acc[kFb * (kFb + 1)];
   __shared__ float sval[kGramWaves][kGramStage];
   __shared__ uint8_t scol[kGramWaves][kGramStage];
   const int64_t ntiles = static_cast<int64_t>(nb) * (nb + 1) / 2;
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
     ++I;
   }
   const int J = I + static_cast<int>(rem);
-  for (int e = threadIdx.x; e < kFb * kFb; e += 64 * kGramWaves) acc[e] = 0.0;
+  for (int e = threadIdx.x; e < kFb * (kFb + 1); e += 64 * kGramWaves) acc[e] = 0.0;
   __syncthreads();
   const Scen sc = scen[g0 + s];
   const float* val = static_cast<const float*>(mat.val);
@@ -244,9 +246,12 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
       nJ += __popcll(mJ);
     }
     wave_lds_sync();
+    // a = p / nJ as (p * mJ) >> 19: exact for p < 67 * 67 and nJ <= 67, the
+    // largest segments (64 columns of a block plus 3 entries of padding)
     const int np = nI * nJ;
+    const uint32_t mJ = nJ > 0 ? (uint32_t{1} << 19) / static_cast<uint32_t>(nJ) + 1 : 0;
     for (int p = lane; p < np; p += 64) {
-      const int a = p / nJ, q = p - a * nJ;
+      const int a = static_cast<int>((static_cast<uint32_t>(p) * mJ) >> 19), q = p - a * nJ;
       if (I == J && a > q) continue;
       const int pa = fI + a, pb = fJ + q;
       double va, vb;
@@ -263,7 +268,7 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
         cb = col_at<C16>(mat, e0 + pb) & (kFb - 1);
       }
       const double prod = (rw * va) * vb;
-      if (prod != 0.0) unsafeAtomicAdd(&acc[ca * kFb + cb], prod);
+      if (prod != 0.0) unsafeAtomicAdd(&acc[ca * (kFb + 1) + cb], prod);
     }
     wave_lds_sync();  // the next row overwrites the staging area
     cur = nxt;
@@ -272,7 +277,7 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
   double* Gs = G + static_cast<int64_t>(s) * ld * ld;
   for (int e = threadIdx.x; e < kFb * kFb; e += 64 * kGramWaves) {
     const int r = e / kFb, c = e % kFb;
-    if (I != J || r <= c) Gs[static_cast<int64_t>(I * kFb + r) * ld + J * kFb + c] = acc[e];
+    if (I != J || r <= c) Gs[static_cast<int64_t>(I * kFb + r) * ld + J * kFb + c] = acc[r * (kFb + 1) + c];
   }
 }
 
