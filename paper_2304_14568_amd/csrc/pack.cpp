@@ -259,27 +259,38 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         pm = std::max(pm, cwi * pr.presc[i]);
         const int64_t dst = r.nnz_base + 4 * static_cast<int64_t>(off);
         const float scl = rmax > 0.0f ? rmax : 1.0f;
-        for (int64_t t = 0; t < len4; ++t) {
-          // pad the row to whole 4-element chunks: value 0, column = the row's last column
-          const int64_t src = t < len ? b + t : e - 1;
-          const int32_t j = A.col[src];
-          const float v = t < len ? A.val[src] : 0.0f;
-          if (P.col16_used)
-            P.col16[static_cast<size_t>(dst + t)] = static_cast<uint16_t>(j);
-          else
-            P.col32[static_cast<size_t>(dst + t)] = j;
-          P.val[static_cast<size_t>(dst + t)] = v;
-          if (lp) {
-            const float qv = v / scl;
-            P.val_lp[static_cast<size_t>(dst + t)] =
-                t < len ? (o.precision == ADMM_PREC_BF16 ? to_bf16_bits(qv) : to_f16_bits(qv)) : 0;
+        const int32_t* colp = A.col + b;
+        const float* valp = A.val + b;
+        // the row, padded to whole 4-element chunks (value 0, column = the
+        // row's last column)
+        if (P.col16_used) {
+          uint16_t* cd = P.col16.data() + dst;
+          for (int64_t t = 0; t < len; ++t) cd[t] = static_cast<uint16_t>(colp[t]);
+          for (int64_t t = len; t < len4; ++t) cd[t] = static_cast<uint16_t>(colp[len - 1]);
+        } else {
+          int32_t* cd = P.col32.data() + dst;
+          for (int64_t t = 0; t < len; ++t) cd[t] = colp[t];
+          for (int64_t t = len; t < len4; ++t) cd[t] = colp[len - 1];
+        }
+        float* vd = P.val.data() + dst;
+        for (int64_t t = 0; t < len; ++t) vd[t] = valp[t];
+        for (int64_t t = len; t < len4; ++t) vd[t] = 0.0f;
+        if (lp) {
+          uint16_t* ld = P.val_lp.data() + dst;
+          const bool bf = o.precision == ADMM_PREC_BF16;
+          for (int64_t t = 0; t < len; ++t) {
+            const float qv = valp[t] / scl;
+            ld[t] = bf ? to_bf16_bits(qv) : to_f16_bits(qv);
           }
-          if (t < len) {
-            r.b[j] += cwi * pr.presc[i] * static_cast<double>(v);
-            r.gdiag[j] += cwi * static_cast<double>(v) * static_cast<double>(v);
-            if (colsum[j] == 0.0) touched.push_back(j);
-            colsum[j] += v;
-          }
+          for (int64_t t = len; t < len4; ++t) ld[t] = 0;
+        }
+        for (int64_t t = 0; t < len; ++t) {
+          const int32_t j = colp[t];
+          const float v = valp[t];
+          r.b[j] += cwi * pr.presc[i] * static_cast<double>(v);
+          r.gdiag[j] += cwi * static_cast<double>(v) * static_cast<double>(v);
+          if (colsum[j] == 0.0) touched.push_back(j);
+          colsum[j] += v;
         }
         const int64_t ro = r.row_base + q;
         if (lp) P.rscale[static_cast<size_t>(ro)] = scl;
