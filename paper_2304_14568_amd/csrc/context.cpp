@@ -98,6 +98,7 @@ struct admm_ctx {
   double *d_xpart = nullptr, *d_c64 = nullptr, *d_b64 = nullptr;
   double* d_rw64 = nullptr;
   XJob *d_rjobs = nullptr, *d_fjobs = nullptr;
+  int64_t* d_fobj_off = nullptr;
   XTile* d_xtiles = nullptr;
   int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
   int64_t gp_elems = 0;
@@ -272,6 +273,7 @@ struct admm_ctx {
     f.nxtiles = n_xjobs;
     f.rjobs = d_rjobs;
     f.fjobs = d_fjobs;
+    f.fobj_off = d_fobj_off;
     f.fpart = d_fpart;
     f.npmax = ld_max;
     return f;
@@ -782,6 +784,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
 
     // dense x-update: sizes, offsets and work lists (before the tables go to the device)
     std::vector<XJob> rjobs, fjobs;
+    std::vector<int64_t> fobj_off;
     std::vector<XTile> xtiles;
     // dense set-up works on chunks of scenarios: G and the sweep matrix (fp64,
     // npad^2 each) for at most kChunkBytes at a time
@@ -832,7 +835,11 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
         goff += tiles * 4096;
         pt.fobj_begin = static_cast<int32_t>(fjobs.size());
         for (int I = 0; I < pt.nbk; ++I)
-          for (int J = I; J < pt.nbk; ++J) fjobs.push_back(XJob{p, I * 65536 + J});
+          for (int J = I; J < pt.nbk; ++J) {
+            // the upper tiles in row-major order: the job's rank is the tile's index
+            fobj_off.push_back(pt.gpack_off + static_cast<int64_t>(fjobs.size() - pt.fobj_begin) * 4096);
+            fjobs.push_back(XJob{p, I * 65536 + J});
+          }
         pt.fobj_end = static_cast<int32_t>(fjobs.size());
         for (int s = 0; s < pt.num_scen; ++s) {
           const int g = pt.scen_begin + s;
@@ -873,6 +880,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       c->d_xtiles = c->upload(xtiles);
       c->d_rjobs = c->upload(rjobs);
       c->d_fjobs = c->upload(fjobs);
+      c->d_fobj_off = c->upload(fobj_off);
       std::vector<double> g0all(static_cast<size_t>(H.zvec_total));
       for (int p = 0; p < num_patients; ++p)
         std::copy(H.g0[p].begin(), H.g0[p].end(), g0all.begin() + H.pat[p].zvec_base);

@@ -630,40 +630,36 @@ __device__ __forceinline__ void fhead_block(const VecArgs& a, int bi, int lane) 
 }
 
 // objective partial of one packed tile T of sum_s G_s: z_I^T T z_J, doubled off
-// the diagonal; a diagonal tile also carries -g0_I^T z_I.  fp64.
+// the diagonal; a diagonal tile also carries -g0_I^T z_I.  fp64.  The tile's
+// 32 KB are requested first, from its offset alone (each wave instruction
+// reads 1 KiB contiguous); thread t then holds rows 8 k + t / 32 (k = 0..7),
+// columns 2 (t % 32) and 2 (t % 32) + 1, and the quadratic form is summed
+// element by element.
 __device__ __forceinline__ void fobj_tile(const FactorArgs& f, const float* __restrict__ z, int jb) {
   __shared__ double zI[kFb], zJ[kFb], red[4];
-  const XJob job = f.fjobs[jb];
-  const Pat pt = f.pat[job.g];
-  if (f.ps[job.g].stopped) return;
-  const int I = job.ij >> 16, J = job.ij & 0xffff;
-  const double2* T =
-      reinterpret_cast<const double2*>(f.Gp + pt.gpack_off + tile_index(I, J, pt.nbk) * kFb * kFb);
   const int tid = threadIdx.x;
+  const double2* T = reinterpret_cast<const double2*>(f.Gp + f.fobj_off[jb]);
   double2 g[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) g[k] = T[tid * 8 + k];
+  for (int k = 0; k < 8; ++k) g[k] = T[k * 256 + tid];
+  const XJob job = f.fjobs[jb];
+  if (f.ps[job.g].stopped) return;
+  const Pat pt = f.pat[job.g];
+  const int I = job.ij >> 16, J = job.ij & 0xffff;
   if (tid < kFb) {
     const int jc = J * kFb + tid, ic = I * kFb + tid;
     zJ[tid] = jc < pt.n ? static_cast<double>(z[pt.zvec_base + jc]) : 0.0;
     zI[tid] = ic < pt.n ? static_cast<double>(z[pt.zvec_base + ic]) : 0.0;
   }
   __syncthreads();
-  const int i = tid >> 2, q = tid & 3;
+  const int c = 2 * (tid & 31), r0 = tid >> 5;
   double a = 0.0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int j0 = 16 * q + 2 * k;
-    a = fma(g[k].x, zJ[j0], a);
-    a = fma(g[k].y, zJ[j0 + 1], a);
-  }
-  a += __shfl_xor(a, 1, 64);
-  a += __shfl_xor(a, 2, 64);
-  double v = 0.0;
-  if (q == 0) {
-    v = (I == J ? 1.0 : 2.0) * zI[i] * a;
-    const int row = I * kFb + i;
-    if (I == J && row < pt.n) v -= f.g0[pt.zvec_base + row] * zI[i];
+  for (int k = 0; k < 8; ++k) a = fma(zI[8 * k + r0], fma(g[k].x, zJ[c], g[k].y * zJ[c + 1]), a);
+  double v = (I == J ? 1.0 : 2.0) * a;
+  if (I == J && tid < kFb) {
+    const int row = I * kFb + tid;
+    if (row < pt.n) v -= f.g0[pt.zvec_base + row] * zI[tid];
   }
   v = wave_sum_d(v);
   if ((tid & 63) == 0) red[tid >> 6] = v;

@@ -215,6 +215,7 @@ struct FactorArgs {
   int32_t nxtiles;
   const XJob* rjobs;  // x-update reduction: one per block row of every scenario
   const XJob* fjobs;  // objective: one per packed tile of every patient
+  const int64_t* fobj_off;  // objective: offset in Gp of each of those tiles
   double* fpart;      // objective partial per objective job
   int32_t npmax;      // largest npad
   int32_t pad;
