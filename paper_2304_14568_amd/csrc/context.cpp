@@ -97,7 +97,8 @@ struct admm_ctx {
   float* d_Mp = nullptr;
   double *d_xpart = nullptr, *d_c64 = nullptr, *d_b64 = nullptr;
   double* d_rw64 = nullptr;
-  XJob *d_rjobs = nullptr, *d_fjobs = nullptr;
+  RJob* d_rjobs = nullptr;
+  XJob* d_fjobs = nullptr;
   int64_t* d_fobj_off = nullptr;
   XTile* d_xtiles = nullptr;
   int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
@@ -783,7 +784,8 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->trace_cap = std::max(1, o.max_iter + 2);
 
     // dense x-update: sizes, offsets and work lists (before the tables go to the device)
-    std::vector<XJob> rjobs, fjobs;
+    std::vector<RJob> rjobs;
+    std::vector<XJob> fjobs;
     std::vector<int64_t> fobj_off;
     std::vector<XTile> xtiles;
     // dense set-up works on chunks of scenarios: G and the sweep matrix (fp64,
@@ -859,7 +861,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
               xt.J = J;
               xtiles.push_back(xt);
             }
-          for (int I = 0; I < pt.nbk; ++I) rjobs.push_back(XJob{g, I});
+          for (int I = 0; I < pt.nbk; ++I) rjobs.push_back(RJob{(sc.mpack_off / 4096) * 128, sc.vec_base, I, pt.nbk, pt.n, p});
         }
       }
       c->n_xjobs = static_cast<int>(xtiles.size());

@@ -569,13 +569,11 @@ __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __rest
 // sums are then added in a fixed order.
 __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
   __shared__ double part[4][kFb];
-  const XJob job = f.rjobs[blockIdx.x];
-  const Scen sc = f.scen[job.g];
-  if (f.ps[sc.patient].stopped) return;
-  const Pat pt = f.pat[sc.patient];
-  const int I = job.ij, nb = pt.nbk;
+  const RJob job = f.rjobs[blockIdx.x];
+  const int I = job.I, nb = job.nb;
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
-  const double* base = f.xpart + (sc.mpack_off / (kFb * kFb)) * (2 * kFb);
+  const double* base = f.xpart + job.part;
+  const int stopped = f.ps[job.patient].stopped;  // read beside the partials; gates the write only
   // four independent accumulators keep four loads in flight per lane
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   auto ld = [&](int J) {
@@ -591,9 +589,9 @@ __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __rest
   for (; J < nb; J += 4) s0 += ld(J);
   part[w][i] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (w == 0) {
+  if (w == 0 && !stopped) {
     const int row = I * kFb + i;
-    if (row < sc.n) x[sc.vec_base + row] = static_cast<float>((part[0][i] + part[1][i]) + (part[2][i] + part[3][i]));
+    if (row < job.n) x[job.vbase + row] = static_cast<float>((part[0][i] + part[1][i]) + (part[2][i] + part[3][i]));
   }
 }
 

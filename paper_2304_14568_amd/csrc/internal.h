@@ -192,7 +192,15 @@ struct XTile {
 
 struct XJob {
   int32_t g;    // scenario (x-update) or patient (objective)
-  int32_t ij;   // tile (I, J) as I * 65536 + J, or the block row I (reduction)
+  int32_t ij;   // tile (I, J) as I * 65536 + J
+};
+
+// x-update reduction: block row I of one scenario's x_s, with every address
+// it needs, so that its loads depend on this entry only
+struct RJob {
+  int64_t part;   // offset in xpart of the scenario's first tile partials
+  int64_t vbase;  // the scenario's offset in the stacked n-vectors
+  int32_t I, nb, n, patient;
 };
 
 // Symmetric matrices of the dense x-update are stored as their upper 64 x 64
@@ -213,7 +221,7 @@ struct FactorArgs {
   double* xpart;      // per packed tile of every scenario: T c_J (64) and T^T c_I (64), fp64
   const XTile* xtiles; // x-update: one per packed tile of every scenario
   int32_t nxtiles;
-  const XJob* rjobs;  // x-update reduction: one per block row of every scenario
+  const RJob* rjobs;  // x-update reduction: one per block row of every scenario
   const XJob* fjobs;  // objective: one per packed tile of every patient
   const int64_t* fobj_off;  // objective: offset in Gp of each of those tiles
   double* fpart;      // objective partial per objective job
