@@ -51,6 +51,7 @@ struct Pat {
   int32_t fobj_begin, fobj_end; // dense x-update: objective workgroups (one per packed tile) of this patient
   int32_t nbk;                  // dense x-update: npad / 64
   int64_t gpack_off;            // dense x-update: offset of sum_s G_s, packed upper tiles, fp64
+  int64_t vec_base;             // its first scenario's offset in the stacked n-vectors (the others follow, n apart)
 };
 
 // A contiguous range of length-sorted rows of one scenario, handled by one

@@ -777,7 +777,7 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   const int p = bk.owner;
   const Pat pt = a.pat[p];
   const PatState* ps = a.ps + p;
-  if (ps->stopped) return;
+  const int stopped = ps->stopped;  // read beside the loads below; checked before any write
   const double rho = ps->rho;
   const int tid = threadIdx.x;
   const int col = tid % kZCols, grp = tid / kZCols;
@@ -787,10 +787,11 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   double acc = 0.0;
   if (valid)
     for (int s = grp; s < pt.num_scen; s += kGroups) {
-      const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
+      const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
       acc += static_cast<double>(a.x[vi]);
       if (a.prm.z_mode == 0) acc += static_cast<double>(a.y[vi]) / rho;
     }
+  if (stopped) return;  // the whole workgroup: one patient
   sacc[grp][col] = acc;
   __syncthreads();
   double v[6] = {0, 0, 0, 0, 0, 0};  // ||dz||^2, ||z||^2, ||d||^2, <dd,d_prev>, ||dd||^2, ||x||^2
@@ -814,7 +815,7 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   if (valid) {
     const double znd = static_cast<double>(zsh[col]);
     for (int s = grp; s < pt.num_scen; s += kGroups) {
-      const int64_t vi = a.scen[pt.scen_begin + s].vec_base + j;
+      const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
       const double xv = static_cast<double>(a.x[vi]);
       const double d = xv - znd;
       const double dp = a.dprev[vi];

@@ -319,6 +319,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       pt.num_scen = N;
       pt.scen_begin = static_cast<int32_t>(P.scen.size());
       pt.zvec_base = P.zvec_total;
+      pt.vec_base = P.vec_total;
       pt.tile_begin = static_cast<int32_t>(P.tiles.size());
       pt.blk_begin = blk_p;
       pt.nblk = (n + kColBlock - 1) / kColBlock;
