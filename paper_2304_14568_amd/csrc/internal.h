@@ -52,6 +52,7 @@ struct Pat {
   int32_t nbk;                  // dense x-update: npad / 64
   int64_t gpack_off;            // dense x-update: offset of sum_s G_s, packed upper tiles, fp64
   int64_t vec_base;             // its first scenario's offset in the stacked n-vectors (the others follow, n apart)
+  int32_t sblk_begin, sblk_end; // column blocks of all its scenarios (contiguous)
 };
 
 // A contiguous range of length-sorted rows of one scenario, handled by one

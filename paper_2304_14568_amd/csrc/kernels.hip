@@ -100,6 +100,36 @@ __device__ __forceinline__ double block_list_sum(int count, F item, double* sh) 
   return v[0];
 }
 
+// Two strided lists at once, so that their loads overlap; each is added in
+// the order block_list_sum uses, and block_sum reduces the two independently,
+// so either result equals its own block_list_sum.  Valid in thread 0.
+template <class F1, class F2>
+__device__ __forceinline__ void block_list_sum2(int n1, F1 item1, int n2, F2 item2, double* sh, double& s1,
+                                                double& s2) {
+  double v[2] = {0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 3 * kThreads < n1; i += 4 * kThreads) {
+    const double e0 = item1(i), e1 = item1(i + kThreads), e2 = item1(i + 2 * kThreads), e3 = item1(i + 3 * kThreads);
+    v[0] += e0;
+    v[0] += e1;
+    v[0] += e2;
+    v[0] += e3;
+  }
+  for (; i < n1; i += kThreads) v[0] += item1(i);
+  i = threadIdx.x;
+  for (; i + 3 * kThreads < n2; i += 4 * kThreads) {
+    const double e0 = item2(i), e1 = item2(i + kThreads), e2 = item2(i + 2 * kThreads), e3 = item2(i + 3 * kThreads);
+    v[1] += e0;
+    v[1] += e1;
+    v[1] += e2;
+    v[1] += e3;
+  }
+  for (; i < n2; i += kThreads) v[1] += item2(i);
+  block_sum<2>(v, sh);
+  s1 = v[0];
+  s2 = v[1];
+}
+
 // ---------------------------------------------------------------------------
 // the fused pass
 // ---------------------------------------------------------------------------
@@ -609,22 +639,24 @@ void launch_reduce(int mode, const VecArgs& a, int blk_begin, int nblk, hipStrea
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void k_head_scalars(VecArgs a, int nscen, int cg_setup) {
-  __shared__ double sh[4];
+  __shared__ double sh[4 * 2];
   const AlgoParams& P = a.prm;
   for (int p = 0; p < P.num_pat; ++p) {
     const Pat pt = a.pat[p];
     PatState* ps = a.ps + p;
-    if (ps->stopped) continue;  // uniform
-    const double f =
-        a.fpart != nullptr
-            ? pt.fconst + block_list_sum(pt.fobj_end - pt.fobj_begin,
-                                         [&](int i) { return a.fpart[pt.fobj_begin + i]; }, sh)
-            : pt.fzero + block_list_sum(pt.tile_end - pt.tile_begin,
-                                        [&](int i) { return a.objpart[pt.tile_begin + i]; }, sh);
-    const int sb0 = a.scen[pt.scen_begin].blk_begin;
-    const Scen last = a.scen[pt.scen_begin + pt.num_scen - 1];
-    const int sb1 = last.blk_begin + last.nblk;
-    const double yy = block_list_sum(sb1 - sb0, [&](int i) { return a.bpart[(int64_t)(sb0 + i) * 8 + 2]; }, sh);
+    const int stopped = ps->stopped;  // read beside the partial sums
+    // objective partials and the blocks' sums of squares of y, loaded together
+    const int sb0 = pt.sblk_begin;
+    auto yitem = [&](int i) { return a.bpart[(int64_t)(sb0 + i) * 8 + 2]; };
+    double fs = 0.0, yy = 0.0;
+    if (a.fpart != nullptr)
+      block_list_sum2(pt.fobj_end - pt.fobj_begin, [&](int i) { return a.fpart[pt.fobj_begin + i]; },
+                      pt.sblk_end - sb0, yitem, sh, fs, yy);
+    else
+      block_list_sum2(pt.tile_end - pt.tile_begin, [&](int i) { return a.objpart[pt.tile_begin + i]; },
+                      pt.sblk_end - sb0, yitem, sh, fs, yy);
+    if (stopped) continue;  // uniform
+    const double f = (a.fpart != nullptr ? pt.fconst : pt.fzero) + fs;
     if (threadIdx.x == 0) {
       ps->f_cur = f;
       if (ps->pending) {
@@ -849,10 +881,11 @@ __global__ __launch_bounds__(kThreads) void k_body_scalars(VecArgs a) {
   for (int p = 0; p < P.num_pat; ++p) {
     const Pat pt = a.pat[p];
     PatState* ps = a.ps + p;
-    if (ps->stopped) continue;
+    const int stopped = ps->stopped;  // read beside the partial sums
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < 4 * pt.nblk; b += kThreads)
       for (int k = 0; k < 6; ++k) v[k] += a.bpartp[(int64_t)(4 * pt.blk_begin + b) * 8 + k];
+    if (stopped) continue;  // uniform
     block_sum<6>(v, sh);
     int cg = 0;
     if (threadIdx.x == 0) {

@@ -328,6 +328,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       std::vector<double> g0(n, 0.0);
       double gsum = 0.0;
       const int k0 = k;
+      pt.sblk_begin = blk_s;
       for (int s = 0; s < N; ++s, ++k) {
         ScenOut& r = so[k];
         const admm_csr& A = pr.A[s];
@@ -365,6 +366,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         }
         P.vec_total += n;
       }
+      pt.sblk_end = blk_s;
       const double mean_diag = gsum / (static_cast<double>(N) * n);
       P.gdiag_mean[p] = mean_diag;
       const double rho = o.rho > 0 ? o.rho : 2.0 * mean_diag;
