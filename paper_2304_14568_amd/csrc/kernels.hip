@@ -885,19 +885,26 @@ __global__ __launch_bounds__(kThreads) void k_body_scalars(VecArgs a) {
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < 4 * pt.nblk; b += kThreads)
       for (int k = 0; k < 6; ++k) v[k] += a.bpartp[(int64_t)(4 * pt.blk_begin + b) * 8 + k];
-    if (stopped) continue;  // uniform
-    block_sum<6>(v, sh);
-    int cg = 0;
+    // thread 0's inputs from the patient's state, requested before the reduction
+    int cg = 0, iter0 = 0, cgt0 = 0;
+    double rho = 0.0, tau0 = 0.0;
     if (threadIdx.x == 0) {
       for (int s = 0; s < pt.num_scen; ++s) cg += a.cgcount[pt.scen_begin + s];
+      rho = ps->rho;
+      tau0 = ps->tau;
+      iter0 = ps->iter;
+      cgt0 = ps->cg_total;
+    }
+    if (stopped) continue;  // uniform
+    block_sum<6>(v, sh);
+    if (threadIdx.x == 0) {
       const int N = pt.num_scen;
-      const double rho = ps->rho;
       const double rp = sqrt(v[2]);
       const double rd = sqrt(static_cast<double>(N)) * rho * sqrt(v[0]);
       double tau = rho;
-      if (P.bb && ps->iter >= 1 && v[4] > 0.0) {
+      if (P.bb && iter0 >= 1 && v[4] > 0.0) {
         // dy = y^k - y^{k-1} = tau_{k-1} d^k, so <dd, dy> = tau_{k-1} <dd, d^k>
-        const double beta = -ps->tau * v[3] / v[4];
+        const double beta = -tau0 * v[3] / v[4];
         if (isfinite(beta) && beta > 0.0) tau = beta;
       }
       if (P.bb_clamp > 0.0) tau = fmin(fmax(tau, rho / P.bb_clamp), rho * P.bb_clamp);
@@ -909,8 +916,8 @@ __global__ __launch_bounds__(kThreads) void k_body_scalars(VecArgs a) {
       ps->r_dual = rd;
       ps->tau = tau;
       ps->cg_steps = cg;
-      ps->cg_total += cg;
-      ps->iter += 1;
+      ps->cg_total = cgt0 + cg;
+      ps->iter = iter0 + 1;
       ps->pending = 1;
     }
     __syncthreads();
