@@ -108,10 +108,15 @@ def test_full_size_cg_forms_match_the_oracle_minimum(full, precision):
 
 
 def test_full_size_dense_pgd_matches_the_oracle_minimum(full):
+    """A fixed budget of 3 000 iterations (PGD's objective never increases):
+    where a relative-change stop fires on this ill-conditioned problem depends
+    on rounding-level differences in the Gram sums, whose accumulation order
+    varies between runs."""
     import paper_2304_14568_amd as A
     P, W, fs, xs = full
     with A.Solver(P) as S:
-        x, info, st = S.pgd(0, obj_rel_tol=1e-11, max_iter=40000)
+        x, info, st = S.pgd(0, obj_rel_tol=0.0, max_iter=3000)
+    assert st == A.MAX_ITER and info["iter"] == 3000
     f = wls.objective(W, x)
     print(f"[full] dense pgd: {info['iter']} it, status {st}, gap {(f - fs) / fs:.2e}", flush=True)
     assert f >= fs * (1 - 1e-9)
