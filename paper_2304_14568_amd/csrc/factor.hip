@@ -600,22 +600,29 @@ __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __rest
 // one wave: column block bi of one scenario, lane = column within the block
 __device__ __forceinline__ void fhead_block(const VecArgs& a, int bi, int lane) {
   const Blk bk = a.blk[bi];
-  const int g = bk.owner;
-  const Scen sc = a.scen[g];
+  const Scen sc = a.scen[bk.owner];
+  const int j = bk.col0 + lane;
+  const bool in = j < sc.n;
+  const int64_t vi = sc.vec_base + j;
+  // the scenario's vectors are requested beside the patient's entries
+  float yv = 0.0f;
+  double dp = 0.0, bv = 0.0;
+  if (in) {
+    yv = a.y[vi];
+    dp = a.dprev[vi];
+    bv = a.b64[vi];
+  }
   const Pat pt = a.pat[sc.patient];
   const PatState* ps = a.ps + sc.patient;
+  const float zj = in ? a.z[pt.zvec_base + j] : 0.0f;
   if (ps->stopped) return;
-  const int j = bk.col0 + lane;
   double yy = 0.0;
-  if (j < sc.n) {
-    const int64_t vi = sc.vec_base + j;
-    float yv = a.y[vi];
+  if (in) {
     if (ps->pending) {
-      yv = static_cast<float>(static_cast<double>(yv) + ps->tau * a.dprev[vi]);
+      yv = static_cast<float>(static_cast<double>(yv) + ps->tau * dp);
       a.y[vi] = yv;
     }
-    const float zj = a.z[pt.zvec_base + j];
-    a.c64[vi] = a.b64[vi] + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv);
+    a.c64[vi] = bv + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv);
     yy = static_cast<double>(yv) * yv;
   }
   yy = wave_sum_d(yy);
