@@ -291,7 +291,7 @@ struct admm_ctx {
       ~DevBuf() {
         if (p) (void)hipFree(p);
       }
-    } bc, bo, bl;
+    } bc, bo, bl, bsc;
     const int nb = pt.nbk;
     const int64_t ntl = static_cast<int64_t>(nb) * (nb + 1) / 2, nt = ntl * cs;
     bool lists = std::getenv("ADMMBB_GRAM_ATOMIC") == nullptr &&
@@ -310,11 +310,27 @@ struct admm_ctx {
       std::memcpy(&total, h_scr, sizeof(total));
       lists = total >= 0 && hipMalloc(&bl.p, sizeof(GramEntry) * static_cast<size_t>(std::max<int64_t>(total, 1))) ==
                                 hipSuccess;
+      // fixed-point scale of each scenario's tiles: a power of two that keeps
+      // 2 max_j (G_s)_jj, a bound of every partial sum, below 2^62
+      std::vector<double> gs(static_cast<size_t>(cs), 1.0);
+      for (int s = 0; s < cs; ++s) {
+        const Scen& sc = H.scen[g0 + s];
+        double gmax = 0.0;
+        for (int j = 0; j < pt.n; ++j) gmax = std::max(gmax, static_cast<double>(H.gdiag[sc.vec_base + j]));
+        int e = 0;
+        if (gmax > 0.0) {
+          (void)std::frexp(2.0 * gmax, &e);  // 2 gmax = f 2^e, 1/2 <= f < 1
+          gs[static_cast<size_t>(s)] = std::ldexp(1.0, std::min(62 - e, 1000));
+        }
+      }
+      lists = lists && hipMalloc(&bsc.p, sizeof(double) * static_cast<size_t>(cs)) == hipSuccess;
       if (lists) {
+        check(hipMemcpy(bsc.p, gs.data(), sizeof(double) * static_cast<size_t>(cs), hipMemcpyHostToDevice), "H2D");
         GramEntry* list = static_cast<GramEntry*>(bl.p);
         for (int s = 0; s < cs; ++s)
           launch_gram_rows(mat32, H.scen[g0 + s], nb, cur + s * ntl, off + s * ntl, list, stream);
-        launch_gram_tiles(mat32, d_rw64, d_scen, g0, cs, nb, off, list, d_G, pt.npad, stream);
+        launch_gram_tiles(mat32, d_rw64, d_scen, g0, cs, nb, off, list, static_cast<const double*>(bsc.p), d_G,
+                          pt.npad, stream);
       }
     }
     if (!lists) {

@@ -180,6 +180,10 @@ __global__ __launch_bounds__(1024) void k_gram_scan(const int32_t* __restrict__ 
 // One workgroup per tile (I, J) of scenario g0 + blockIdx.y: the rows of its
 // list add c_s w_i a_ij a_ik for j in block I, k in block J (j <= k inside a
 // diagonal tile) to an fp64 LDS tile, which is then written to G (upper part).
+// The tile is accumulated in 64-bit fixed point (gscale[s], a power of two,
+// keeps every partial sum below 2^61: all products are nonnegative, so no
+// partial sum exceeds its entry G_jk <= sqrt(G_jj G_kk) <= max_j G_jj), which
+// makes it exact and independent of the order of the atomics.
 // A row's nonzeros in one block are contiguous (at most 64, plus padding of
 // value 0).  Each wave takes one listed row at a time: its columns and values
 // are read once (with the next list entry already in flight) and staged in the
@@ -193,10 +197,11 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
                                                                 const Scen* __restrict__ scen, int g0, int nb,
                                                                 const int64_t* __restrict__ off,
                                                                 const GramEntry* __restrict__ list,
+                                                                const double* __restrict__ gscale,
                                                                 double* __restrict__ G, int ld) {
   // row stride kFb + 1: the lanes of one atomic instruction mostly share a
   // column and differ in the row, so rows must fall in different banks
-  __shared__ double acc[kFb * (kFb + 1)];
+  __shared__ unsigned long long acc[kFb * (kFb + 1)];
   __shared__ float sval[kGramWaves][kGramStage];
   __shared__ uint8_t scol[kGramWaves][kGramStage];
   const int64_t ntiles = static_cast<int64_t>(nb) * (nb + 1) / 2;
@@ -209,9 +214,10 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
     ++I;
   }
   const int J = I + static_cast<int>(rem);
-  for (int e = threadIdx.x; e < kFb * (kFb + 1); e += 64 * kGramWaves) acc[e] = 0.0;
+  for (int e = threadIdx.x; e < kFb * (kFb + 1); e += 64 * kGramWaves) acc[e] = 0ull;
   __syncthreads();
   const Scen sc = scen[g0 + s];
+  const double scale = gscale[s];
   const float* val = static_cast<const float*>(mat.val);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float* sv = sval[w];
@@ -268,16 +274,17 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_gram_tiles(MatDev mat, cons
         cb = col_at<C16>(mat, e0 + pb) & (kFb - 1);
       }
       const double prod = (rw * va) * vb;
-      if (prod != 0.0) unsafeAtomicAdd(&acc[ca * (kFb + 1) + cb], prod);
+      if (prod != 0.0) atomicAdd(&acc[ca * (kFb + 1) + cb], __double2ull_rn(prod * scale));
     }
     wave_lds_sync();  // the next row overwrites the staging area
     cur = nxt;
   }
   __syncthreads();
   double* Gs = G + static_cast<int64_t>(s) * ld * ld;
+  const double unscale = 1.0 / scale;  // exact: a power of two
   for (int e = threadIdx.x; e < kFb * kFb; e += 64 * kGramWaves) {
     const int r = e / kFb, c = e % kFb;
-    if (I != J || r <= c) Gs[static_cast<int64_t>(I * kFb + r) * ld + J * kFb + c] = acc[r * (kFb + 1) + c];
+    if (I != J || r <= c) Gs[static_cast<int64_t>(I * kFb + r) * ld + J * kFb + c] = static_cast<double>(acc[r * (kFb + 1) + c]) * unscale;
   }
 }
 
@@ -718,13 +725,14 @@ void launch_gram_scan(const int32_t* cnt, int64_t nt, int64_t* off, hipStream_t 
 }
 
 void launch_gram_tiles(const MatDev& m, const double* rw64, const Scen* scen, int g0, int nscen, int nb,
-                       const int64_t* off, const GramEntry* list, double* G, int ld, hipStream_t st) {
+                       const int64_t* off, const GramEntry* list, const double* gscale, double* G, int ld,
+                       hipStream_t st) {
   const unsigned nt = static_cast<unsigned>(static_cast<int64_t>(nb) * (nb + 1) / 2);
   const dim3 grid(nt, static_cast<unsigned>(nscen)), block(64 * kGramWaves);
   if (m.col16)
-    hipLaunchKernelGGL(k_gram_tiles<true>, grid, block, 0, st, m, rw64, scen, g0, nb, off, list, G, ld);
+    hipLaunchKernelGGL(k_gram_tiles<true>, grid, block, 0, st, m, rw64, scen, g0, nb, off, list, gscale, G, ld);
   else
-    hipLaunchKernelGGL(k_gram_tiles<false>, grid, block, 0, st, m, rw64, scen, g0, nb, off, list, G, ld);
+    hipLaunchKernelGGL(k_gram_tiles<false>, grid, block, 0, st, m, rw64, scen, g0, nb, off, list, gscale, G, ld);
 }
 
 void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, int npad, int n, double rho,

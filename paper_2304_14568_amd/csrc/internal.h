@@ -265,7 +265,8 @@ void launch_gram_rows(const MatDev& m, const Scen& sc, int nb, int32_t* cnt, con
                       hipStream_t st);
 void launch_gram_scan(const int32_t* cnt, int64_t nt, int64_t* off, hipStream_t st);
 void launch_gram_tiles(const MatDev& m, const double* rw64, const Scen* scen, int g0, int nscen, int nb,
-                       const int64_t* off, const GramEntry* list, double* G, int ld, hipStream_t st);
+                       const int64_t* off, const GramEntry* list, const double* gscale, double* G, int ld,
+                       hipStream_t st);
 void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, int npad, int n, double rho,
                         int accumulate_gsum, hipStream_t st);
 void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st);

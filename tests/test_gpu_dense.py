@@ -219,3 +219,22 @@ def test_tile_gram_matches_the_normal_equations_and_the_atomic_gram(which, monke
         assert np.linalg.norm(r) <= 1e-4 * np.linalg.norm(b), np.linalg.norm(r) / np.linalg.norm(b)
         # both Gram paths give the same inverse up to its fp32 rounding
         assert np.linalg.norm(x_tile[s] - x_atom[s]) <= 1e-6 * np.linalg.norm(x_atom[s])
+
+
+def test_dense_set_up_and_iterations_are_bitwise_reproducible(monkeypatch):
+    """The Gram tiles are summed in 64-bit fixed point (exact, independent of
+    the order of the atomics) and everything after them in fixed order, so two
+    contexts of the same problem produce identical iterates."""
+    import paper_2304_14568_amd as A
+    monkeypatch.delenv("ADMMBB_GRAM_ATOMIC", raising=False)
+    P = synth.hn_small(6)
+    states = []
+    for _ in range(2):
+        with A.Solver(P, xupdate="dense") as S:
+            S.iterate(5)
+            st = S.get_state()
+            states.append((np.asarray(st["z"]).copy(), np.asarray(st["y"]).copy(), np.asarray(st["d"]).copy(),
+                           S.objective(st["z"])))
+    (z0, y0, d0, f0), (z1, y1, d1, f1) = states
+    assert np.array_equal(z0, z1) and np.array_equal(y0, y1) and np.array_equal(d0, d1)
+    assert f0 == f1
