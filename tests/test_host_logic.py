@@ -62,3 +62,17 @@ def test_stored_references_match_the_generator():
     # more scenarios, larger minimum
     fs = [load(f"hn_full_s0_n{N}")[0]["f_star"] for N in range(1, 13)] + [rec["f_star"]]
     assert all(a < b for a, b in zip(fs, fs[1:]))
+
+
+def test_gram_pair_index_multiply_shift_is_exact():
+    """The tile Gram kernel splits a pair index p of an nI x nJ block of
+    products as a = p / nJ, computed as (p * (2^19 // nJ + 1)) >> 19 in 32-bit
+    arithmetic.  A row's segment in one 64-column block holds at most 64
+    nonzeros plus 3 entries of padding, so nJ <= 67 and p < 67 * 67; the
+    formula must be exact on that whole range and must not overflow."""
+    for nJ in range(1, 68):
+        m = (1 << 19) // nJ + 1
+        p = np.arange(67 * 67, dtype=np.uint64)
+        assert int(p.max()) * m < 2 ** 32
+        a = ((p * np.uint64(m)) & np.uint64(0xFFFFFFFF)) >> np.uint64(19)
+        assert np.array_equal(a, p // np.uint64(nJ))
