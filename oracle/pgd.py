@@ -35,7 +35,8 @@ class PgdResult:
 
 
 def hessian_apply(W: wls.Wls, v: np.ndarray) -> np.ndarray:
-    """H v = 2 sum_s A_s^T diag(c_s w) A_s v."""
+    """H v = 2 sum_s A_s^T diag(c_s w) A_s v.  Pinned by a hand-worked value and
+    by H v = grad f(v) - grad f(0)."""
     out = np.zeros(W.n)
     for s in range(W.N):
         out += 2.0 * W.c[s] * (W.A[s].T @ (W.w * (W.A[s] @ v)))
@@ -43,7 +44,9 @@ def hessian_apply(W: wls.Wls, v: np.ndarray) -> np.ndarray:
 
 
 def lipschitz(W: wls.Wls, iters: int = 30, seed: int = 0) -> float:
-    """Largest eigenvalue of H by power iteration (deterministic start vector of ones)."""
+    """Largest eigenvalue of H by power iteration (deterministic start vector of
+    ones).  Pinned by the closed-form eigenvalue of a hand-worked 2 x 2 Hessian
+    and by LAPACK's eigenvalues of the quadratic form."""
     v = np.ones(W.n) / np.sqrt(W.n)
     lam = 0.0
     for _ in range(iters):

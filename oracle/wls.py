@@ -121,7 +121,8 @@ def kkt_residual(W: Wls, x: np.ndarray, g0_inf: float | None = None) -> float:
 
 
 def mean_gram_diagonal(W: Wls) -> float:
-    """mean_s mean_j (G_s)_jj = mean over scenarios and spots of sum_i c_s w_i a_ij^2."""
+    """mean_s mean_j (G_s)_jj = mean over scenarios and spots of sum_i c_s w_i a_ij^2.
+    Pinned by a hand-worked value and by second differences of f_s."""
     tot = 0.0
     for s in range(W.N):
         As = W.A[s]
@@ -134,7 +135,7 @@ def default_rho(W: Wls, scale: float = 1.0) -> float:
     """Penalty used when the caller gives none (the paper leaves rho to the user,
     Sec. 2.2): rho = 2 * scale * mean diag(G_s), i.e. rho/2 equals the mean
     diagonal of the scenario Gram matrices, which keeps the rule invariant to a
-    rescaling of A or w."""
+    rescaling of A or w.  Pinned by a hand-worked value and second differences."""
     return 2.0 * scale * mean_gram_diagonal(W)
 
 
@@ -156,16 +157,22 @@ def rmatvec(W: Wls, s: int, t: np.ndarray) -> np.ndarray:
 
 
 def rmatvec_abs(W: Wls, s: int, t: np.ndarray) -> np.ndarray:
+    """|A_s|^T |t|, the per-entry scale of A_s^T t.  Pinned by a hand-worked value
+    and by the triangle inequality (equality for t >= 0)."""
     return abs(W.A[s]).T @ np.abs(np.asarray(t, dtype=np.float64))
 
 
 def normal_apply(W: Wls, s: int, v: np.ndarray, rho: float) -> np.ndarray:
-    """B_s v = (A_s^T diag(c_s w) A_s + rho/2 I) v  (Appendix A)."""
+    """B_s v = (A_s^T diag(c_s w) A_s + rho/2 I) v  (Appendix A).  Pinned by a
+    hand-worked value and by the gradient identity
+    B_s v = (grad f_s(v) - grad f_s(0)) / 2 + rho/2 v."""
     v = np.asarray(v, dtype=np.float64)
     return W.A[s].T @ (W.c[s] * W.w * (W.A[s] @ v)) + 0.5 * rho * v
 
 
 def normal_apply_abs(W: Wls, s: int, v: np.ndarray, rho: float) -> np.ndarray:
+    """(|A_s|^T diag(c_s w) |A_s| + rho/2 I) |v|, the per-entry scale of B_s v.
+    Pinned by a hand-worked value and by the triangle inequality."""
     av = np.abs(np.asarray(v, dtype=np.float64))
     aA = abs(W.A[s])
     return aA.T @ (W.c[s] * W.w * (aA @ av)) + 0.5 * rho * av

@@ -142,6 +142,105 @@ def test_spmv_references_match_dense(tinyW):
 
 
 # ----------------------------------------------------------------------------
+# operators of the x-update, PGD step size and penalty default
+# ----------------------------------------------------------------------------
+
+def _operator_case():
+    g = H.golden("admm_steps.json")["operators"]
+    P = H.problem_from_dense(g["A"], g["w"], g["p"], c=g["c"])
+    return g, wls.from_problem(P)
+
+
+def test_operator_hand_values():
+    """B_s v (Appendix A), its |.| scale, |A_s|^T |t|, H v, the Gram diagonal
+    mean and the default penalty against values worked by hand."""
+    g, W = _operator_case()
+    v, t, rho = np.asarray(g["v"]), np.asarray(g["t"]), g["rho"]
+    for s in range(W.N):
+        np.testing.assert_allclose(wls.normal_apply(W, s, v, rho), g["normal"][s], rtol=1e-15)
+        np.testing.assert_allclose(wls.normal_apply_abs(W, s, v, rho), g["normal_abs"][s], rtol=1e-15)
+        np.testing.assert_allclose(wls.rmatvec_abs(W, s, t), g["rmatvec_abs"][s], rtol=1e-15)
+    np.testing.assert_allclose(pgd.hessian_apply(W, v), g["hessian_v"], rtol=1e-15)
+    assert wls.mean_gram_diagonal(W) == pytest.approx(g["mean_gram_diagonal"], rel=1e-15)
+    assert wls.default_rho(W) == pytest.approx(g["default_rho"], rel=1e-15)
+
+
+def test_lipschitz_is_the_closed_form_largest_eigenvalue():
+    """Power iteration on the hand-worked 2 x 2 Hessian [[24, 8], [8, 17]]
+    reaches lambda_max = (41 + sqrt(305)) / 2 (eigenvalue ratio 0.4, 30 steps)."""
+    g, W = _operator_case()
+    assert pgd.lipschitz(W) == pytest.approx((41.0 + math.sqrt(305.0)) / 2.0, rel=1e-10)
+
+
+def test_lipschitz_matches_eigvalsh(tinyW, tinyQ):
+    """The step-size bound of Sec. 2.1's PGD against LAPACK's symmetric
+    eigenvalues of the quadratic form's Hessian (itself pinned by the objective
+    identity); a unit-norm power iterate never overshoots lambda_max."""
+    Hm = tinyQ[0]
+    lam = np.linalg.eigvalsh(Hm)[-1]
+    L = pgd.lipschitz(tinyW)
+    assert L <= lam * (1 + 1e-12)
+    assert L == pytest.approx(lam, rel=1e-6)
+
+
+def test_normal_operator_is_the_subproblem_gradient(tinyW):
+    """grad f_s(v) - grad f_s(0) = 2 A_s^T diag(c_s w) A_s v (Sec. 2.1; the
+    gradient is pinned by central differences), so B_s v equals half of it
+    plus rho/2 v, and H v is the sum of those differences."""
+    rng = np.random.default_rng(5)
+    rho = 0.7
+    v = rng.normal(size=tinyW.n)
+    zero = np.zeros(tinyW.n)
+    hv = np.zeros(tinyW.n)
+    for s in range(tinyW.N):
+        dg = wls.scenario_gradient(tinyW, s, v) - wls.scenario_gradient(tinyW, s, zero)
+        scale = np.abs(dg).max()
+        np.testing.assert_allclose(wls.normal_apply(tinyW, s, v, rho), 0.5 * dg + 0.5 * rho * v,
+                                   rtol=0, atol=1e-12 * scale)
+        hv += dg
+    np.testing.assert_allclose(pgd.hessian_apply(tinyW, v), hv, rtol=0, atol=1e-12 * np.abs(hv).max())
+
+
+def test_absolute_scales_bound_the_products(tinyW):
+    """|B_s v| <= (|A_s|^T c_s W |A_s| + rho/2) |v| and |A_s^T t| <= |A_s|^T |t|
+    entry by entry (triangle inequality), with equality for nonnegative
+    arguments because A_s >= 0 (Sec. 2.1)."""
+    rng = np.random.default_rng(6)
+    rho = 0.3
+    v = rng.normal(size=tinyW.n)
+    t = rng.normal(size=tinyW.m)
+    for s in range(tinyW.N):
+        nb = wls.normal_apply_abs(tinyW, s, v, rho)
+        assert np.all(np.abs(wls.normal_apply(tinyW, s, v, rho)) <= nb * (1 + 1e-13))
+        np.testing.assert_allclose(nb, wls.normal_apply(tinyW, s, np.abs(v), rho), rtol=1e-13)
+        rb = wls.rmatvec_abs(tinyW, s, t)
+        assert np.all(np.abs(wls.rmatvec(tinyW, s, t)) <= rb * (1 + 1e-13))
+        np.testing.assert_allclose(rb, wls.rmatvec(tinyW, s, np.abs(t)), rtol=1e-13)
+        # mixed signs make the scale strictly larger somewhere
+        assert np.any(nb > np.abs(wls.normal_apply(tinyW, s, v, rho)) * (1 + 1e-6))
+
+
+def test_gram_diagonal_from_second_differences(tinyW):
+    """(G_s)_jj is half the second derivative of f_s along spot j (Sec. 2.1):
+    f_s(h e_j) + f_s(-h e_j) - 2 f_s(0) = 2 h^2 (G_s)_jj exactly for a
+    quadratic; the penalty default is twice the mean over s and j."""
+    h = 0.5
+    tot = 0.0
+    f0 = [wls.scenario_objective(tinyW, s, np.zeros(tinyW.n)) for s in range(tinyW.N)]
+    for s in range(tinyW.N):
+        d = np.empty(tinyW.n)
+        for j in range(tinyW.n):
+            e = np.zeros(tinyW.n)
+            e[j] = h
+            d[j] = (wls.scenario_objective(tinyW, s, e) + wls.scenario_objective(tinyW, s, -e) - 2 * f0[s]) / (2 * h * h)
+        tot += d.mean()
+    mean_diag = tot / tinyW.N
+    assert wls.mean_gram_diagonal(tinyW) == pytest.approx(mean_diag, rel=1e-9)
+    assert wls.default_rho(tinyW) == pytest.approx(2.0 * mean_diag, rel=1e-9)
+    assert wls.default_rho(tinyW, scale=0.25) == pytest.approx(0.5 * mean_diag, rel=1e-9)
+
+
+# ----------------------------------------------------------------------------
 # exact minimisers: brute force vs a library solver vs the polish
 # ----------------------------------------------------------------------------
 

@@ -12,7 +12,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import admm, wls
+from oracle import admm, pgd, wls
 from tests import test_oracle as T
 from tests import test_oracle_iterates as TI
 
@@ -131,3 +131,65 @@ def test_dual_sign_flip_moves_the_fixed_point(monkeypatch, tiny_w):
         return self.b[s] + 0.5 * self.rho * (z + y_s / self.rho)
     monkeypatch.setattr(admm.AdmmSetup, "rhs", rhs)
     _must_fail(TI.test_the_optimum_with_its_duals_is_a_fixed_point, tiny_w, 0)
+
+
+# ---- pins of the operators, the PGD step bound and the penalty default ----
+
+def test_normal_apply_without_scenario_probability(monkeypatch):
+    def na(W, s, v, rho):
+        v = np.asarray(v, dtype=np.float64)
+        return W.A[s].T @ (W.w * (W.A[s] @ v)) + 0.5 * rho * v
+    monkeypatch.setattr(wls, "normal_apply", na)
+    _must_fail(T.test_operator_hand_values)
+
+
+def test_normal_apply_with_full_rho_shift(monkeypatch):
+    def na(W, s, v, rho):
+        v = np.asarray(v, dtype=np.float64)
+        return W.A[s].T @ (W.c[s] * W.w * (W.A[s] @ v)) + rho * v
+    monkeypatch.setattr(wls, "normal_apply", na)
+    _must_fail(T.test_operator_hand_values)
+
+
+def test_normal_apply_without_shift_breaks_gradient_identity(monkeypatch):
+    def na(W, s, v, rho):
+        v = np.asarray(v, dtype=np.float64)
+        return W.A[s].T @ (W.c[s] * W.w * (W.A[s] @ v))
+    monkeypatch.setattr(wls, "normal_apply", na)
+    W = wls.from_problem(__import__("synth").make_tiny(0))
+    _must_fail(T.test_normal_operator_is_the_subproblem_gradient, W)
+
+
+def test_normal_scale_without_absolute_values(monkeypatch):
+    monkeypatch.setattr(wls, "normal_apply_abs", lambda W, s, v, rho: wls.normal_apply(W, s, v, rho))
+    _must_fail(T.test_operator_hand_values)
+
+
+def test_transpose_scale_without_absolute_values(monkeypatch):
+    monkeypatch.setattr(wls, "rmatvec_abs", lambda W, s, t: wls.rmatvec(W, s, t))
+    _must_fail(T.test_operator_hand_values)
+
+
+def test_hessian_without_factor_two(monkeypatch):
+    orig = pgd.hessian_apply
+    monkeypatch.setattr(pgd, "hessian_apply", lambda W, v: 0.5 * orig(W, v))
+    _must_fail(T.test_operator_hand_values)
+    _must_fail(T.test_lipschitz_is_the_closed_form_largest_eigenvalue)
+
+
+def test_lipschitz_with_too_few_power_steps(monkeypatch):
+    orig = pgd.lipschitz
+    monkeypatch.setattr(pgd, "lipschitz", lambda W, iters=30, seed=0: orig(W, iters=2))
+    _must_fail(T.test_lipschitz_is_the_closed_form_largest_eigenvalue)
+
+
+def test_default_rho_without_factor_two(monkeypatch):
+    monkeypatch.setattr(wls, "default_rho", lambda W, scale=1.0: scale * wls.mean_gram_diagonal(W))
+    _must_fail(T.test_operator_hand_values)
+
+
+def test_gram_diagonal_without_weights(monkeypatch):
+    def mgd(W):
+        return float(np.mean([np.mean(np.asarray(W.A[s].multiply(W.A[s]).sum(axis=0)).ravel()) for s in range(W.N)]))
+    monkeypatch.setattr(wls, "mean_gram_diagonal", mgd)
+    _must_fail(T.test_operator_hand_values)
