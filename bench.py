@@ -77,37 +77,69 @@ def spmv_bytes(P) -> dict:
     return out
 
 
-def cpu_baseline(P, seconds_budget: float = 25.0) -> dict:
-    """Time the FP64 oracle's ADMM-BB on a bounded sample of the workload: the
-    same patient restricted to 3 of its 13 scenarios (set-up: dense Gram matrix
-    and Cholesky factor per scenario; then ADMM iterations), scaled linearly to
-    13 scenarios (both phases are per-scenario work plus O(n) glue)."""
+def cpu_baseline(P, fstar, budget_s: float = 90.0) -> dict:
+    """Time the FP64 oracle's ADMM-BB (the paper's algorithm: cached Cholesky
+    x-updates, Appendix A) on the whole workload, all 13 scenarios, on this
+    host: the set-up (dense Gram matrix and Cholesky factor per scenario), then
+    iterations from zero until (f - f*)/f* <= 1e-5 against the stored oracle
+    minimum, stopped by the oracle's own per-iteration callback.  The oracle is
+    used as it stands: its scenario loop is serial, so the cores it actually
+    keeps busy are measured (process CPU time over wall time) next to the BLAS
+    thread pool it may use.  A second, short run limited to one BLAS thread
+    gives the single-thread iteration rate."""
     from oracle import admm as oadmm, wls as owls
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        blas_threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
-    sub = P.subset([0, 1, 2])
-    W = owls.from_problem(sub)
-    t0 = time.perf_counter()
+        threadpool_limits = None
+        blas_threads = os.cpu_count() or 1
+
+    class _Done(Exception):
+        pass
+
+    W = owls.from_problem(P)
+    c0, t0 = time.process_time(), time.perf_counter()
     S = oadmm.AdmmSetup(W, owls.default_rho(W))
     t_setup = time.perf_counter() - t0
-    iters = 0
-    t1 = time.perf_counter()
-    rem = max(2.0, seconds_budget - t_setup)
-    while True:
-        oadmm.admm_bb(W, setup=S, max_iter=1, record=False)
-        iters += 1
-        if time.perf_counter() - t1 > rem or iters >= 50:
-            break
-    t_it = (time.perf_counter() - t1) / iters
-    scale = P.num_scen / sub.num_scen
-    return {"value": 1.0 / (t_it * scale), "unit": "ADMM iter/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"FP64 oracle ADMM-BB (cached Cholesky x-update) on 3 of the 13 scenarios, {iters} iterations "
-                      f"timed ({t_it * 1e3:.0f} ms each), scaled x{scale:.2f} to 13 scenarios; set-up "
-                      f"{t_setup:.1f} s for 3 scenarios (~{t_setup * scale:.0f} s for 13)",
-            "setup_s_13_scen_est": t_setup * scale}
+    cpu_setup = time.process_time() - c0
+    stamps = []
+    t_start = time.perf_counter()
+
+    def cb(k, z, f):
+        stamps.append((k + 1, time.perf_counter(), f))
+        if fstar is not None and (f - fstar) / fstar <= 1e-5:
+            raise _Done
+        if time.perf_counter() - t_start > budget_s:
+            raise _Done
+
+    c1 = time.process_time()
+    try:
+        oadmm.admm_bb(W, setup=S, max_iter=5000, record=False, callback=cb)
+    except _Done:
+        pass
+    solve_s = time.perf_counter() - t_start
+    cpu_solve = time.process_time() - c1
+    iters, _, f_last = stamps[-1]
+    reached = fstar is not None and (f_last - fstar) / fstar <= 1e-5
+    # single BLAS thread: a few iterations, rate from the callback stamps
+    one = []
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            oadmm.admm_bb(W, setup=S, max_iter=4, obj_rel_tol=0.0, eps_abs=0.0, eps_rel=0.0, record=False,
+                          callback=lambda k, z, f: one.append(time.perf_counter()))
+    rate1 = (len(one) - 1) / (one[-1] - one[0]) if len(one) > 1 else None
+    busy = (cpu_setup + cpu_solve) / (t_setup + solve_s)
+    return {"value": iters / solve_s, "unit": "ADMM iter/s", "cores": int(math.ceil(busy - 1e-9)), "kind": "oracle",
+            "sample": f"FP64 oracle ADMM-BB (cached Cholesky x-updates) on the whole workload, all "
+                      f"{P.num_scen} scenarios: set-up {t_setup:.1f} s, then {iters} iterations from zero in "
+                      f"{solve_s:.1f} s" + (" to the 1e-5 objective gap" if reached else
+                                             " (time budget; the 1e-5 gap was not reached)"),
+            "setup_s": t_setup, "solve_s": solve_s, "iters": int(iters),
+            "time_to_1e-5_s": (t_setup + solve_s) if reached else None,
+            "time_to_1e-5_solve_only_s": solve_s if reached else None,
+            "reached_1e-5": bool(reached), "blas_threads": int(blas_threads),
+            "cpu_busy_cores": busy, "iter_per_s_1_thread": rate1}
 
 
 def main():
@@ -136,7 +168,7 @@ def main():
     import torch
     import synth
     import paper_2304_14568_amd as A
-    from tests.golden.refs import load as load_ref
+    from paper_2304_14568_amd.refdata import load as load_ref
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -309,7 +341,7 @@ def main():
             result["note"] = "stored oracle reference missing or digest mismatch: no time-to-tolerance"
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(P)
+        result["cpu_baseline"] = cpu_baseline(P, fstar)
     S.close()
     print(json.dumps(result), flush=True)
 

@@ -2,7 +2,7 @@
 
   scaling   total runtime of ADMM-BB (dense and CG x-updates) and PGD (dense
             form; --sparse-pgd adds the sparse form) versus the
-            number of scenarios N = 1..13 of one patient (Sec. 3.2, the
+            number of scenarios N = 1..13 of one patient (Sec. 3.3, the
             scenario-count study), plus the time to reach the 1e-5 relative
             objective gap against the oracle's exact minimum where stored.
   precision bf16 / fp16 values inside CG against fp32 and the oracle minimum
@@ -17,7 +17,7 @@
   python -m paper_2304_14568_amd.experiments batch --patients 8 --scen 64 --out batch.json
 
 Everything runs on the GPU through the library; the oracle is not used here
-(the stored minima it wrote are read from tests/golden when present).
+(the stored minima it wrote are read by `refdata` when present).
 """
 from __future__ import annotations
 
@@ -29,7 +29,7 @@ import time
 
 import numpy as np
 
-from . import Solver
+from . import Solver, refdata
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -40,13 +40,7 @@ def _sync():
 
 
 def _stored_fstar(name: str, digest: str):
-    sys.path.insert(0, ROOT)
-    try:
-        from tests.golden.refs import load
-    except Exception:  # pragma: no cover
-        return None
-    rec, _ = load(name)
-    return rec["f_star"] if (rec is not None and rec["digest"] == digest) else None
+    return refdata.fstar(name, digest)
 
 
 def _admm_run(P, f_ref, xupdate: str, stream):
@@ -240,11 +234,9 @@ def cmd_precision(args):
     import torch
     import synth
     from .clinical import evaluate
-    sys.path.insert(0, ROOT)
-    from tests.golden.refs import load
     stream = torch.cuda.Stream()
     P = synth.hn_full(args.seed)
-    rec, xstar = load(f"hn_full_s{args.seed}")
+    rec, xstar = refdata.load(f"hn_full_s{args.seed}")
     if rec is None or rec["digest"] != P.digest():
         raise SystemExit("stored oracle reference missing or stale")
     fstar = rec["f_star"]

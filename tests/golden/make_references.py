@@ -27,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 WORKLOADS = {
     "hn_full_s0": lambda: synth.hn_full(0),
 }
-# the same patient with its first N scenarios (scenario-count scaling, Sec. 3.2)
+# the same patient with its first N scenarios (scenario-count scaling, Sec. 3.3)
 for _n in range(1, 13):
     WORKLOADS[f"hn_full_s0_n{_n}"] = (lambda n: (lambda: synth.hn_full(0).subset(list(range(n)))))(_n)
 
