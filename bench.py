@@ -142,6 +142,39 @@ def cpu_baseline(P, fstar, budget_s: float = 90.0) -> dict:
             "cpu_busy_cores": busy, "iter_per_s_1_thread": rate1}
 
 
+def cpu_scaling(args):
+    """The oracle's side of the scenario-count study (Sec. 3.3): cpu_baseline on
+    the workload restricted to its first N scenarios, against the stored oracle
+    minimum of each restriction, and on the two smallest patients of the batch
+    recipe with their 64-scenario lattice."""
+    import synth
+    from paper_2304_14568_amd.refdata import load as load_ref
+    P_all = synth.hn_full(args.seed)
+    rows = []
+    for N in [int(v) for v in args.cpu_scaling.split(",")]:
+        P = P_all.subset(list(range(N)))
+        name = f"hn_full_s{args.seed}" if N == P_all.num_scen else f"hn_full_s{args.seed}_n{N}"
+        rec, _ = load_ref(name)
+        fstar = rec["f_star"] if (rec is not None and rec["digest"] == P.digest()) else None
+        r = cpu_baseline(P, fstar, budget_s=300.0)
+        r.update(N=N, workload=name)
+        rows.append(r)
+        print(f"[cpu-scaling] N={N}: set-up {r['setup_s']:.1f}s, {r['iters']} it in {r['solve_s']:.1f}s",
+              file=sys.stderr, flush=True)
+    for k in (2, 1):
+        P = synth.batch_patient(k, num=8, scen=64, seed=10)
+        rec, _ = load_ref(f"batch_s10_p{k}")
+        if rec is None or rec["digest"] != P.digest():
+            continue
+        r = cpu_baseline(P, rec["f_star"], budget_s=600.0)
+        r.update(N=P.num_scen, workload=f"batch_s10_p{k}", m=P.m, n=P.n)
+        rows.append(r)
+        print(f"[cpu-scaling] batch patient {k} (N={P.num_scen}): set-up {r['setup_s']:.1f}s, {r['iters']} it in "
+              f"{r['solve_s']:.1f}s", file=sys.stderr, flush=True)
+        break
+    print(json.dumps({"kind": "oracle scenario-count scaling", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,7 +192,13 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="replay each iteration from a captured HIP graph in the throughput region "
                          "(the instrumented region always launches directly)")
+    ap.add_argument("--cpu-scaling", default="",
+                    help="only time the FP64 oracle (set-up and iterations to the 1e-5 gap) on the first N "
+                         "scenarios of the workload for each N of this comma-separated list, and on the "
+                         "64-scenario lattice patients with stored minima; print one JSON line")
     args = ap.parse_args()
+    if args.cpu_scaling:
+        return cpu_scaling(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU scenario sharding is a design "
                                    "note only (one all-reduce of an n-vector per iteration)", "n_gpus": args.gpus}))

@@ -15,9 +15,13 @@
  * Method (Sec. 2.2 and Appendix A): consensus ADMM over scenarios with a
  * Barzilai-Borwein dual step.  Each iteration solves, for every scenario, the
  * regularised WLS subproblem through its normal equations
- *     (A_s^T diag(c_s w) A_s + rho/2 I) x_s = A_s^T diag(c_s w) p + rho/2 (z - y_s/rho),
- * here by warm-started conjugate gradients on the GPU (the paper factors the
- * matrix once by Cholesky); then z = P(mean_s(x_s + y_s/rho)), the BB step
+ *     (A_s^T diag(c_s w) A_s + rho/2 I) x_s = A_s^T diag(c_s w) p + rho/2 (z - y_s/rho).
+ * The paper factors each matrix once by Cholesky (Appendix A).  Here the
+ * default x-update (ADMM_XUPDATE_DENSE, chosen whenever the matrices fit)
+ * caches the inverse of every such matrix in fp32 and applies it with one
+ * GEMV per iteration, an exact solve like the paper's; the alternative
+ * (ADMM_XUPDATE_CG) runs warm-started conjugate gradients whose every step is
+ * one fused pass over the sparse A_s.  Then z = P(mean_s(x_s + y_s/rho)), the BB step
  * beta = -<dd, dy>/||dd||^2 replacing rho in y_s += tau (x_s - z) when
  * positive, and the residual stopping test of Sec. 2.2 combined with a
  * relative-objective-change test (Sec. 2.3).  pgd_solve is the comparison
@@ -103,7 +107,8 @@ typedef struct {
   double bb_clamp;     /* 0: none (default); c > 0: tau clamped to [rho/c, rho*c] */
   int32_t cg_max;      /* CG steps per ADMM iteration, 1..64; default 8 */
   double cg_eta;       /* CG stops at ||r|| <= eta ||c_s||, eta = max(eta_floor, cg_eta*min(1, r_prim/||x||)); default 0.01 */
-  double cg_eta_floor; /* default 1e-6 */
+  double cg_eta_floor; /* default 1e-8 (a floor of 1e-6 holds the intensities of the fp32 CG solve
+                          about 4e-4 from the minimiser on the 13-scenario head-and-neck workload) */
   int32_t precision;   /* ADMM_PREC_*: value type of A_s inside CG; the objective and the
                           per-iteration residual always use the fp32 matrix; default FP32 */
   int32_t precond;     /* 1: Jacobi-preconditioned CG; default 0 */
@@ -140,6 +145,10 @@ typedef struct {
   double obj;        /* f(z) (fp32 matrix, fp64 accumulation) */
   double r_prim, r_dual, eps_prim, eps_dual;
   double tau;        /* dual step used */
+  double kkt;        /* scaled KKT residual of the returned point, as admm_kkt computes it:
+                        filled by admm_solve (at the point where the stopping test ended the run)
+                        and pgd_solve (when x_out is given); -1 where it is not evaluated
+                        (admm_iterate, trace records) */
 } admm_info;
 
 /* PGD options (Sec. 2.1). alpha <= 0 selects 10 / lambda_max(H) (30 power iterations). */

@@ -67,7 +67,7 @@ class InfoC(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("cg_steps", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("obj", ctypes.c_double), ("r_prim", ctypes.c_double),
                 ("r_dual", ctypes.c_double), ("eps_prim", ctypes.c_double), ("eps_dual", ctypes.c_double),
-                ("tau", ctypes.c_double)]
+                ("tau", ctypes.c_double), ("kkt", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}

@@ -418,11 +418,16 @@ struct admm_ctx {
     launch_body_scalars(va, stream);
   }
 
+  // One iteration recorded into a graph.  No event is ever recorded inside a
+  // capture: timed runs launch directly (one_iteration), and the body is
+  // captured without its timing events, so a replayed graph holds kernel nodes
+  // only and nothing the host reads back between replays.
   void capture(int stop_enabled, hipGraph_t* gr, hipGraphExec_t* ge) {
+    if (timing) throw HipError{hipErrorInvalidValue, "graph capture refused while timing events are enabled"};
     check(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
       launch_head(stop_enabled, 1);
-      launch_body(stop_enabled, timing);
+      launch_body(stop_enabled, false);
     } catch (...) {
       hipGraph_t tmp = nullptr;
       (void)hipStreamEndCapture(stream, &tmp);
@@ -512,6 +517,7 @@ struct admm_ctx {
       o.eps_prim = s.eps_prim;
       o.eps_dual = s.eps_dual;
       o.tau = s.tau;
+      o.kkt = -1.0;
     }
   }
 
@@ -680,7 +686,7 @@ admm_status admm_default_options(admm_options* o) {
   o->bb_clamp = 0.0;
   o->cg_max = 8;
   o->cg_eta = 0.01;
-  o->cg_eta_floor = 1e-6;
+  o->cg_eta_floor = 1e-8;
   o->precision = ADMM_PREC_FP32;
   o->precond = 0;
   o->use_graph = 1;
@@ -1183,15 +1189,28 @@ admm_status admm_solve(admm_ctx* ctx, double* z_out, admm_info* info) {
   const int k = std::max(0, ctx->opts.max_iter - done);
   ctx->run(k, 1);
   ctx->fill_info(info);
-  if (z_out) {
-    std::vector<float> z(static_cast<size_t>(ctx->H.zvec_total));
+  std::vector<float> z(static_cast<size_t>(ctx->H.zvec_total));
+  if (z_out || info) {
+    check(hipStreamSynchronize(ctx->stream), "sync");
     check(hipMemcpy(z.data(), ctx->d_z, sizeof(float) * z.size(), hipMemcpyDeviceToHost), "D2H");
-    for (size_t i = 0; i < z.size(); ++i) z_out[i] = z[i];
   }
+  if (z_out)
+    for (size_t i = 0; i < z.size(); ++i) z_out[i] = z[i];
   admm_status worst = ADMM_OK;
   for (int p = 0; p < ctx->P; ++p) {
     if (ctx->h_ps[p].status == 2) return set_err(ctx, ADMM_E_DIVERGED, "iterates became non-finite");
     if (ctx->h_ps[p].status != 1) worst = ADMM_MAX_ITER;
+  }
+  if (info) {
+    // KKT residual of every returned z (one gradient pass per patient)
+    for (int p = 0; p < ctx->P; ++p) {
+      const Pat& pt = ctx->H.pat[p];
+      std::vector<double> zp(z.begin() + pt.zvec_base, z.begin() + pt.zvec_base + pt.n);
+      double r = -1.0;
+      const admm_status ks = admm_kkt(ctx, p, zp.data(), &r);
+      if (ks != ADMM_OK) return ks;
+      info[p].kkt = r;
+    }
   }
   return worst;
   GUARD_END(ctx)
@@ -1549,8 +1568,9 @@ admm_status pgd_dense(admm_ctx* ctx, const pgd_options& o, int32_t patient, cons
 
 }  // namespace
 
-admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, const double* x0, double* x_out,
-                      admm_info* info) {
+namespace {
+admm_status pgd_solve_impl(admm_ctx* ctx, const pgd_options* popts, int32_t patient, const double* x0,
+                           double* x_out, admm_info* info) {
   admm_status st = check_patient(ctx, patient);
   if (st != ADMM_OK) return st;
   pgd_options o;
@@ -1663,6 +1683,21 @@ admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, 
   (void)failed;
   return converged ? ADMM_OK : ADMM_MAX_ITER;
   GUARD_END(ctx)
+}
+}  // namespace
+
+admm_status pgd_solve(admm_ctx* ctx, const pgd_options* popts, int32_t patient, const double* x0, double* x_out,
+                      admm_info* info) {
+  const admm_status st = pgd_solve_impl(ctx, popts, patient, x0, x_out, info);
+  if (st < 0 || !info) return st;
+  info->kkt = -1.0;
+  if (x_out) {
+    double r = -1.0;
+    const admm_status ks = admm_kkt(ctx, patient, x_out, &r);
+    if (ks != ADMM_OK) return ks;
+    info->kkt = r;
+  }
+  return st;
 }
 
 admm_status admm_get_state(admm_ctx* ctx, int32_t patient, double* z, double* y, double* d, double* scalars) {

@@ -54,9 +54,9 @@ extern "C" admm_status admm_stream_probe(int64_t bytes, int32_t reps, double* gb
     const unsigned grid = static_cast<unsigned>((n4 + 1023) / 1024);
     hipLaunchKernelGGL(k_fill4, dim3(static_cast<unsigned>((n4 + 255) / 256)), dim3(256), 0, st, a, n4);
     hipLaunchKernelGGL(k_stream, dim3(grid), dim3(256), 0, st, a, sink, n4);  // warm-up
-    hipEventRecord(e0, st);
+    (void)hipEventRecord(e0, st);
     for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_stream, dim3(grid), dim3(256), 0, st, a, sink, n4);
-    hipEventRecord(e1, st);
+    (void)hipEventRecord(e1, st);
     float ms = 0.0f;
     if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
         hipGetLastError() != hipSuccess || !(ms > 0.0f))

@@ -126,11 +126,18 @@ def cmd_scaling(args):
     stream = torch.cuda.Stream()
     P_all = synth.hn_full(args.seed)
     rows = []
-    for N in [int(v) for v in args.n.split(",")]:
-        P = P_all.subset(list(range(N)))
+    cases = []
+    for N in [int(v) for v in args.n.split(",") if v]:
         name = f"hn_full_s{args.seed}" if N == P_all.num_scen else f"hn_full_s{args.seed}_n{N}"
+        cases.append((name, (lambda N: (lambda: P_all.subset(list(range(N)))))(N)))
+    if args.lattice:
+        # the smallest patient of the batch recipe with its 64-scenario shift lattice
+        cases.append(("batch_s10_p2", lambda: synth.batch_patient(2, num=8, scen=64, seed=10)))
+    for name, make in cases:
+        P = make()
+        N = P.num_scen
         f_ref = _stored_fstar(name, P.digest())
-        row = dict(N=N, f_star=f_ref)
+        row = dict(N=N, workload=name, m=P.m, n=P.n, nnz=P.nnz, f_star=f_ref)
         for xu in ("dense", "cg"):
             row[f"admm_{xu}"] = _admm_run(P, f_ref, xu, stream)
         if not args.no_pgd:
@@ -147,7 +154,8 @@ def cmd_scaling(args):
         if "pgd_over_admm_time_to_1e-5" in row:
             msg += f" pgd/admm to 1e-5 {row['pgd_over_admm_time_to_1e-5']:.1f}x"
         print(msg, flush=True)
-    res = dict(workload=f"hn_full({args.seed}) restricted to its first N scenarios", rows=rows)
+    res = dict(workload=f"hn_full({args.seed}) restricted to its first N scenarios"
+                        + ("; batch patient 2 (seed 10) with 64 lattice scenarios" if args.lattice else ""), rows=rows)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)
@@ -155,17 +163,13 @@ def cmd_scaling(args):
 
 
 def _batch_patients(num: int, scen: int, seed: int):
-    """Patients of uneven size from the head-and-neck generator: body semi-axes
-    and target scale drawn per patient, a shift-lattice scenario set."""
+    """Patients of uneven size from the head-and-neck generator (the batch
+    recipe of synth.batch_params: body and target scales drawn per patient,
+    a shift-lattice scenario set)."""
     import synth
-    rng = np.random.default_rng(seed)
     out = []
     for k in range(num):
-        f = rng.uniform(0.62, 1.17)  # linear body scale: m ~ f^3 * 250k, 60k..400k voxels
-        semi = (int(50 * f), int(40 * f), int(30 * f))
-        grid = (int(2 * semi[0] + 20), int(2 * semi[1] + 40), int(2 * semi[2] + 20))
-        P = synth.make_hn(seed=seed * 100 + k, grid=grid, body_semi_vox=semi, target_size=rng.uniform(0.7, 2.0),
-                          scenarios="lattice", num_scen=scen)
+        P = synth.batch_patient(k, num=num, scen=scen, seed=seed)
         out.append(P)
         print(f"[batch] patient {k}: m={P.m} n={P.n} nnz={P.nnz}", flush=True)
     return out
@@ -351,6 +355,8 @@ def main(argv=None):
     a.add_argument("--n", default="1,2,3,4,5,6,7,8,9,10,11,12,13")
     a.add_argument("--no-pgd", action="store_true")
     a.add_argument("--sparse-pgd", action="store_true", help="also time PGD over the sparse matrices")
+    a.add_argument("--lattice", action="store_true",
+                   help="add the smallest batch patient with its 64-scenario shift lattice")
     a.add_argument("--out", default="")
     a = sub.add_parser("pgd")
     a.add_argument("--seed", type=int, default=0)

@@ -465,3 +465,26 @@ def hn_small(seed: int = 0, num_scen: int = 13, **kw) -> Problem:
                 num_layers=8, num_scen=num_scen)
     args.update(kw)
     return make_hn(seed=seed, **args)
+
+
+def batch_params(num: int, seed: int):
+    """Per-patient recipe of the multi-patient batch: for patient k the linear
+    body scale f ~ U[0.62, 1.17] (in-body voxels ~ f^3 * 250k, 60k..400k) and
+    the target scale ~ U[0.7, 2.0], drawn in that order from one seeded stream."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(num):
+        f = rng.uniform(0.62, 1.17)
+        ts = rng.uniform(0.7, 2.0)
+        semi = (int(50 * f), int(40 * f), int(30 * f))
+        grid = (int(2 * semi[0] + 20), int(2 * semi[1] + 40), int(2 * semi[2] + 20))
+        out.append(dict(seed=seed * 100 + k, grid=grid, body_semi_vox=semi, target_size=ts))
+    return out
+
+
+def batch_patient(k: int, num: int = 8, scen: int = 64, seed: int = 10) -> Problem:
+    """Patient k of the batch recipe (batch_params) with the shift-lattice
+    scenario set of `scen` scenarios."""
+    p = batch_params(num, seed)[k]
+    return make_hn(seed=p["seed"], grid=p["grid"], body_semi_vox=p["body_semi_vox"], target_size=p["target_size"],
+                   scenarios="lattice", num_scen=scen)

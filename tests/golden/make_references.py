@@ -30,6 +30,10 @@ WORKLOADS = {
 # the same patient with its first N scenarios (scenario-count scaling, Sec. 3.3)
 for _n in range(1, 13):
     WORKLOADS[f"hn_full_s0_n{_n}"] = (lambda n: (lambda: synth.hn_full(0).subset(list(range(n)))))(_n)
+# the two smallest patients of the multi-patient batch recipe (seed 10), with
+# their 64-scenario shift lattice
+for _k in (2, 1):
+    WORKLOADS[f"batch_s10_p{_k}"] = (lambda k: (lambda: synth.batch_patient(k, num=8, scen=64, seed=10)))(_k)
 
 
 def make(name: str) -> dict:
