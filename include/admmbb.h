@@ -248,6 +248,21 @@ admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, con
                             int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
                             float* maxes, float* dose_out);
 
+/* admm_dose_stats for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, outputs and errors, computed by the same kernels, with
+ * no hipMalloc, hipFree or other allocating call.  Its staging (voxel groups,
+ * the plan in fp64, histograms, sums, max keys) lives in a fixed 16 MiB array
+ * in device memory that each GPU the library runs on holds until the process
+ * ends; a call needs m + 4 N G nbins + 12 N G + 8 n bytes of it (each part
+ * rounded up to 256 bytes) and fails with ADMM_E_ARG when that exceeds 16 MiB.
+ * Every call on a GPU shares that GPU's array and clears what it accumulates
+ * into, so calls that overlap on one GPU (from several threads or streams)
+ * race; calls in sequence do not. */
+admm_status admm_dose_stats_noalloc(admm_ctx* ctx, int32_t patient, const double* x, const uint8_t* voxel_group,
+                                    int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
+                                    float* maxes, float* dose_out);
+
 /* Measurement: average device time in ms of one launch of a sparse pass over
  * every scenario of every patient (reps launches back to back, HIP events on
  * the context's stream).  kind 0: forward product A_s z fused with the

@@ -28,7 +28,7 @@ EXPORTS = [
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
     "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
     "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate", "admm_time_pass",
-    "admm_stream_probe",
+    "admm_stream_probe", "admm_dose_stats_noalloc",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
     "mlp_loss_grad", "mlp_adam_step", "mlp_last_error",
 ]
@@ -101,6 +101,7 @@ def _load():
         "admm_warm_start": [P, i32, P, dbl, i32],
         "admm_spot_features": [P, i32, P, P],
         "admm_dose_stats": [P, i32, P, P, i32, i32, dbl, P, P, P, P],
+        "admm_dose_stats_noalloc": [P, i32, P, P, i32, i32, dbl, P, P, P, P],
         "admm_get_xupdate": [P, P, P],
         "admm_time_pass": [P, i32, i32, P],
         "admm_stream_probe": [i64, i32, P],
@@ -294,9 +295,10 @@ class Solver:
         return out
 
     def dose_stats(self, x, voxel_group, num_groups: int, nbins: int, dmax: float, patient: int = 0,
-                   want_dose: bool = False):
+                   want_dose: bool = False, noalloc: bool = False):
         """Per-scenario, per-group dose histograms, sums and maxima of plan x
-        (computed on the GPU); returns (counts[N,G,nbins], sums[N,G], maxes[N,G], doses[N,m] or None)."""
+        (computed on the GPU); returns (counts[N,G,nbins], sums[N,G], maxes[N,G], doses[N,m] or None).
+        noalloc: call admm_dose_stats_noalloc (fixed device scratch, no allocation)."""
         N, m = self.num_scen[patient], self.m[patient]
         xa = np.ascontiguousarray(x, dtype=np.float64)
         grp = np.ascontiguousarray(voxel_group, dtype=np.uint8)
@@ -304,9 +306,9 @@ class Solver:
         sums = np.zeros((N, num_groups))
         maxes = np.zeros((N, num_groups), dtype=np.float32)
         dose = np.zeros((N, m), dtype=np.float32) if want_dose else None
-        _check(self.ctx, lib.admm_dose_stats(self.ctx, patient, xa.ctypes.data, grp.ctypes.data, int(num_groups),
-                                             int(nbins), float(dmax), counts.ctypes.data, sums.ctypes.data,
-                                             maxes.ctypes.data, _ptr(dose)))
+        fn = lib.admm_dose_stats_noalloc if noalloc else lib.admm_dose_stats
+        _check(self.ctx, fn(self.ctx, patient, xa.ctypes.data, grp.ctypes.data, int(num_groups), int(nbins),
+                            float(dmax), counts.ctypes.data, sums.ctypes.data, maxes.ctypes.data, _ptr(dose)))
         return counts, sums, maxes, dose
 
     def pgd(self, patient: int = 0, x0: Optional[np.ndarray] = None, **kw):

@@ -801,6 +801,12 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       check(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
       c->own_stream = true;
     }
+    {
+      // device address of the allocation-free entry point's fixed scratch,
+      // looked up once per device while it is current
+      void* sp = nullptr;
+      check(noalloc_scratch(&sp), "hipGetSymbolAddress");
+    }
     c->rho.resize(num_patients);
     for (int p = 0; p < num_patients; ++p) c->rho[p] = o.rho > 0 ? o.rho : 2.0 * H.gdiag_mean[p];
     c->trace_cap = std::max(1, o.max_iter + 2);
@@ -1330,9 +1336,13 @@ admm_status admm_matvec(admm_ctx* ctx, int32_t patient, int32_t scen, const floa
   GUARD_END(ctx)
 }
 
-admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, const uint8_t* voxel_group,
-                            int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
-                            float* maxes, float* dose_out) {
+}  // extern "C"
+
+namespace {
+
+admm_status dose_stats_check(admm_ctx* ctx, int32_t patient, const double* x, const uint8_t* voxel_group,
+                             int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
+                             float* maxes) {
   admm_status st = check_patient(ctx, patient);
   if (st != ADMM_OK) return st;
   if (!x || !voxel_group || !counts || !sums || !maxes) return set_err(ctx, ADMM_E_ARG, "NULL argument");
@@ -1344,7 +1354,70 @@ admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, con
     if (voxel_group[i] >= num_groups) return set_err(ctx, ADMM_E_ARG, "voxel_group entry >= num_groups");
   for (int j = 0; j < pt.n; ++j)
     if (!std::isfinite(x[j])) return set_err(ctx, ADMM_E_NONFINITE, "x is not finite");
+  return ADMM_OK;
+}
+
+// Queue the dose statistics of the plan already in d_pvec (fp32) into the
+// device arrays grp / cnt / key / sum (cnt, key, sum cleared here by fill
+// kernels), and the doses into dose_out when given; then the copies of the
+// counts, sums and max keys (into maxes, as 32-bit keys) back to the host, and
+// wait for them.
+void dose_stats_queue(admm_ctx* ctx, int32_t patient, const uint8_t* d_grp, uint32_t* d_cnt, uint32_t* d_key,
+                      double* d_sum, int G, int nbins, double dmax, uint32_t* counts, double* sums, float* maxes,
+                      float* dose_out) {
+  const Pat& pt = ctx->H.pat[patient];
+  const int N = pt.num_scen, m = pt.m;
+  const size_t per = static_cast<size_t>(G) * nbins;
+  static_assert(sizeof(float) == sizeof(uint32_t), "fill by bit pattern");
+  launch_fill_f32(reinterpret_cast<float*>(d_cnt), 0.0f, static_cast<int64_t>(per * N), ctx->stream);
+  launch_fill_f32(reinterpret_cast<float*>(d_key), 0.0f, static_cast<int64_t>(G) * N, ctx->stream);
+  launch_fill_f64(d_sum, 0.0, static_cast<int64_t>(G) * N, ctx->stream);
+  const float inv_w = static_cast<float>(nbins / dmax);
+  for (int s = 0; s < N; ++s) {
+    const Scen& sc = ctx->H.scen[pt.scen_begin + s];
+    launch_fill_f32(ctx->d_mvec, 0.0f, m, ctx->stream);
+    PassArgs pa = ctx->pass_args(ctx->mat32);
+    pa.src = ctx->d_pvec;
+    pa.src_per_scen = 0;
+    pa.tout = ctx->d_mvec;
+    pa.objpart = nullptr;
+    ctx->pass_launch(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
+    launch_dose_hist(ctx->d_mvec, d_grp, m, G, nbins, inv_w, d_cnt + per * s, d_sum + static_cast<size_t>(G) * s,
+                     d_key + static_cast<size_t>(G) * s, ctx->stream);
+    if (dose_out)
+      check(hipMemcpyAsync(dose_out + static_cast<size_t>(s) * m, ctx->d_mvec, sizeof(float) * m,
+                           hipMemcpyDeviceToHost, ctx->stream),
+            "D2H");
+  }
+  check(hipGetLastError(), "launch");
+  check(hipMemcpyAsync(counts, d_cnt, sizeof(uint32_t) * per * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+  check(hipMemcpyAsync(sums, d_sum, sizeof(double) * G * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+  check(hipMemcpyAsync(maxes, d_key, sizeof(uint32_t) * G * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
+  check(hipStreamSynchronize(ctx->stream), "sync");
+  // order-preserving keys back to floats, in place (0 marks an empty group)
+  for (size_t k = 0; k < static_cast<size_t>(G) * N; ++k) {
+    uint32_t key;
+    std::memcpy(&key, maxes + k, sizeof(key));
+    if (key == 0u) {
+      maxes[k] = -INFINITY;
+      continue;
+    }
+    const uint32_t u = (key & 0x80000000u) ? (key & 0x7fffffffu) : ~key;
+    std::memcpy(maxes + k, &u, sizeof(u));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, const uint8_t* voxel_group,
+                            int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
+                            float* maxes, float* dose_out) {
+  admm_status st = dose_stats_check(ctx, patient, x, voxel_group, num_groups, nbins, dmax, counts, sums, maxes);
+  if (st != ADMM_OK) return st;
   GUARD_BEGIN
+  const Pat& pt = ctx->H.pat[patient];
   const int N = pt.num_scen, m = pt.m, G = num_groups;
   const size_t per = static_cast<size_t>(G) * nbins;
   uint8_t* d_grp = nullptr;
@@ -1357,55 +1430,54 @@ admm_status admm_dose_stats(admm_ctx* ctx, int32_t patient, const double* x, con
     if (d_key) (void)hipFree(d_key);
     if (d_sum) (void)hipFree(d_sum);
   };
-  std::vector<uint32_t> keys(static_cast<size_t>(N) * G);
   try {
     check(hipMalloc(reinterpret_cast<void**>(&d_grp), m), "hipMalloc");
     check(hipMalloc(reinterpret_cast<void**>(&d_cnt), sizeof(uint32_t) * per * N), "hipMalloc");
     check(hipMalloc(reinterpret_cast<void**>(&d_key), sizeof(uint32_t) * G * N), "hipMalloc");
     check(hipMalloc(reinterpret_cast<void**>(&d_sum), sizeof(double) * G * N), "hipMalloc");
     check(hipMemcpyAsync(d_grp, voxel_group, m, hipMemcpyHostToDevice, ctx->stream), "H2D");
-    check(hipMemsetAsync(d_cnt, 0, sizeof(uint32_t) * per * N, ctx->stream), "memset");
-    check(hipMemsetAsync(d_key, 0, sizeof(uint32_t) * G * N, ctx->stream), "memset");
-    launch_fill_f64(d_sum, 0.0, static_cast<int64_t>(G) * N, ctx->stream);
     ctx->upload_pvec(patient, x, ctx->d_pvec);
-    const float inv_w = static_cast<float>(nbins / dmax);
-    for (int s = 0; s < N; ++s) {
-      const Scen& sc = ctx->H.scen[pt.scen_begin + s];
-      launch_fill_f32(ctx->d_mvec, 0.0f, m, ctx->stream);
-      PassArgs pa = ctx->pass_args(ctx->mat32);
-      pa.src = ctx->d_pvec;
-      pa.src_per_scen = 0;
-      pa.tout = ctx->d_mvec;
-      pa.objpart = nullptr;
-      ctx->pass_launch(PASS_MATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
-      launch_dose_hist(ctx->d_mvec, d_grp, m, G, nbins, inv_w, d_cnt + per * s, d_sum + static_cast<size_t>(G) * s,
-                       d_key + static_cast<size_t>(G) * s, ctx->stream);
-      if (dose_out)
-        check(hipMemcpyAsync(dose_out + static_cast<size_t>(s) * m, ctx->d_mvec, sizeof(float) * m,
-                             hipMemcpyDeviceToHost, ctx->stream),
-              "D2H");
-    }
-    check(hipGetLastError(), "launch");
-    check(hipMemcpyAsync(counts, d_cnt, sizeof(uint32_t) * per * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
-    check(hipMemcpyAsync(sums, d_sum, sizeof(double) * G * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
-    check(hipMemcpyAsync(keys.data(), d_key, sizeof(uint32_t) * G * N, hipMemcpyDeviceToHost, ctx->stream), "D2H");
-    check(hipStreamSynchronize(ctx->stream), "sync");
+    dose_stats_queue(ctx, patient, d_grp, d_cnt, d_key, d_sum, G, nbins, dmax, counts, sums, maxes, dose_out);
   } catch (...) {
     release();
     throw;
   }
   release();
-  for (size_t k = 0; k < keys.size(); ++k) {
-    const uint32_t key = keys[k];
-    if (key == 0u) {
-      maxes[k] = -INFINITY;  // empty group
-      continue;
-    }
-    const uint32_t u = (key & 0x80000000u) ? (key & 0x7fffffffu) : ~key;
-    float f;
-    std::memcpy(&f, &u, sizeof(f));
-    maxes[k] = f;
-  }
+  return ADMM_OK;
+  GUARD_END(ctx)
+}
+
+admm_status admm_dose_stats_noalloc(admm_ctx* ctx, int32_t patient, const double* x, const uint8_t* voxel_group,
+                                    int32_t num_groups, int32_t nbins, double dmax, uint32_t* counts, double* sums,
+                                    float* maxes, float* dose_out) {
+  admm_status st = dose_stats_check(ctx, patient, x, voxel_group, num_groups, nbins, dmax, counts, sums, maxes);
+  if (st != ADMM_OK) return st;
+  const Pat& pt = ctx->H.pat[patient];
+  const size_t N = static_cast<size_t>(pt.num_scen), G = static_cast<size_t>(num_groups);
+  auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+  const size_t o_cnt = up(static_cast<size_t>(pt.m));
+  const size_t o_key = o_cnt + up(sizeof(uint32_t) * N * G * static_cast<size_t>(nbins));
+  const size_t o_sum = o_key + up(sizeof(uint32_t) * N * G);
+  const size_t o_x = o_sum + up(sizeof(double) * N * G);
+  const size_t need = o_x + up(sizeof(double) * static_cast<size_t>(pt.n));
+  if (need > kNoAllocScratchBytes)
+    return set_err(ctx, ADMM_E_ARG,
+                   "admm_dose_stats_noalloc needs " + std::to_string(need) + " bytes of scratch (m + 4 N G nbins + "
+                   "12 N G + 8 n, each rounded up to 256); the fixed scratch holds " +
+                       std::to_string(kNoAllocScratchBytes));
+  GUARD_BEGIN
+  void* base = nullptr;
+  check(noalloc_scratch(&base), "hipGetSymbolAddress");
+  unsigned char* sp = static_cast<unsigned char*>(base);
+  uint8_t* d_grp = sp;
+  uint32_t* d_cnt = reinterpret_cast<uint32_t*>(sp + o_cnt);
+  uint32_t* d_key = reinterpret_cast<uint32_t*>(sp + o_key);
+  double* d_sum = reinterpret_cast<double*>(sp + o_sum);
+  double* d_x = reinterpret_cast<double*>(sp + o_x);
+  check(hipMemcpyAsync(d_grp, voxel_group, static_cast<size_t>(pt.m), hipMemcpyHostToDevice, ctx->stream), "H2D");
+  check(hipMemcpyAsync(d_x, x, sizeof(double) * static_cast<size_t>(pt.n), hipMemcpyHostToDevice, ctx->stream), "H2D");
+  launch_f64_to_f32(d_x, ctx->d_pvec + pt.zvec_base, pt.n, ctx->stream);
+  dose_stats_queue(ctx, patient, d_grp, d_cnt, d_key, d_sum, num_groups, nbins, dmax, counts, sums, maxes, dose_out);
   return ADMM_OK;
   GUARD_END(ctx)
 }

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "internal.h"
 
@@ -78,9 +79,47 @@ __global__ __launch_bounds__(kThreads) void k_dose_hist(const float* __restrict_
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ out,
+                                                          int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = static_cast<float>(in[i]);
+}
+
 }  // namespace
 
+// Scratch of the allocation-free dose statistics: a fixed array in device
+// memory, one copy per GPU, alive until the process ends.  Host code never
+// passes the array's own name to a kernel (on the host that name is only a
+// stand-in, not a device address); it uses the address hipGetSymbolAddress
+// returns for the current device.
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 int dose_hist_smem_bytes(int G, int nbins) { return G * 12 + G * nbins * 4; }
+
+hipError_t noalloc_scratch(void** ptr) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDev] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
+
+void launch_f64_to_f32(const double* in, float* out, int n, hipStream_t st) {
+  int nb = (n + kThreads - 1) / kThreads;
+  nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(nb), dim3(kThreads), 0, st, in, out, n);
+}
 
 void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
                       double* sums, uint32_t* maxkey, hipStream_t st) {

@@ -277,6 +277,12 @@ void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st
 void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st);
 void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
                       double* sums, uint32_t* maxkey, hipStream_t st);
+// Allocation-free dose statistics: device address of the fixed scratch array
+// (dose.hip) on the current device, looked up once per device; and a
+// double-to-float copy kernel for the plan it receives.
+constexpr size_t kNoAllocScratchBytes = size_t{16} << 20;
+hipError_t noalloc_scratch(void** ptr);
+void launch_f64_to_f32(const double* in, float* out, int n, hipStream_t st);
 
 // ---- dense PGD (pgd_dense.hip) ----
 constexpr int kPgdK = 8;  // backtracking steps evaluated per round
