@@ -77,7 +77,7 @@ def spmv_bytes(P) -> dict:
     return out
 
 
-def cpu_baseline(P, fstar, budget_s: float = 90.0) -> dict:
+def cpu_baseline(P, fstar, budget_s: float = 90.0, progress: bool = False) -> dict:
     """Time the FP64 oracle's ADMM-BB (the paper's algorithm: cached Cholesky
     x-updates, Appendix A) on the whole workload, all 13 scenarios, on this
     host: the set-up (dense Gram matrix and Cholesky factor per scenario), then
@@ -108,6 +108,8 @@ def cpu_baseline(P, fstar, budget_s: float = 90.0) -> dict:
 
     def cb(k, z, f):
         stamps.append((k + 1, time.perf_counter(), f))
+        if progress:
+            print(f"[cpu] iteration {k + 1}: {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
         if fstar is not None and (f - fstar) / fstar <= 1e-5:
             raise _Done
         if time.perf_counter() - t_start > budget_s:
@@ -156,7 +158,7 @@ def cpu_scaling(args):
         name = f"hn_full_s{args.seed}" if N == P_all.num_scen else f"hn_full_s{args.seed}_n{N}"
         rec, _ = load_ref(name)
         fstar = rec["f_star"] if (rec is not None and rec["digest"] == P.digest()) else None
-        r = cpu_baseline(P, fstar, budget_s=300.0)
+        r = cpu_baseline(P, fstar, budget_s=300.0, progress=True)
         r.update(N=N, workload=name)
         rows.append(r)
         print(f"[cpu-scaling] N={N}: set-up {r['setup_s']:.1f}s, {r['iters']} it in {r['solve_s']:.1f}s",
@@ -166,7 +168,9 @@ def cpu_scaling(args):
         rec, _ = load_ref(f"batch_s10_p{k}")
         if rec is None or rec["digest"] != P.digest():
             continue
-        r = cpu_baseline(P, rec["f_star"], budget_s=600.0)
+        print(f"[cpu-scaling] batch patient {k}: oracle set-up of {P.num_scen} scenarios", file=sys.stderr,
+              flush=True)
+        r = cpu_baseline(P, rec["f_star"], budget_s=600.0, progress=True)
         r.update(N=P.num_scen, workload=f"batch_s10_p{k}", m=P.m, n=P.n)
         rows.append(r)
         print(f"[cpu-scaling] batch patient {k} (N={P.num_scen}): set-up {r['setup_s']:.1f}s, {r['iters']} it in "
@@ -181,6 +185,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--format", default="auto", choices=["auto", "csr", "sell"],
+                    help="layout of A_s for the sparse passes (auto: the set-up autotuner picks)")
     ap.add_argument("--cg-max", type=int, default=8)
     ap.add_argument("--xupdate", default="auto", choices=["auto", "cg", "dense"],
                     help="x-update: warm-started CG on the sparse A_s, or the cached dense inverse")
@@ -233,7 +239,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = A.Solver(P, precision=args.precision, cg_max=args.cg_max, max_iter=2000, stream=stream,
-                 use_graph=1 if args.graph else 0, xupdate=args.xupdate)
+                 use_graph=1 if args.graph else 0, xupdate=args.xupdate, format=args.format)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     xmode, factor_ms = S.xupdate()

@@ -133,8 +133,22 @@ typedef struct {
                             matrices take at most a quarter of the free device memory, else CG.
                           The set-up works on chunks of scenarios whose fp64 matrices take at most
                           8 GiB (environment variable ADMMBB_DENSE_CHUNK_MB overrides the limit). */
+  int32_t format;      /* layout of A_s read by the sparse passes (the same length-sorted rows in
+                          4-element chunks either way):
+                          ADMM_FORMAT_CSR: each row's chunks contiguous, L lanes per row;
+                          ADMM_FORMAT_SELL: sliced, the rows of a tile in slices of 64 / L rows with
+                            their chunks interleaved so that a wave load reads 64 consecutive chunks
+                            (16-bit column indices only, n <= 65535);
+                          ADMM_FORMAT_AUTO (default): both are built and the set-up autotuner
+                            picks the faster for the CG pass (the sliced one when it does not run) */
+  int32_t deterministic; /* 1: every sum of an iteration is exact or in a fixed order (64-bit
+                          fixed-point column accumulators, lds_acc -1 or 2 required), so runs and
+                          resumed runs repeat bit for bit; default 0 (the autotuner may pick fp64
+                          LDS atomics, whose sums depend on the order of the additions) */
   void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
 } admm_options;
+
+enum { ADMM_FORMAT_AUTO = -1, ADMM_FORMAT_CSR = 0, ADMM_FORMAT_SELL = 1 };
 
 /* Per-iteration record (also the summary returned by solve / iterate). */
 typedef struct {
@@ -318,6 +332,10 @@ admm_status admm_get_trace(admm_ctx* ctx, int32_t patient, admm_info* buf, int32
  * accumulator kind, and the measured average pass time in ms of the chosen one
  * (all scenarios, fp32 or the CG value precision). */
 admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms);
+
+/* Layout of A_s the sparse passes read (ADMM_FORMAT_CSR or ADMM_FORMAT_SELL):
+ * the one asked for, or the set-up autotuner's pick under ADMM_FORMAT_AUTO. */
+admm_status admm_get_format(const admm_ctx* ctx, int32_t* format);
 
 /* CG steps performed per scenario of a patient since its last reset
  * (num_scen int64 entries): the number of fused CG-pass applications of A_s. */

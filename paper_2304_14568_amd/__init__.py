@@ -20,13 +20,14 @@ OK, MAX_ITER = 0, 1
 E_ARG, E_CSR, E_NEGATIVE, E_NONFINITE, E_OOM, E_HIP, E_DIVERGED, E_STATE = -1, -2, -3, -4, -5, -6, -7, -8
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 XUPDATE = {"auto": -1, "cg": 0, "dense": 1}
+FORMAT = {"auto": -1, "csr": 0, "sell": 1}
 
 # every symbol include/admmbb.h declares
 EXPORTS = [
     "admm_default_options", "pgd_default_options", "admm_setup", "admm_setup_batch", "admm_warm_start",
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
-    "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
+    "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_format", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
     "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate", "admm_time_pass",
     "admm_stream_probe", "admm_dose_stats_noalloc",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
@@ -60,7 +61,8 @@ class OptionsC(ctypes.Structure):
                 ("cg_eta", ctypes.c_double), ("cg_eta_floor", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("lds_acc", ctypes.c_int32), ("tile_nnz", ctypes.c_int32), ("pass_threads", ctypes.c_int32),
-                ("pass_unroll", ctypes.c_int32), ("xupdate", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("pass_unroll", ctypes.c_int32), ("xupdate", ctypes.c_int32), ("format", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class InfoC(ctypes.Structure):
@@ -128,6 +130,7 @@ def _load():
         "admm_get_trace": [P, i32, P, i32, P],
         "admm_get_cg_counts": [P, i32, P],
         "admm_get_tuning": [P, P, P, P, P],
+        "admm_get_format": [P, P],
         "admm_get_sizes": [P, i32, P, P, P, P],
         "admm_enable_timing": [P, i32],
         "admm_get_timing": [P, P, P, P],
@@ -208,6 +211,8 @@ def default_options(**kw) -> OptionsC:
             v = PREC[v]
         if k == "xupdate" and isinstance(v, str):
             v = XUPDATE[v]
+        if k == "format" and isinstance(v, str):
+            v = FORMAT[v]
         if k == "stream" and v is not None and not isinstance(v, int):
             v = int(getattr(v, "cuda_stream", v))  # torch.cuda.Stream -> hipStream_t
         if not hasattr(o, k):
@@ -398,7 +403,10 @@ class Solver:
         ms = ctypes.c_double()
         _check(self.ctx, lib.admm_get_tuning(self.ctx, ctypes.byref(t), ctypes.byref(u), ctypes.byref(a),
                                              ctypes.byref(ms)))
-        return dict(threads=t.value, unroll=u.value, lds_acc=a.value, pass_ms=ms.value)
+        f = ctypes.c_int32()
+        _check(self.ctx, lib.admm_get_format(self.ctx, ctypes.byref(f)))
+        return dict(threads=t.value, unroll=u.value, lds_acc=a.value, pass_ms=ms.value,
+                    format="sell" if f.value == 1 else "csr")
 
     def cg_counts(self, patient: int = 0):
         c = np.zeros(self.num_scen[patient], dtype=np.int64)

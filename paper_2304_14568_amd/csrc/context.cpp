@@ -61,7 +61,17 @@ struct admm_ctx {
   Tile* d_tiles = nullptr;
   Blk* d_blk = nullptr;
   Blk* d_pblk = nullptr;
+  // the sparse passes read mat32 / matlp (the layout in use); the Gram
+  // kernels of the dense set-up read the chunk-row layout csr32
   MatDev mat32{}, matlp{};
+  MatDev csr32{}, csrlp{}, sell32{}, selllp{};
+  bool has_sell = false;
+  int fmt = FMT_CSR;
+  void use_format(int f) {
+    fmt = (f == FMT_SELL && has_sell) ? FMT_SELL : FMT_CSR;
+    mat32 = fmt == FMT_SELL ? sell32 : csr32;
+    matlp = fmt == FMT_SELL ? selllp : csrlp;
+  }
   // device vectors
   float *d_x = nullptr, *d_r = nullptr, *d_v = nullptr, *d_q = nullptr, *d_zp = nullptr, *d_y = nullptr;
   float *d_b = nullptr, *d_dinv = nullptr, *d_z = nullptr, *d_lb = nullptr, *d_ub = nullptr;
@@ -153,6 +163,19 @@ struct admm_ctx {
     }
     for (auto& t : th) t.join();
     for (hipError_t e : rc) check(e, "hipMemcpy H2D");
+    return p;
+  }
+  // One device array holding per-scenario host parts one after the other
+  // (the sliced layout, 4 elements per chunk slot).
+  template <class T>
+  T* upload_parts(const std::vector<RawVec<T>>& parts, int64_t total_elems) {
+    T* p = alloc<T>(static_cast<size_t>(std::max<int64_t>(total_elems, 1)));
+    int64_t o = 0;
+    for (const auto& v : parts) {
+      if (!v.empty())
+        check(hipMemcpy(p + o, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+      o += static_cast<int64_t>(v.size());
+    }
     return p;
   }
   ~admm_ctx() {
@@ -302,7 +325,7 @@ struct admm_ctx {
       int32_t* cur = cnt + nt;
       int64_t* off = static_cast<int64_t*>(bo.p);
       launch_fill_f32(reinterpret_cast<float*>(cnt), 0.0f, 2 * nt, stream);  // counts and cursors
-      for (int s = 0; s < cs; ++s) launch_gram_rows(mat32, H.scen[g0 + s], nb, cnt + s * ntl, nullptr, nullptr, stream);
+      for (int s = 0; s < cs; ++s) launch_gram_rows(csr32, H.scen[g0 + s], nb, cnt + s * ntl, nullptr, nullptr, stream);
       launch_gram_scan(cnt, nt, off, stream);
       check(hipMemcpyAsync(h_scr, off + nt, sizeof(int64_t), hipMemcpyDeviceToHost, stream), "D2H");
       check(hipStreamSynchronize(stream), "sync");
@@ -328,15 +351,15 @@ struct admm_ctx {
         check(hipMemcpy(bsc.p, gs.data(), sizeof(double) * static_cast<size_t>(cs), hipMemcpyHostToDevice), "H2D");
         GramEntry* list = static_cast<GramEntry*>(bl.p);
         for (int s = 0; s < cs; ++s)
-          launch_gram_rows(mat32, H.scen[g0 + s], nb, cur + s * ntl, off + s * ntl, list, stream);
-        launch_gram_tiles(mat32, d_rw64, d_scen, g0, cs, nb, off, list, static_cast<const double*>(bsc.p), d_G,
+          launch_gram_rows(csr32, H.scen[g0 + s], nb, cur + s * ntl, off + s * ntl, list, stream);
+        launch_gram_tiles(csr32, d_rw64, d_scen, g0, cs, nb, off, list, static_cast<const double*>(bsc.p), d_G,
                           pt.npad, stream);
       }
     }
     if (!lists) {
       (void)hipGetLastError();  // the failed allocation
       launch_fill_f64(d_G, 0.0, nn * cs, stream);
-      for (int s = 0; s < cs; ++s) launch_gram(mat32, d_rw64, H.scen[g0 + s], d_G + s * nn, pt.npad, stream);
+      for (int s = 0; s < cs; ++s) launch_gram(csr32, d_rw64, H.scen[g0 + s], d_G + s * nn, pt.npad, stream);
     }
     check(hipGetLastError(), "Gram launch");
     check(hipStreamSynchronize(stream), "sync");  // before the lists are freed
@@ -524,25 +547,30 @@ struct admm_ctx {
   // Time the fused CG pass over every tile for each candidate configuration
   // and keep the fastest (values of the multiplied vector do not change the work).
   void autotune() {
-    const MatDev& m = (opts.precision == ADMM_PREC_FP32) ? mat32 : matlp;
-    std::vector<int> th = {256, 512}, un = {1, 2}, ac = {ACC_FIX64, ACC_F64};
+    std::vector<int> th = {256, 512}, un = {1, 2}, ac = {ACC_FIX64, ACC_F64}, fm = {FMT_CSR};
     if (opts.pass_threads) th = {opts.pass_threads};
     if (opts.pass_unroll) un = {opts.pass_unroll};
     if (opts.lds_acc >= 0) ac = {opts.lds_acc};
+    if (opts.deterministic) ac = {ACC_FIX64};
+    if (has_sell) fm = opts.format == FMT_SELL ? std::vector<int>{FMT_SELL} : std::vector<int>{FMT_CSR, FMT_SELL};
     if (pass_smem_bytes(H.nmax, ac[0]) > 65536) return;
     hipEvent_t e0, e1;
     check(hipEventCreate(&e0), "hipEventCreate");
     check(hipEventCreate(&e1), "hipEventCreate");
     double best = 1e30;
-    int bt = th[0], bu = un[0], ba = ac[0];
+    int bt = th[0], bu = un[0], ba = ac[0], bf = fm[0];
     const int reps = 3;
+    for (int f : fm)
     for (int a64 : ac)
       for (int t : th)
         for (int u : un) {
+          // the sliced layout has no row pipelining variant
+          if (f == FMT_SELL && u != un[0]) continue;
+          use_format(f);
           acc = a64;
           pass_threads = t;
           pass_unroll = u;
-          PassArgs pa = pass_args(m);
+          PassArgs pa = pass_args(opts.precision == ADMM_PREC_FP32 ? mat32 : matlp);
           pa.src = d_v;
           pa.src_per_scen = 1;
           pa.objpart = nullptr;
@@ -558,10 +586,12 @@ struct admm_ctx {
             bt = t;
             bu = u;
             ba = a64;
+            bf = f;
           }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    use_format(bf);
     acc = ba;
     pass_threads = bt;
     pass_unroll = bu;
@@ -695,6 +725,8 @@ admm_status admm_default_options(admm_options* o) {
   o->tile_nnz = 0;
   o->pass_threads = 0;
   o->pass_unroll = 0;
+  o->format = -1;
+  o->deterministic = 0;
   o->xupdate = ADMM_XUPDATE_AUTO;
   o->stream = nullptr;
   return ADMM_OK;
@@ -794,7 +826,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->T = static_cast<int>(H.tiles.size());
     c->NB = static_cast<int>(H.blk.size());
     c->NPB = static_cast<int>(H.pblk.size());
-    c->acc = o.lds_acc >= 0 ? o.lds_acc : ACC_FIX64;
+    c->acc = (o.lds_acc >= 0 && !o.deterministic) ? o.lds_acc : ACC_FIX64;
     if (o.stream) {
       c->stream = static_cast<hipStream_t>(o.stream);
     } else {
@@ -930,15 +962,36 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     const float* d_rw = c->upload(H.rw);
     const float* d_rpres = c->upload(H.rpres);
     const int32_t* d_rorig = c->upload(H.rorig);
-    c->mat32 = MatDev{d_rp, d_col, c->upload(H.val), nullptr, d_rw, d_rpres, d_rorig, H.col16_used ? 1 : 0, VAL_F32};
-    clk.mark("sparse matrix upload");
+    const int c16 = H.col16_used ? 1 : 0;
+    const int vlp = o.precision == ADMM_PREC_BF16 ? VAL_BF16 : VAL_F16;
+    c->csr32 = MatDev{d_rp, d_col, c->upload(H.val), nullptr, d_rw, d_rpres, d_rorig, nullptr, c16, VAL_F32,
+                      FMT_CSR, 0};
     // the host copies of the largest arrays are not needed after upload
     decltype(H.val)().swap(H.val);
+    const float* d_rscale = nullptr;
     if (o.precision != ADMM_PREC_FP32) {
-      c->matlp = MatDev{d_rp, d_col, c->upload(H.val_lp), c->upload(H.rscale), d_rw, d_rpres, d_rorig,
-                        H.col16_used ? 1 : 0, o.precision == ADMM_PREC_BF16 ? VAL_BF16 : VAL_F16};
+      d_rscale = c->upload(H.rscale);
+      c->csrlp = MatDev{d_rp, d_col, c->upload(H.val_lp), d_rscale, d_rw, d_rpres, d_rorig, nullptr, c16, vlp,
+                        FMT_CSR, 0};
       decltype(H.val_lp)().swap(H.val_lp);
     }
+    c->has_sell = !H.soff.empty() && !H.sell_val.empty();
+    if (c->has_sell) {
+      const uint32_t* d_soff = c->upload(H.soff);
+      const int64_t ne = 4 * H.sell_total;  // elements: four per chunk slot (low-precision records: eight)
+      const void* d_scol = c->upload_parts(H.sell_col16, ne);
+      c->sell32 = MatDev{d_rp, d_scol, c->upload_parts(H.sell_val, ne), nullptr, d_rw, d_rpres, d_rorig, d_soff,
+                         c16, VAL_F32, FMT_SELL, 0};
+      if (o.precision != ADMM_PREC_FP32)
+        c->selllp = MatDev{d_rp, d_scol, c->upload_parts(H.sell_val_lp, 2 * ne), d_rscale, d_rw, d_rpres, d_rorig,
+                           d_soff, c16, vlp, FMT_SELL, 0};
+      decltype(H.sell_val)().swap(H.sell_val);
+      decltype(H.sell_col16)().swap(H.sell_col16);
+      decltype(H.sell_val_lp)().swap(H.sell_val_lp);
+    }
+    // before the set-up autotuner decides: the sliced layout unless the chunk-row one is asked for
+    c->use_format(o.format == FMT_CSR ? FMT_CSR : FMT_SELL);
+    clk.mark("sparse matrix upload");
     decltype(H.col16)().swap(H.col16);
     decltype(H.col32)().swap(H.col32);
     decltype(H.rp)().swap(H.rp);
@@ -1901,6 +1954,12 @@ admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms
   *ms_out = static_cast<double>(ms) / reps;
   return ADMM_OK;
   GUARD_END(ctx)
+}
+
+admm_status admm_get_format(const admm_ctx* ctx, int32_t* format) {
+  if (!ctx || !format) return ADMM_E_ARG;
+  *format = ctx->fmt == FMT_SELL ? ADMM_FORMAT_SELL : ADMM_FORMAT_CSR;
+  return ADMM_OK;
 }
 
 admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms) {

@@ -54,6 +54,14 @@ struct Packed {
   RawVec<float> rw, rpres;
   RawVec<double> rw64;            // c_s w_i per sorted row in fp64 (Gram matrices of the dense x-update)
   RawVec<int32_t> rorig;
+  // sliced layout (MatDev FMT_SELL), one array per (patient, scenario) in
+  // scenario order, uploaded at sell_base of each; slice offsets of all
+  // scenarios in soff (one terminal entry after each scenario's slices)
+  std::vector<RawVec<float>> sell_val;
+  std::vector<RawVec<uint16_t>> sell_col16;
+  std::vector<RawVec<uint16_t>> sell_val_lp;
+  std::vector<uint32_t> soff;
+  int64_t sell_total = 0;         // chunk slots of the sliced layout over all scenarios
   std::vector<float> b;           // A_s^T c_s W p per scenario (stacked)
   std::vector<double> b64;        // the same in fp64 (dense x-update right-hand sides)
   std::vector<float> dinv;        // Jacobi inverse diagonal (stacked), filled when requested

@@ -36,6 +36,7 @@ struct Scen {
   float cw;             // scenario probability c_s (already folded into rw)
   int32_t pad;
   int64_t mpack_off;    // dense x-update: offset of its packed inverse (upper 64 x 64 tiles, 4096 each)
+  int64_t sell_base;    // sliced layout: first 4-element chunk slot of the scenario
 };
 
 // One per patient.
@@ -66,7 +67,7 @@ struct Tile {
   float wmax;         // max over the tile's rows of c_s w_i sum_j |a_ij|
   float pmax;         // max over the tile's rows of c_s w_i p_i
   float cmax;         // max over columns of sum over the tile's rows of |a_ij|
-  int32_t pad;
+  int32_t slice_begin; // sliced layout: index of the tile's first slice in MatDev::soff
 };
 
 // Column block of a scenario (owner = scenario) or of a patient (owner = patient).
@@ -109,17 +110,29 @@ struct AlgoParams {
   int32_t num_pat;
 };
 
-// Matrix storage of all (patient, scenario) pairs, length-sorted rows.
+// Matrix storage of all (patient, scenario) pairs, length-sorted rows, in one
+// of two layouts of the same 4-element chunks:
+//   FMT_CSR   every row's chunks one after the other (row r at rp[r]);
+//   FMT_SELL  sliced: the rows of a tile in slices of G = 64 / L consecutive
+//             rows (L = the tile's lanes per row), each slice padded to K
+//             chunk slots per lane; slot (k, lane) of a slice at
+//             soff[slice] + 64 k + lane, lane = g L + l holding chunk k L + l
+//             of the slice's row g, so that one wave load instruction reads 64
+//             consecutive chunks.  Padding slots hold value 0 and a valid column.
+enum MatFmt { FMT_CSR = 0, FMT_SELL = 1 };
 struct MatDev {
   const uint32_t* rp;      // row starts in 4-element chunks relative to nnz_base (rows padded to whole chunks)
-  const void* col;         // uint16 (n <= 65535) or int32 column indices
-  const void* val;         // float / bf16 bits / fp16 values
+  const void* col;         // uint16 (n <= 65535) or int32 column indices (in the layout of fmt)
+  const void* val;         // float / bf16 bits / fp16 values (in the layout of fmt)
   const float* rscale;     // per-row scale for low-precision values (nullptr for fp32)
   const float* rw;         // c_s * w_i per sorted row
   const float* rpres;      // p_i per sorted row
   const int32_t* rorig;    // original row index per sorted row
+  const uint32_t* soff;    // FMT_SELL: slot offset of every slice relative to the scenario's sell_base
   int32_t col16;           // 1 when col holds uint16
   int32_t vkind;           // ValKind
+  int32_t fmt;             // MatFmt
+  int32_t pad;
 };
 
 struct PassArgs {

@@ -229,6 +229,20 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
   const uint32_t* __restrict__ rp = a.mat.rp + sc.rp_base;
   const VC* __restrict__ valc = reinterpret_cast<const VC*>(static_cast<const VT*>(a.mat.val) + sc.nnz_base);
   const CCk* __restrict__ colc = reinterpret_cast<const CCk*>(static_cast<const CT*>(a.mat.col) + sc.nnz_base);
+  // bf16 / fp16 values with 16-bit columns: one 16-byte record per chunk (four
+  // values, then their four columns), one load instruction per chunk
+  constexpr bool kRec = VK != VAL_F32 && C16;
+  const uint4* __restrict__ recc = reinterpret_cast<const uint4*>(a.mat.val) + sc.nnz_base / 4;
+  auto ld = [&](uint32_t c, float (&v4)[4], CCk& c4) {
+    if constexpr (kRec) {
+      const uint4 q = recc[c];
+      VChunk<VK>::unpack(VC{q.x, q.y}, v4);
+      c4 = CCk{q.z, q.w};
+    } else {
+      VChunk<VK>::unpack(valc[c], v4);
+      c4 = colc[c];
+    }
+  };
   const int64_t rb = sc.row_base;
   const int rend = t.row_end;
   float* __restrict__ qf = static_cast<float*>(qacc);
@@ -264,8 +278,7 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
     for (int k = 0; k < K; ++k) {
       const uint32_t c = s0 + lane + k * L;
       if (c < e0) {
-        VChunk<VK>::unpack(valc[c], vv[k]);
-        cc[k] = colc[c];
+        ld(c, vv[k], cc[k]);
       } else {
         vv[k][0] = vv[k][1] = vv[k][2] = vv[k][3] = 0.0f;
         cc[k] = CCk{};
@@ -311,8 +324,9 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
       for (int k = 0; k < K; ++k) dot4(cc[k], vv[k], dot);
       for (uint32_t c = s + lane + K * L; c < e; c += L) {
         float v4[4];
-        VChunk<VK>::unpack(valc[c], v4);
-        dot4(colc[c], v4, dot);
+        CCk c4;
+        ld(c, v4, c4);
+        dot4(c4, v4, dot);
       }
 #pragma unroll
       for (int off = L / 2; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
@@ -335,8 +349,9 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
       }
       for (uint32_t c = s + lane + K * L; c < e; c += L) {
         float v4[4];
-        VChunk<VK>::unpack(valc[c], v4);
-        scatter4(colc[c], v4, tv, td);
+        CCk c4;
+        ld(c, v4, c4);
+        scatter4(c4, v4, tv, td);
       }
     }
     s = sn;
@@ -352,7 +367,146 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
   }
 }
 
-template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE>
+// The same work over the sliced layout (FMT_SELL): wave w of the workgroup
+// takes slices w, w + NW, ... of the tile; in a slice, lanes g L .. g L + L - 1
+// hold row g (G = 64 / L rows), and the wave's k-th load instruction reads the
+// slice's 64 consecutive chunk slots of step k (1 KiB of fp32 values).  The
+// number of steps is the slice's, uniform across the wave, so the loads are
+// not predicated; padding slots hold zeros and add nothing.
+template <int VK, bool C16, int L, int MODE, int ACC, int NT>
+__device__ __forceinline__ void pass_slices(const PassArgs& a, const Tile& t, const Scen& sc, const float* vsh,
+                                            void* qacc, double fscale, double& objacc) {
+  using VC = typename VChunk<VK>::T;
+  using CCk = typename CChunk<C16>::T;
+  using VT = typename ValT<VK>::T;
+  using CT = std::conditional_t<C16, uint16_t, int32_t>;
+  constexpr bool kDot = MODE != PASS_RMATVEC;
+  constexpr bool kScatter = MODE == PASS_GRAD || MODE == PASS_CG || MODE == PASS_RMATVEC;
+  constexpr bool kDot64 = MODE == PASS_GRAD || MODE == PASS_OBJ || MODE == PASS_MATVEC;
+  using DACC = std::conditional_t<kDot64, double, float>;
+  constexpr int K = kRegChunks;
+  constexpr int G = 64 / L;
+  constexpr int NW = NT / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int g = lane / L;
+  const VC* __restrict__ valc = reinterpret_cast<const VC*>(static_cast<const VT*>(a.mat.val) + sc.sell_base * 4);
+  const CCk* __restrict__ colc = reinterpret_cast<const CCk*>(static_cast<const CT*>(a.mat.col) + sc.sell_base * 4);
+  constexpr bool kRec = VK != VAL_F32 && C16;
+  const uint4* __restrict__ recc = reinterpret_cast<const uint4*>(a.mat.val) + sc.sell_base;
+  auto ld = [&](uint32_t c, float (&v4)[4], CCk& c4) {
+    if constexpr (kRec) {
+      const uint4 q = recc[c];
+      VChunk<VK>::unpack(VC{q.x, q.y}, v4);
+      c4 = CCk{q.z, q.w};
+    } else {
+      VChunk<VK>::unpack(valc[c], v4);
+      c4 = colc[c];
+    }
+  };
+  const uint32_t* __restrict__ soff = a.mat.soff + t.slice_begin;
+  const int64_t rb = sc.row_base;
+  const int nsl = (t.row_end - t.row_begin + G - 1) / G;
+  float* __restrict__ qf = static_cast<float*>(qacc);
+  double* __restrict__ qd = static_cast<double*>(qacc);
+  unsigned long long* __restrict__ qi = static_cast<unsigned long long*>(qacc);
+
+  auto scatter4 = [&](const CCk& c4, const float (&v4)[4], float tv, double td) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jc = CChunk<C16>::get(c4, q);
+      if constexpr (ACC == ACC_FIX64)
+        atomicAdd(&qi[jc], to_fixed(td * static_cast<double>(v4[q])));
+      else if constexpr (ACC == ACC_F64)
+        atomicAdd(&qd[jc], static_cast<double>(tv * v4[q]));
+      else
+        atomicAdd(&qf[jc], tv * v4[q]);
+    }
+  };
+  auto dot4 = [&](const CCk& c4, const float (&v4)[4], DACC& dot) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float xv = vsh[CChunk<C16>::get(c4, q)];
+      if constexpr (kDot64)
+        dot += static_cast<double>(v4[q]) * static_cast<double>(xv);
+      else
+        dot = fmaf(v4[q], xv, dot);
+    }
+  };
+
+  for (int j = wave; j < nsl; j += NW) {
+    const uint32_t s0 = soff[j];
+    const int nk = static_cast<int>((soff[j + 1] - s0) >> 6);
+    const int r = t.row_begin + j * G + g;
+    const bool real = r < t.row_end;
+    float vv[K][4];
+    CCk cc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k < nk) {
+        const uint32_t c = s0 + static_cast<uint32_t>(k * 64 + lane);
+        ld(c, vv[k], cc[k]);
+      } else {
+        vv[k][0] = vv[k][1] = vv[k][2] = vv[k][3] = 0.0f;
+        cc[k] = CCk{};
+      }
+    }
+    float rw = 0.0f, aux = 0.0f;
+    if (real) {
+      if constexpr (MODE == PASS_RMATVEC) {
+        rw = a.tin[a.mat.rorig[rb + r]];
+      } else if constexpr (MODE != PASS_MATVEC) {
+        rw = a.mat.rw[rb + r];
+        if constexpr (kDot64)
+          aux = a.mat.rpres[rb + r];
+        else if (a.mat.rscale != nullptr)
+          aux = a.mat.rscale[rb + r];
+        else
+          aux = 1.0f;
+      }
+    }
+    float tv = rw;
+    if constexpr (kDot) {
+      DACC dot = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) dot4(cc[k], vv[k], dot);
+      for (int k = K; k < nk; ++k) {
+        const uint32_t c = s0 + static_cast<uint32_t>(k * 64 + lane);
+        float v4[4];
+        CCk c4;
+        ld(c, v4, c4);
+        dot4(c4, v4, dot);
+      }
+#pragma unroll
+      for (int off = L / 2; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+      if constexpr (MODE == PASS_MATVEC) {
+        if (real && (lane % L) == 0) a.tout[a.mat.rorig[rb + r]] = static_cast<float>(dot);
+      } else if constexpr (kDot64) {
+        const double res = real ? dot - static_cast<double>(aux) : 0.0;
+        const double wgt = static_cast<double>(rw);
+        if ((lane % L) == 0) objacc += wgt * res * res;
+        tv = static_cast<float>(wgt * res);
+      } else {
+        tv = rw * dot * aux * aux;
+      }
+    }
+    if constexpr (kScatter) {
+      const double td = static_cast<double>(tv) * fscale;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (k < nk) scatter4(cc[k], vv[k], tv, td);
+      for (int k = K; k < nk; ++k) {
+        const uint32_t c = s0 + static_cast<uint32_t>(k * 64 + lane);
+        float v4[4];
+        CCk c4;
+        ld(c, v4, c4);
+        scatter4(c4, v4, tv, td);
+      }
+    }
+  }
+}
+
+template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE, int FMT>
 __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float vmax_sh[NT / 64];
@@ -413,14 +567,26 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
   __syncthreads();
 
   double objacc = 0.0;
-  switch (t.lanes) {
-    case 1: pass_rows<VK, C16, 1, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 2: pass_rows<VK, C16, 2, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 4: pass_rows<VK, C16, 4, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 8: pass_rows<VK, C16, 8, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 16: pass_rows<VK, C16, 16, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    case 32: pass_rows<VK, C16, 32, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
-    default: pass_rows<VK, C16, 64, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+  if constexpr (FMT == FMT_SELL) {
+    switch (t.lanes) {
+      case 1: pass_slices<VK, C16, 1, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 2: pass_slices<VK, C16, 2, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 4: pass_slices<VK, C16, 4, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 8: pass_slices<VK, C16, 8, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 16: pass_slices<VK, C16, 16, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 32: pass_slices<VK, C16, 32, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      default: pass_slices<VK, C16, 64, MODE, ACC, NT>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    }
+  } else {
+    switch (t.lanes) {
+      case 1: pass_rows<VK, C16, 1, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 2: pass_rows<VK, C16, 2, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 4: pass_rows<VK, C16, 4, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 8: pass_rows<VK, C16, 8, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 16: pass_rows<VK, C16, 16, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      case 32: pass_rows<VK, C16, 32, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+      default: pass_rows<VK, C16, 64, MODE, ACC, NT, PIPE>(a, t, sc, vsh, qacc, fscale, objacc); break;
+    }
   }
 
   if constexpr (MODE == PASS_GRAD || MODE == PASS_OBJ) {
@@ -451,11 +617,11 @@ int pass_smem_bytes(int nmax, int acc) {
   return qoff + nmax * (acc == ACC_F32 ? 4 : 8);
 }
 
-template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE>
+template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE, int FMT>
 static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStream_t st, hipEvent_t e0,
                      hipEvent_t e1) {
   const int smem = pass_smem_bytes(a.nmax, ACC);
-  auto kern = k_pass<VK, C16, MODE, ACC, NT, PIPE>;
+  auto kern = k_pass<VK, C16, MODE, ACC, NT, PIPE, FMT>;
   static bool attr_done = false;
   if (!attr_done && smem > 65536) {
     // a refusal here leaves the launch to report whether the size fits; do not
@@ -474,17 +640,28 @@ static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStrea
 
 template <int VK, bool C16, int MODE, int ACC>
 static void launch_nt(const PassArgs& a, int tb, int tc, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  if constexpr (C16) {
+    // the sliced layout exists for 16-bit column indices (set-up keeps the
+    // chunk-row layout for patients with more than 65 535 spots)
+    if (a.mat.fmt == FMT_SELL) {
+      if (a.threads == 256)
+        launch_k<VK, C16, MODE, ACC, 256, false, FMT_SELL>(a, tb, tc, st, e0, e1);
+      else
+        launch_k<VK, C16, MODE, ACC, 512, false, FMT_SELL>(a, tb, tc, st, e0, e1);
+      return;
+    }
+  }
   const bool pipe = a.unroll == 2;
   if (a.threads == 256) {
     if (pipe)
-      launch_k<VK, C16, MODE, ACC, 256, true>(a, tb, tc, st, e0, e1);
+      launch_k<VK, C16, MODE, ACC, 256, true, FMT_CSR>(a, tb, tc, st, e0, e1);
     else
-      launch_k<VK, C16, MODE, ACC, 256, false>(a, tb, tc, st, e0, e1);
+      launch_k<VK, C16, MODE, ACC, 256, false, FMT_CSR>(a, tb, tc, st, e0, e1);
   } else {
     if (pipe)
-      launch_k<VK, C16, MODE, ACC, 512, true>(a, tb, tc, st, e0, e1);
+      launch_k<VK, C16, MODE, ACC, 512, true, FMT_CSR>(a, tb, tc, st, e0, e1);
     else
-      launch_k<VK, C16, MODE, ACC, 512, false>(a, tb, tc, st, e0, e1);
+      launch_k<VK, C16, MODE, ACC, 512, false, FMT_CSR>(a, tb, tc, st, e0, e1);
   }
 }
 

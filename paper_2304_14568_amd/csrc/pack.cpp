@@ -13,7 +13,10 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <numeric>
+#include <stdexcept>
 #include <system_error>
 #include <thread>
 
@@ -45,29 +48,127 @@ static int lanes_for(int64_t chunks) {
   return L;
 }
 
+// Rows of equal length sit in voxel order after the sort, so the rows that
+// one wave instruction handles are neighbouring voxels reached by nearly the
+// same spots: their scatters hit the same LDS column accumulators at once.
+// Within every class of equal length the rows are visited with a stride near
+// 0.618 of the class size (coprime to it), which spreads neighbours apart.
+static bool scramble_rows() {
+  const char* e = std::getenv("ADMMBB_ROW_ORDER");
+  return e == nullptr || e[0] != '0';
+}
+
+static void scramble_length_classes(const admm_csr& A, std::vector<int32_t>& order) {
+  std::vector<int32_t> tmp;
+  const size_t R = order.size();
+  size_t a = 0;
+  while (a < R) {
+    const int64_t len = A.row_ptr[order[a] + 1] - A.row_ptr[order[a]];
+    size_t b = a + 1;
+    while (b < R && A.row_ptr[order[b] + 1] - A.row_ptr[order[b]] == len) ++b;
+    const size_t c = b - a;
+    if (c > 2) {
+      size_t step = std::max<size_t>(1, static_cast<size_t>(0.6180339887498949 * static_cast<double>(c)));
+      while (std::gcd(step, c) != 1) ++step;
+      tmp.assign(order.begin() + static_cast<std::ptrdiff_t>(a), order.begin() + static_cast<std::ptrdiff_t>(b));
+      size_t q = 0;
+      for (size_t p = 0; p < c; ++p) {
+        order[a + p] = tmp[q];
+        q += step;
+        if (q >= c) q -= c;
+      }
+    }
+    a = b;
+  }
+}
+
 namespace {
 
 // What one thread produces for one (patient, scenario) pair besides the shared arrays.
 struct ScenOut {
   int64_t rows = 0, chunks = 0;        // nonempty rows, 4-element chunks after padding
   int64_t nnz_base = 0, row_base = 0, rp_base = 0;
-  std::vector<Tile> tiles;             // part_off filled at the merge
+  std::vector<Tile> tiles;             // part_off filled at the merge; slice_begin local
   std::vector<double> b, gdiag;        // n each
   double fzero = 0.0, fconst = 0.0;
+  std::vector<uint32_t> soff;          // sliced layout: slot offset of every slice, then a terminal entry
 };
+
+// The sliced copy of one scenario's rows (MatDev FMT_SELL), read from its
+// chunk-row copy: tile by tile, slices of G = 64 / L consecutive rows, each
+// row's chunk c at slot 64 (c / L) + g L + (c % L) of its slice, every slice
+// padded to the most chunk slots per lane any of its rows needs.
+template <class CT>
+void build_sliced(ScenOut& r, const uint32_t* rpp, const float* val, const CT* col, const uint16_t* lp,
+                  RawVec<float>& sval, RawVec<CT>& scol, RawVec<uint16_t>* slp) {
+  r.soff.clear();
+  uint64_t slots = 0;
+  for (Tile& t : r.tiles) {
+    const int L = t.lanes, G = 64 / L;
+    t.slice_begin = static_cast<int32_t>(r.soff.size());
+    for (int32_t rb = t.row_begin; rb < t.row_end; rb += G) {
+      const int32_t re = std::min(rb + G, t.row_end);
+      uint32_t K = 0;
+      for (int32_t q = rb; q < re; ++q) K = std::max<uint32_t>(K, (rpp[q + 1] - rpp[q] + L - 1) / L);
+      r.soff.push_back(static_cast<uint32_t>(slots));
+      slots += 64ull * K;
+    }
+  }
+  if (slots >= (1ull << 32)) throw std::length_error("sliced layout of one scenario exceeds 2^32 slots");
+  r.soff.push_back(static_cast<uint32_t>(slots));
+  sval.resize(static_cast<size_t>(slots) * 4);
+  scol.resize(static_cast<size_t>(slots) * 4);
+  if (slp) slp->resize(static_cast<size_t>(slots) * 8);  // records: four values, four columns
+  size_t sl = 0;
+  for (const Tile& t : r.tiles) {
+    const int L = t.lanes, G = 64 / L;
+    for (int32_t rb = t.row_begin; rb < t.row_end; rb += G, ++sl) {
+      const uint32_t s0 = r.soff[sl], K = (r.soff[sl + 1] - s0) / 64;
+      for (int g = 0; g < G; ++g) {
+        const int32_t q = rb + g;
+        const bool real = q < t.row_end;
+        const uint32_t ch = real ? rpp[q + 1] - rpp[q] : 0;
+        const size_t src = real ? static_cast<size_t>(rpp[q]) * 4 : 0;
+        const CT pad_col = real ? col[src + 4 * static_cast<size_t>(ch) - 1] : CT{0};
+        for (uint32_t c = 0; c < K * static_cast<uint32_t>(L); ++c) {
+          const size_t dst = (static_cast<size_t>(s0) + 64ull * (c / L) + static_cast<size_t>(g) * L + c % L) * 4;
+          if (c < ch) {
+            for (int e = 0; e < 4; ++e) {
+              sval[dst + e] = val[src + 4 * c + e];
+              scol[dst + e] = col[src + 4 * c + e];
+            }
+            if (slp)
+              for (int e = 0; e < 8; ++e) (*slp)[2 * dst + e] = lp[2 * (src + 4 * c) + e];
+          } else {
+            for (int e = 0; e < 4; ++e) {
+              sval[dst + e] = 0.0f;
+              scol[dst + e] = pad_col;
+              if (slp) {
+                (*slp)[2 * dst + e] = 0;
+                (*slp)[2 * dst + 4 + e] = static_cast<uint16_t>(pad_col);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
 
 template <class F>
 void parallel_for(int count, F&& fn) {
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
   const int nt = static_cast<int>(std::min<unsigned>(hw, static_cast<unsigned>(std::max(1, count))));
   std::atomic<int> next{0};
-  std::atomic<bool> oom{false};
+  std::atomic<bool> oom{false}, failed{false};
   auto worker = [&]() {
     for (int k = next++; k < count; k = next++) {
       try {
         fn(k);
       } catch (const std::bad_alloc&) {
         oom = true;
+      } catch (const std::exception&) {
+        failed = true;
       }
     }
   };
@@ -82,6 +183,7 @@ void parallel_for(int count, F&& fn) {
   worker();
   for (auto& t : th) t.join();
   if (oom) throw std::bad_alloc();
+  if (failed) throw std::length_error("a scenario exceeds the packed layout's 32-bit chunk offsets");
 }
 
 }  // namespace
@@ -161,9 +263,12 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
       P.col32.resize(ntot);
       std::fill(P.col32.begin() + tail, P.col32.end(), 0);
     }
+    // low-precision values with 16-bit columns: one 8 x 16-bit record per
+    // chunk (its four values, then its four columns)
+    const size_t lpw = P.col16_used ? 2 : 1;
     if (lp) {
-      P.val_lp.resize(ntot);
-      std::fill(P.val_lp.begin() + tail, P.val_lp.end(), uint16_t{0});
+      P.val_lp.resize(lpw * ntot);
+      std::fill(P.val_lp.begin() + lpw * tail, P.val_lp.end(), uint16_t{0});
       P.rscale.resize(static_cast<size_t>(row_base));
     }
     P.rw.resize(static_cast<size_t>(row_base));
@@ -171,6 +276,13 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
     P.rpres.resize(static_cast<size_t>(row_base));
     P.rorig.resize(static_cast<size_t>(row_base));
     P.rp.resize(static_cast<size_t>(rp_base));
+    // the sliced layout is built for 16-bit columns unless the chunk-row layout is asked for
+    const bool sell = P.col16_used && o.format != ADMM_FORMAT_CSR;
+    if (sell) {
+      P.sell_val.resize(static_cast<size_t>(J));
+      P.sell_col16.resize(static_cast<size_t>(J));
+      if (lp) P.sell_val_lp.resize(static_cast<size_t>(J));
+    }
 
     // fill every scenario's ranges
     parallel_for(J, [&](int k) {
@@ -199,6 +311,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         const int64_t len = A.row_ptr[i + 1] - A.row_ptr[i];
         if (len > 0) order[static_cast<size_t>(cnt[static_cast<size_t>(maxlen - len)]++)] = i;
       }
+      if (scramble_rows()) scramble_length_classes(A, order);
       for (int i = 0; i < m; ++i) {
         const double wp2 = c * pr.struct_weight[pr.struct_id[i]] * pr.presc[i] * pr.presc[i];
         r.fconst += wp2;
@@ -276,13 +389,24 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         for (int64_t t = 0; t < len; ++t) vd[t] = valp[t];
         for (int64_t t = len; t < len4; ++t) vd[t] = 0.0f;
         if (lp) {
-          uint16_t* ld = P.val_lp.data() + dst;
           const bool bf = o.precision == ADMM_PREC_BF16;
-          for (int64_t t = 0; t < len; ++t) {
-            const float qv = valp[t] / scl;
-            ld[t] = bf ? to_bf16_bits(qv) : to_f16_bits(qv);
+          if (lpw == 2) {
+            uint16_t* ld = P.val_lp.data() + 2 * dst;
+            const uint16_t* cd = P.col16.data() + dst;
+            for (int64_t t = 0; t < len4; ++t) {
+              const float qv = t < len ? valp[t] / scl : 0.0f;
+              const int64_t rec = 8 * (t / 4), e = t % 4;
+              ld[rec + e] = t < len ? (bf ? to_bf16_bits(qv) : to_f16_bits(qv)) : uint16_t{0};
+              ld[rec + 4 + e] = cd[t];
+            }
+          } else {
+            uint16_t* ld = P.val_lp.data() + dst;
+            for (int64_t t = 0; t < len; ++t) {
+              const float qv = valp[t] / scl;
+              ld[t] = bf ? to_bf16_bits(qv) : to_f16_bits(qv);
+            }
+            for (int64_t t = len; t < len4; ++t) ld[t] = 0;
           }
-          for (int64_t t = len; t < len4; ++t) ld[t] = 0;
         }
         for (int64_t t = 0; t < len; ++t) {
           const int32_t j = colp[t];
@@ -303,6 +427,14 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         t_chunks += len4 / 4;
       }
       if (r.rows > 0) close_tile(r.rows);
+      // the sliced copy of the same rows
+      if (sell) {
+        const float* v0 = P.val.data() + r.nnz_base;
+        const uint16_t* lp0 = lp ? P.val_lp.data() + 2 * r.nnz_base : nullptr;
+        RawVec<uint16_t>* slp = lp ? &P.sell_val_lp[static_cast<size_t>(k)] : nullptr;
+        build_sliced<uint16_t>(r, rpp, v0, P.col16.data() + r.nnz_base, lp0, P.sell_val[static_cast<size_t>(k)],
+                               P.sell_col16[static_cast<size_t>(k)], slp);
+      }
     });
 
     // merge in (patient, scenario) order
@@ -347,11 +479,16 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         for (int b = 0; b < sc.nblk; ++b) P.blk.push_back(Blk{k, b * kColBlock});
         blk_s += sc.nblk;
         sc.tile_begin = static_cast<int32_t>(P.tiles.size());
+        const int32_t slice_base = static_cast<int32_t>(P.soff.size());
         for (Tile t : r.tiles) {
           t.part_off = P.part_total;
+          t.slice_begin += slice_base;
           P.part_total += n;
           P.tiles.push_back(t);
         }
+        P.soff.insert(P.soff.end(), r.soff.begin(), r.soff.end());
+        sc.sell_base = P.sell_total;
+        P.sell_total += r.soff.empty() ? 0 : static_cast<int64_t>(r.soff.back());
         sc.tile_end = static_cast<int32_t>(P.tiles.size());
         P.scen.push_back(sc);
         P.scen_nnz.push_back(A.nnz);

@@ -134,6 +134,10 @@ admm_status validate_options(const admm_options* o, std::string* msg) {
     return fail(msg, ADMM_E_ARG, "pass_threads must be 0, 256 or 512");
   if (o->pass_unroll != 0 && o->pass_unroll != 1 && o->pass_unroll != 2)
     return fail(msg, ADMM_E_ARG, "pass_unroll must be 0, 1 or 2");
+  if (o->format < -1 || o->format > 1) return fail(msg, ADMM_E_ARG, "format must be -1, 0 or 1");
+  if (o->deterministic != 0 && o->deterministic != 1) return fail(msg, ADMM_E_ARG, "deterministic must be 0 or 1");
+  if (o->deterministic && o->lds_acc >= 0 && o->lds_acc != 2)
+    return fail(msg, ADMM_E_ARG, "deterministic needs lds_acc -1 or 2 (64-bit fixed-point column sums)");
   if (o->xupdate < -1 || o->xupdate > 1) return fail(msg, ADMM_E_ARG, "xupdate must be -1, 0 or 1");
   return ADMM_OK;
 }

@@ -45,11 +45,12 @@ def _per_entry(got, ref, scale):
     assert bad.size == 0, f"{bad.size} entries over bound; worst ratio {np.max(err / bound):.3g}"
 
 
-def test_full_size_products(full):
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+def test_full_size_products(full, fmt):
     import paper_2304_14568_amd as A
     P, W, _, _, _ = full
     rng = np.random.default_rng(21)
-    with A.Solver(P) as S:
+    with A.Solver(P, format=fmt) as S:
         rho = S.rho()
         for s in (0, 6, P.num_scen - 1):
             v = rng.uniform(0, 1, P.n).astype(np.float32)

@@ -51,11 +51,12 @@ def _spmv_check(got, ref, scale, tol=SPMV_TOL):
     assert bad.size == 0, f"{bad.size} entries over bound; worst ratio {np.max(err / bound):.3g}"
 
 
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
 @pytest.mark.parametrize("tile_nnz", [0, 4096])
-def test_matvec_rmatvec_parity(tiny, small, tile_nnz):
+def test_matvec_rmatvec_parity(tiny, small, tile_nnz, fmt):
     rng = np.random.default_rng(7)
     for P, W in ((tiny[0], tiny[1]), (small[0], small[1])):
-        with _solver(P, tile_nnz=tile_nnz) as S:
+        with _solver(P, tile_nnz=tile_nnz, format=fmt, xupdate="cg") as S:
             for s in range(P.num_scen):
                 v = rng.uniform(0, 1, P.n).astype(np.float32)
                 _spmv_check(S.matvec(v, s), wls.matvec(W, s, v), wls.matvec_abs(W, s, v))
@@ -63,11 +64,12 @@ def test_matvec_rmatvec_parity(tiny, small, tile_nnz):
                 _spmv_check(S.rmatvec(t, s), wls.rmatvec(W, s, t), wls.rmatvec_abs(W, s, t))
 
 
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
 @pytest.mark.parametrize("lds_acc", [0, 1, 2])
-def test_normal_apply_parity(small, lds_acc):
+def test_normal_apply_parity(small, lds_acc, fmt):
     P, W, _, _ = small
     rng = np.random.default_rng(8)
-    with _solver(P, lds_acc=lds_acc, tile_nnz=20000) as S:
+    with _solver(P, lds_acc=lds_acc, tile_nnz=20000, format=fmt, xupdate="cg") as S:
         rho = S.rho()
         for s in (0, 5, P.num_scen - 1):
             v = rng.normal(size=P.n).astype(np.float32)
@@ -76,10 +78,11 @@ def test_normal_apply_parity(small, lds_acc):
             _spmv_check(got, ref, wls.normal_apply_abs(W, s, v, rho))
 
 
-def test_gradient_objective_parity(tiny, small):
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+def test_gradient_objective_parity(tiny, small, fmt):
     rng = np.random.default_rng(9)
     for P, W, xs, _ in (tiny, small):
-        with _solver(P) as S:
+        with _solver(P, format=fmt) as S:
             for x in (xs, rng.uniform(0, 0.5, P.n)):
                 x32 = x.astype(np.float32).astype(np.float64)
                 g, f = S.gradient(x32)
@@ -94,10 +97,10 @@ def test_gradient_objective_parity(tiny, small):
                 assert abs(S.objective(x32) - fr) <= 1e-6 * fr
 
 
-@pytest.mark.parametrize("xupdate", ["cg", "dense"])
-def test_admm_solve_tiny(tiny, xupdate):
+@pytest.mark.parametrize("xupdate,fmt", [("cg", "csr"), ("cg", "sell"), ("dense", "auto")])
+def test_admm_solve_tiny(tiny, xupdate, fmt):
     P, W, xs, fs = tiny
-    with _solver(P, max_iter=3000, xupdate=xupdate) as S:
+    with _solver(P, max_iter=3000, xupdate=xupdate, format=fmt) as S:
         zs, info, st = S.solve()
         z = zs[0]
         assert st == 0, info
@@ -143,11 +146,12 @@ def test_pgd_gpu(tiny):
         assert abs(f - fs) <= 1e-4 * fs
 
 
-def test_fixed_point_pass_is_deterministic(small):
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+def test_fixed_point_pass_is_deterministic(small, fmt):
     """With 64-bit fixed-point column accumulators every sum in an iteration is
     order-independent or in a fixed order, so two runs agree bit for bit."""
     P = small[0]
-    with _solver(P, lds_acc=2, xupdate="cg") as S:
+    with _solver(P, lds_acc=2, xupdate="cg", format=fmt) as S:
         rng = np.random.default_rng(11)
         v = rng.normal(size=P.n).astype(np.float32)
         a = S.normal_apply(v, 3)
@@ -159,3 +163,23 @@ def test_fixed_point_pass_is_deterministic(small):
         S.iterate(6)
         z2 = S.z()
         assert np.array_equal(z1, z2)
+
+
+def test_layouts_agree_bit_for_bit(small):
+    """The chunk-row and the sliced layouts hold the same chunks of the same
+    rows, each lane takes the same chunks of its row and the row sums use the
+    same lane butterfly, and the column sums are exact (64-bit fixed point):
+    products and iterates agree bit for bit."""
+    P = small[0]
+    rng = np.random.default_rng(12)
+    v = rng.normal(size=P.n).astype(np.float32)
+    t = rng.normal(size=P.m).astype(np.float32)
+    out = {}
+    for fmt in ("csr", "sell"):
+        with _solver(P, lds_acc=2, xupdate="cg", format=fmt, deterministic=1) as S:
+            res = [S.matvec(v, 2), S.rmatvec(t, 2), S.normal_apply(v, 2)]
+            S.iterate(5)
+            res.append(S.z())
+            out[fmt] = res
+    for a, b in zip(out["csr"], out["sell"]):
+        assert np.array_equal(a, b)
