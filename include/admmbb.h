@@ -32,8 +32,10 @@
  *     ABI.  Negative codes mean the outputs were not written; ADMM_MAX_ITER
  *     means outputs are valid but the stopping test was not met.
  *     admm_last_error() gives a message for the last failure.
- *   - Input arrays are host memory, borrowed only for the duration of the call;
- *     the library copies and repacks what it needs into device memory it owns.
+ *   - Input arrays are host memory (or, for the CSR arrays, device memory when
+ *     admm_problem.mem_kind says so), borrowed only for the duration of the
+ *     call; the library copies and repacks what it needs into device memory it
+ *     owns.
  *   - Output arrays are caller-allocated host memory.
  *   - One context is used by one host thread at a time.  All device work of a
  *     context is issued on its stream (admm_options.stream; NULL means a
@@ -80,9 +82,20 @@ typedef struct {
   double prob;
 } admm_csr;
 
+/* Where the CSR arrays (row_ptr, col, val) of a problem live. */
+enum { ADMM_MEM_HOST = 0, ADMM_MEM_DEVICE = 1 };
+
 /* One patient: num_scen matrices with the same m, n.
  * w_i = struct_weight[struct_id[i]] >= 0 (weights constant per structure, Sec. 2.1);
- * presc[i] = p_i >= 0 (Sec. 2.1); lb/ub: n bounds each, NULL means 0 / +inf. */
+ * presc[i] = p_i >= 0 (Sec. 2.1); lb/ub: n bounds each, NULL means 0 / +inf.
+ * mem_kind: ADMM_MEM_HOST (0): every array is host memory.  ADMM_MEM_DEVICE
+ * (1): row_ptr, col and val of every scenario are device memory of the
+ * current device (for example tensors allocated by PyTorch on the GPU), read
+ * only during admm_setup / admm_setup_batch, which copy them to host staging
+ * buffers (synchronous copies, before any other device work) and then
+ * validate and pack them like host input; the caller keeps ownership.  A
+ * failed copy (for example nnz larger than the arrays) returns ADMM_E_HIP.  The admm_csr array, struct_id,
+ * struct_weight, presc, lb and ub are host memory in both cases. */
 typedef struct {
   int32_t m, n, num_scen;
   const admm_csr* A;
@@ -92,6 +105,7 @@ typedef struct {
   const double* presc;
   const double* lb;
   const double* ub;
+  int32_t mem_kind;
 } admm_problem;
 
 enum { ADMM_XUPDATE_AUTO = -1, ADMM_XUPDATE_CG = 0, ADMM_XUPDATE_DENSE = 1 };
@@ -359,7 +373,9 @@ const char* admm_last_error(const admm_ctx* ctx);
 
 void admm_destroy(admm_ctx* ctx);
 
-/* Host-only validation of a problem (the checks admm_setup performs first). */
+/* Host-only validation of a problem (the checks admm_setup performs first);
+ * a problem with mem_kind ADMM_MEM_DEVICE is refused with ADMM_E_ARG (its
+ * CSR arrays are not host memory). */
 admm_status admm_validate(const admm_problem* prob);
 
 /* ---- Learned warm start: a small network trained and run on the GPU ----

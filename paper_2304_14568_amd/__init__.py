@@ -51,7 +51,9 @@ class ProblemC(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("num_scen", ctypes.c_int32),
                 ("A", ctypes.POINTER(CsrC)), ("struct_id", ctypes.c_void_p), ("num_struct", ctypes.c_int32),
                 ("struct_weight", ctypes.c_void_p), ("presc", ctypes.c_void_p), ("lb", ctypes.c_void_p),
-                ("ub", ctypes.c_void_p)]
+                ("ub", ctypes.c_void_p), ("mem_kind", ctypes.c_int32)]
+
+MEM_HOST, MEM_DEVICE = 0, 1
 
 
 class OptionsC(ctypes.Structure):
@@ -167,11 +169,26 @@ class _ProblemHold:
         self.arrays = []
         A = prob.A
         self.csr = (CsrC * len(A))()
+        # CSR arrays given as GPU tensors (row_ptr int64, col int32, val float32,
+        # contiguous) are passed as device pointers (ADMM_MEM_DEVICE)
+        dev = [bool(getattr(x, "is_cuda", False)) for a in A for x in (a.row_ptr, a.col, a.val)]
+        if any(dev) and not all(dev):
+            raise ValueError("either every CSR array is a GPU tensor or none is")
+        self.mem_kind = MEM_DEVICE if dev and all(dev) else MEM_HOST
         for s, a in enumerate(A):
+            c = float(prob.prob[s]) if getattr(prob, "prob", None) is not None else 1.0
+            if self.mem_kind == MEM_DEVICE:
+                ptrs = []
+                for x, dt in ((a.row_ptr, "int64"), (a.col, "int32"), (a.val, "float32")):
+                    if str(x.dtype) != "torch." + dt or not x.is_contiguous():
+                        raise ValueError(f"device CSR arrays must be contiguous torch.{dt} tensors")
+                    self.arrays.append(x)
+                    ptrs.append(x.data_ptr())
+                self.csr[s] = CsrC(int(a.col.shape[0]), ptrs[0], ptrs[1], ptrs[2], c)
+                continue
             rp = self._keep(a.row_ptr, np.int64)
             col = self._keep(a.col, np.int32)
             val = self._keep(a.val, np.float32)
-            c = float(prob.prob[s]) if getattr(prob, "prob", None) is not None else 1.0
             self.csr[s] = CsrC(int(col.shape[0]), rp.ctypes.data, col.ctypes.data, val.ctypes.data, c)
         sid = self._keep(prob.struct_id, np.uint8)
         sw = self._keep(prob.struct_weight, np.float64)
@@ -179,7 +196,7 @@ class _ProblemHold:
         lb = None if getattr(prob, "lb", None) is None else self._keep(prob.lb, np.float64)
         ub = None if getattr(prob, "ub", None) is None else self._keep(prob.ub, np.float64)
         self.c = ProblemC(int(prob.m), int(prob.n), len(A), self.csr, sid.ctypes.data, int(sw.shape[0]),
-                          sw.ctypes.data, pr.ctypes.data, _ptr(lb), _ptr(ub))
+                          sw.ctypes.data, pr.ctypes.data, _ptr(lb), _ptr(ub), self.mem_kind)
 
     def _keep(self, a, dt):
         a = np.ascontiguousarray(a, dtype=dt)

@@ -787,6 +787,56 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
   std::string msg;
   admm_status st = validate_options(&o, &msg);
   if (st != ADMM_OK) return set_err(nullptr, st, msg);
+  // device-resident CSR arrays: host staging copies, then the host path
+  std::vector<admm_problem> staged;
+  std::vector<std::vector<admm_csr>> staged_csr;
+  std::vector<std::vector<int64_t>> st_rp;
+  std::vector<std::vector<int32_t>> st_col;
+  std::vector<std::vector<float>> st_val;
+  bool any_device = false;
+  for (int p = 0; p < num_patients; ++p) any_device = any_device || probs[p].mem_kind == ADMM_MEM_DEVICE;
+  if (any_device) {
+    try {
+      staged.assign(probs, probs + num_patients);
+      staged_csr.resize(num_patients);
+      for (int p = 0; p < num_patients; ++p) {
+        admm_problem& q = staged[p];
+        if (q.mem_kind != ADMM_MEM_DEVICE) continue;
+        if (!q.A || q.m <= 0 || q.num_scen <= 0)
+          return set_err(nullptr, ADMM_E_ARG, "patient " + std::to_string(p) + ": NULL A or non-positive sizes");
+        for (int s = 0; s < q.num_scen; ++s) {
+          const admm_csr& a = q.A[s];
+          if (a.nnz < 0 || !a.row_ptr || (a.nnz > 0 && (!a.col || !a.val)))
+            return set_err(nullptr, ADMM_E_ARG,
+                           "patient " + std::to_string(p) + " scenario " + std::to_string(s) + ": bad device CSR");
+          st_rp.emplace_back(static_cast<size_t>(q.m) + 1);
+          st_col.emplace_back(static_cast<size_t>(a.nnz));
+          st_val.emplace_back(static_cast<size_t>(a.nnz));
+          hipError_t e = hipMemcpy(st_rp.back().data(), a.row_ptr, sizeof(int64_t) * (q.m + 1), hipMemcpyDeviceToHost);
+          if (e == hipSuccess && a.nnz > 0)
+            e = hipMemcpy(st_col.back().data(), a.col, sizeof(int32_t) * a.nnz, hipMemcpyDeviceToHost);
+          if (e == hipSuccess && a.nnz > 0)
+            e = hipMemcpy(st_val.back().data(), a.val, sizeof(float) * a.nnz, hipMemcpyDeviceToHost);
+          if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(nullptr, ADMM_E_HIP,
+                           "patient " + std::to_string(p) + " scenario " + std::to_string(s) +
+                               ": copying the device CSR arrays failed: " + hipGetErrorString(e));
+          }
+          admm_csr h = a;
+          h.row_ptr = st_rp.back().data();
+          h.col = st_col.back().data();
+          h.val = st_val.back().data();
+          staged_csr[p].push_back(h);
+        }
+        q.A = staged_csr[p].data();
+        q.mem_kind = ADMM_MEM_HOST;
+      }
+    } catch (const std::bad_alloc&) {
+      return set_err(nullptr, ADMM_E_OOM, "host allocation failed while staging device input");
+    }
+    probs = staged.data();
+  }
   for (int p = 0; p < num_patients; ++p) {
     st = validate_problem(&probs[p], &msg);
     if (st != ADMM_OK) return set_err(nullptr, st, "patient " + std::to_string(p) + ": " + msg);

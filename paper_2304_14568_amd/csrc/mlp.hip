@@ -17,6 +17,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/admmbb.h"
@@ -69,6 +70,68 @@ __global__ void k_dense(const float* __restrict__ in, int nin, const float* __re
 #pragma unroll
   for (int r = 0; r < kRows; ++r)
     if (b0 + r < B) out[static_cast<int64_t>(b0 + r) * H + k] = acc[r] + bk;
+}
+
+// bf16 inference with the hidden activations stored as bf16:
+// out[b][k] = bf16(relu(sum_i in[b][i] W[k][i] + bias[k])), in given as fp32
+// (the network input) or as bf16 bits (a stored hidden layer).
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+__device__ __forceinline__ uint16_t bf16_bits(float x) { return static_cast<uint16_t>(__float_as_uint(bf16_round(x)) >> 16); }
+
+template <class TIN>
+__global__ void k_dense_bf16(const TIN* __restrict__ in, int nin, const float* __restrict__ W,
+                             const float* __restrict__ bias, uint16_t* __restrict__ out, int B, int H) {
+  extern __shared__ float xs[];  // kRows x nin
+  const int b0 = blockIdx.x * kRows;
+  for (int idx = threadIdx.x; idx < kRows * nin; idx += blockDim.x) {
+    const int r = idx / nin, i = idx % nin;
+    float v = 0.0f;
+    if (b0 + r < B) {
+      if constexpr (std::is_same<TIN, uint16_t>::value)
+        v = bf16_value(in[static_cast<int64_t>(b0 + r) * nin + i]);
+      else
+        v = in[static_cast<int64_t>(b0 + r) * nin + i];
+    }
+    xs[idx] = v;
+  }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k >= H) return;
+  float acc[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) acc[r] = 0.0f;
+  const float* wk = W + static_cast<int64_t>(k) * nin;
+  for (int i = 0; i < nin; ++i) {
+    const float w = wk[i];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) acc[r] = fmaf(xs[r * nin + i], w, acc[r]);
+  }
+  const float bk = bias[k];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+    if (b0 + r < B) out[static_cast<int64_t>(b0 + r) * H + k] = bf16_bits(fmaxf(acc[r] + bk, 0.0f));
+}
+
+// y_b = softplus(sum_k h2[b][k] w3[k] + b3) from the stored bf16 activations
+__global__ void k_head_bf16(const uint16_t* __restrict__ h2, const float* __restrict__ w3,
+                            const float* __restrict__ b3, float* __restrict__ z3, float* __restrict__ y, int B, int H) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  float acc = 0.0f;
+  const uint16_t* hr = h2 + static_cast<int64_t>(b) * H;
+  for (int k = 0; k < H; ++k) acc = fmaf(bf16_value(hr[k]), w3[k], acc);
+  const float z = acc + b3[0];
+  z3[b] = z;
+  y[b] = fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z)));
+}
+
+// pooled[k] = mean_b h2[b][k] over the stored bf16 activations (fixed order)
+__global__ void k_pool_bf16(const uint16_t* __restrict__ h2, float* __restrict__ pooled, int B, int H) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= H) return;
+  double s = 0.0;
+  for (int b = 0; b < B; ++b) s += bf16_value(h2[static_cast<int64_t>(b) * H + k]);
+  pooled[k] = static_cast<float>(s / B);
 }
 
 // y_b = softplus(sum_k relu(z2[b][k]) w3[k] + b3); z3 stored for the backward pass
@@ -237,6 +300,7 @@ struct admm_mlp {
   int cap = 0;  // rows the activation buffers hold
   float *X = nullptr, *t = nullptr, *z1 = nullptr, *z2 = nullptr, *z3 = nullptr, *y = nullptr, *dz3 = nullptr;
   float *dz2 = nullptr, *dz1 = nullptr, *pooled = nullptr;
+  uint16_t *h1b = nullptr, *h2b = nullptr;  // bf16 inference: hidden activations as bf16
   double* sc = nullptr;
   double* h_sc = nullptr;
   int64_t step = 0;
@@ -255,7 +319,10 @@ struct admm_mlp {
   void free_rows() {
     for (float* p : {X, t, z1, z2, z3, y, dz3, dz2, dz1, pooled})
       if (p) (void)hipFree(p);
+    for (uint16_t* p : {h1b, h2b})
+      if (p) (void)hipFree(p);
     X = t = z1 = z2 = z3 = y = dz3 = dz2 = dz1 = pooled = nullptr;
+    h1b = h2b = nullptr;
     cap = 0;
   }
   void ensure(int B) {
@@ -273,10 +340,23 @@ struct admm_mlp {
     a(&dz2, static_cast<int64_t>(c) * H);
     a(&dz1, static_cast<int64_t>(c) * H);
     a(&pooled, H);
+    ck(hipMalloc(reinterpret_cast<void**>(&h1b), sizeof(uint16_t) * static_cast<int64_t>(c) * H));
+    ck(hipMalloc(reinterpret_cast<void**>(&h2b), sizeof(uint16_t) * static_cast<int64_t>(c) * H));
     cap = c;
   }
   void forward(int B, int bf16) {
     const int nb = (B + kRows - 1) / kRows;
+    if (bf16) {
+      // inference only: the hidden layers are stored as bf16 (fp32 weights and accumulation)
+      hipLaunchKernelGGL(k_dense_bf16<float>, dim3(nb), dim3(H), sizeof(float) * kRows * F, stream, X, F, th + oW1,
+                         th + ob1, h1b, B, H);
+      hipLaunchKernelGGL(k_dense_bf16<uint16_t>, dim3(nb), dim3(H), sizeof(float) * kRows * H, stream, h1b, H,
+                         th + oW2, th + ob2, h2b, B, H);
+      hipLaunchKernelGGL(k_head_bf16, dim3((B + 255) / 256), dim3(256), 0, stream, h2b, th + ow3, th + ob3, z3, y, B,
+                         H);
+      hipLaunchKernelGGL(k_pool_bf16, dim3((H + 127) / 128), dim3(128), 0, stream, h2b, pooled, B, H);
+      return;
+    }
     hipLaunchKernelGGL(k_dense, dim3(nb), dim3(H), sizeof(float) * kRows * F, stream, X, F, th + oW1, th + ob1, z1, B,
                        H, 0, 0);
     hipLaunchKernelGGL(k_dense, dim3(nb), dim3(H), sizeof(float) * kRows * H, stream, z1, H, th + oW2, th + ob2, z2, B,

@@ -53,10 +53,6 @@ static int lanes_for(int64_t chunks) {
 // same spots: their scatters hit the same LDS column accumulators at once.
 // Within every class of equal length the rows are visited with a stride near
 // 0.618 of the class size (coprime to it), which spreads neighbours apart.
-static bool scramble_rows() {
-  const char* e = std::getenv("ADMMBB_ROW_ORDER");
-  return e == nullptr || e[0] != '0';
-}
 
 static void scramble_length_classes(const admm_csr& A, std::vector<int32_t>& order) {
   std::vector<int32_t> tmp;
@@ -311,7 +307,7 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         const int64_t len = A.row_ptr[i + 1] - A.row_ptr[i];
         if (len > 0) order[static_cast<size_t>(cnt[static_cast<size_t>(maxlen - len)]++)] = i;
       }
-      if (scramble_rows()) scramble_length_classes(A, order);
+      scramble_length_classes(A, order);
       for (int i = 0; i < m; ++i) {
         const double wp2 = c * pr.struct_weight[pr.struct_id[i]] * pr.presc[i] * pr.presc[i];
         r.fconst += wp2;

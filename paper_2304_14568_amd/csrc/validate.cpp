@@ -25,6 +25,10 @@ static admm_status fail(std::string* msg, admm_status st, const char* fmt, long 
 
 admm_status validate_problem(const admm_problem* p, std::string* msg) {
   if (!p) return fail(msg, ADMM_E_ARG, "problem is NULL");
+  if (p->mem_kind != ADMM_MEM_HOST && p->mem_kind != ADMM_MEM_DEVICE)
+    return fail(msg, ADMM_E_ARG, "mem_kind=%lld is neither ADMM_MEM_HOST nor ADMM_MEM_DEVICE", p->mem_kind);
+  if (p->mem_kind == ADMM_MEM_DEVICE)
+    return fail(msg, ADMM_E_ARG, "device-resident CSR arrays are staged to the host by admm_setup first");
   if (p->m <= 0 || p->n <= 0 || p->num_scen <= 0)
     return fail(msg, ADMM_E_ARG, "sizes must be positive (m=%lld n=%lld num_scen=%lld)", p->m, p->n, p->num_scen);
   if (p->n > 1 << 24) return fail(msg, ADMM_E_ARG, "n=%lld exceeds the supported 2^24 spots", p->n);

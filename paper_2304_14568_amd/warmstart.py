@@ -132,6 +132,44 @@ def solve_warm(S: Solver, P, ws: WarmStart, patient: int = 0, f_ref=None):
     return zs[patient], info[patient], dt, z0, rho, k_gap
 
 
+def solve_rho_only(S: Solver, P, ws: WarmStart, patient: int = 0, f_ref=None):
+    """Zero-initialised solve with only the network's penalty (the rho head);
+    the time includes features and inference.  Returns (z, info, seconds, rho,
+    iterations to 1e-5 of f_ref or None)."""
+    rho0 = S.rho(patient)
+    t0 = time.perf_counter()
+    _, rho = ws.predict(S, P, patient)
+    S.warm_start(patient, None, rho, dual_init=False)
+    zs, info, st = S.solve()
+    dt = time.perf_counter() - t0
+    k_gap = iters_to_gap(S, f_ref, patient=patient) if f_ref is not None else None
+    S.warm_start(patient, None, rho0, dual_init=False)
+    return zs[patient], info[patient], dt, rho, k_gap
+
+
+def compare(seeds, ws: WarmStart = None, stream=None):
+    """Zero-initialised, warm-started and penalty-only solves of the given
+    held-out patients: iterations to 1e-5 of the zero-initialised objective
+    and wall times (warm and penalty-only times include features and
+    inference).  Returns one dict per patient."""
+    import synth
+    ws = ws or WarmStart.load(stream=stream)
+    out = []
+    for seed in seeds:
+        P = synth.hn_full(seed)
+        with Solver(P, max_iter=2000, stream=stream) as S:
+            S.solve()  # first solve of a context: page in code and caches
+            _, i_ref, t_ref = solve_zero(S)
+            f_ref = i_ref["obj"]
+            k_ref = iters_to_gap(S, f_ref)
+            _, i_w, t_w, _, _, k_w = solve_warm(S, P, ws, f_ref=f_ref)
+            _, i_r, t_r, rho, k_r = solve_rho_only(S, P, ws, f_ref=f_ref)
+            out.append(dict(seed=seed, f_ref=f_ref, iters_zero=k_ref, iters_warm=k_w, iters_rho=k_r,
+                            s_zero=t_ref, s_warm=t_w, s_rho=t_r, f_warm=i_w["obj"], f_rho=i_r["obj"],
+                            rho_factor=rho / S.rho()))
+    return out
+
+
 # ----------------------------------------------------------------------------
 # dataset, training, evaluation
 # ----------------------------------------------------------------------------

@@ -138,7 +138,7 @@ def test_bad_options_rejected_before_device_work():
     P = _tiny()
     for kw in (dict(cg_max=0), dict(cg_max=65), dict(z_mode=2), dict(lds_acc=3), dict(pass_threads=128),
                dict(pass_unroll=3), dict(max_iter=-1), dict(check_every=0), dict(precision=7),
-               dict(xupdate=2)):
+               dict(xupdate=2), dict(format=2), dict(deterministic=2), dict(deterministic=1, lds_acc=1)):
         with pytest.raises(A.AdmmError) as e:
             A.Solver(P, **kw)
         assert e.value.code == -1, kw
@@ -186,3 +186,15 @@ def test_stream_probe_rejects_bad_arguments_before_device_work():
     assert A.lib.admm_stream_probe(1 << 30, 0, ctypes.byref(gbs)) == A.E_ARG    # no passes
     assert A.lib.admm_stream_probe(17 << 30, 1, ctypes.byref(gbs)) == A.E_ARG   # above 16 GiB
     assert A.lib.admm_stream_probe(1 << 30, 1, None) == A.E_ARG
+
+
+def test_memory_kind_checked_on_the_host():
+    """An unknown mem_kind is refused, and host-only validation refuses a
+    problem whose CSR arrays are device memory (it cannot read them)."""
+    A = _codes()
+    P = _tiny()
+    for kind in (1, 7):
+        h = A._ProblemHold(P)
+        h.c.mem_kind = kind
+        assert A.lib.admm_validate(h.c) == -1
+        assert "mem_kind" in A.last_setup_error() or "device" in A.last_setup_error()
