@@ -154,7 +154,8 @@ typedef struct {
                             their chunks interleaved so that a wave load reads 64 consecutive chunks
                             (16-bit column indices only, n <= 65535);
                           ADMM_FORMAT_AUTO (default): both are built and the set-up autotuner
-                            picks the faster for the CG pass (the sliced one when it does not run) */
+                            picks the faster for the CG pass (the chunk-row one when it does not
+                            run: dense x-update, or more than about 5 400 spots in a patient) */
   int32_t deterministic; /* 1: every sum of an iteration is exact or in a fixed order (64-bit
                           fixed-point column accumulators, lds_acc -1 or 2 required), so runs and
                           resumed runs repeat bit for bit; default 0 (the autotuner may pick fp64

@@ -417,7 +417,11 @@ struct admm_ctx {
         launch_xsym(f, d_c64, n_xjobs, stream);
       launch_xsym_reduce(f, d_x, n_rjobs, stream);
       launch_zres(va, NPB, stream);
-      launch_body_scalars(va, stream);
+      // residual norms and BB step beside the objective tiles at the new z,
+      // then the stopping test beside the dual update and the next right-hand
+      // sides: the iteration ends complete, with no head of its own next time
+      launch_dense_tail(f, va, n_fjobs, stream);
+      launch_dense_head(va, NB, stream);
       return;
     }
     for (int k = 0; k < opts.cg_max; ++k) {
@@ -449,7 +453,7 @@ struct admm_ctx {
     if (timing) throw HipError{hipErrorInvalidValue, "graph capture refused while timing events are enabled"};
     check(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-      launch_head(stop_enabled, 1);
+      if (!dense) launch_head(stop_enabled, 1);
       launch_body(stop_enabled, false);
     } catch (...) {
       hipGraph_t tmp = nullptr;
@@ -470,7 +474,7 @@ struct admm_ctx {
       if (!ge) capture(stop_enabled, &gr, &ge);
       check(hipGraphLaunch(ge, stream), "hipGraphLaunch");
     } else {
-      launch_head(stop_enabled, 1);
+      if (!dense) launch_head(stop_enabled, 1);
       launch_body(stop_enabled, timing);
     }
   }
@@ -493,13 +497,20 @@ struct admm_ctx {
   }
 
   // Run up to `k` iterations.  With stop_enabled the loop ends early once every
-  // patient has stopped.  A final head completes the bookkeeping of the last iteration.
+  // patient has stopped.  CG x-update: every iteration starts with its head (the
+  // gradient pass at z, completion of the previous iteration, CG set-up) and a
+  // final head completes the bookkeeping of the last one.  Dense x-update: each
+  // iteration ends complete (stopping test, dual update, next right-hand sides),
+  // and one head before the first iteration forms the right-hand sides and the
+  // objective of the state the run starts from (completing a pending dual
+  // update, as left by a checkpoint).
   void run(int k, int stop_enabled) {
     if (timing) {
       check(hipEventRecord(ev_a, stream), "hipEventRecord");
       pass_ms_sum = 0.0;
       pass_count = 0;
     }
+    if (dense) launch_head(stop_enabled, 0);
     const int every = std::max(1, opts.check_every);
     for (int it = 0; it < k; ++it) {
       one_iteration(stop_enabled);
@@ -514,7 +525,7 @@ struct admm_ctx {
         if (all) break;
       }
     }
-    launch_head(stop_enabled, 0);
+    if (!dense) launch_head(stop_enabled, 0);
     if (timing) {
       check(hipEventRecord(ev_b, stream), "hipEventRecord");
       check(hipEventSynchronize(ev_b), "hipEventSynchronize");
@@ -1039,8 +1050,9 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       decltype(H.sell_col16)().swap(H.sell_col16);
       decltype(H.sell_val_lp)().swap(H.sell_val_lp);
     }
-    // before the set-up autotuner decides: the sliced layout unless the chunk-row one is asked for
-    c->use_format(o.format == FMT_CSR ? FMT_CSR : FMT_SELL);
+    // the layout asked for; under AUTO the chunk-row layout until the set-up
+    // autotuner (CG x-update, LDS within 64 KiB) measures both
+    c->use_format(o.format == FMT_SELL ? FMT_SELL : FMT_CSR);
     clk.mark("sparse matrix upload");
     decltype(H.col16)().swap(H.col16);
     decltype(H.col32)().swap(H.col32);

@@ -31,6 +31,7 @@
 #include <cstdint>
 
 #include "internal.h"
+#include "scalars.h"
 
 namespace admmbb {
 
@@ -679,6 +680,60 @@ __device__ __forceinline__ void fobj_tile(const FactorArgs& f, const float* __re
   if (tid == 0) f.fpart[jb] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The five-launch dense iteration ends with two launches that each pair one
+// scalar workgroup with independent wide work:
+//   tail: workgroup 0 the residual norms, tolerances and BB step of every
+//         patient (body_scalars_run), the others the objective tiles at the
+//         new z;
+//   head: workgroup 0 the objective sums and stopping tests
+//         (head_scalars_run), the others the dual update y_s += tau d_s and
+//         the right-hand sides c_s of the next x-update, gated by dual_go,
+//         which the tail set (the stopping test of the same launch does not
+//         gate them: as in the six-launch order, the dual update of an
+//         iteration precedes its stopping test).
+__device__ __forceinline__ void dense_head_block(const VecArgs& a, int bi, int lane) {
+  const Blk bk = a.blk[bi];
+  const Scen sc = a.scen[bk.owner];
+  const int j = bk.col0 + lane;
+  const bool in = j < sc.n;
+  const int64_t vi = sc.vec_base + j;
+  float yv = 0.0f;
+  double dp = 0.0, bv = 0.0;
+  if (in) {
+    yv = a.y[vi];
+    dp = a.dprev[vi];
+    bv = a.b64[vi];
+  }
+  const Pat pt = a.pat[sc.patient];
+  const PatState* ps = a.ps + sc.patient;
+  const float zj = in ? a.z[pt.zvec_base + j] : 0.0f;
+  if (!ps->dual_go) return;
+  if (in) {
+    yv = static_cast<float>(static_cast<double>(yv) + ps->tau * dp);
+    a.y[vi] = yv;
+    a.c64[vi] = bv + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dense_tail(FactorArgs f, VecArgs a, int nfobj) {
+  const int b = static_cast<int>(blockIdx.x);
+  if (b == 0) {
+    body_scalars_run<true>(a);
+    return;
+  }
+  if (b - 1 < nfobj) fobj_tile(f, a.z, b - 1);
+}
+
+__global__ __launch_bounds__(256) void k_dense_head(VecArgs a, int nblk) {
+  const int b = static_cast<int>(blockIdx.x);
+  if (b == 0) {
+    head_scalars_run<true>(a, 0, 0);
+    return;
+  }
+  const int bi = 4 * (b - 1) + static_cast<int>(threadIdx.x >> 6);
+  if (bi < nblk) dense_head_block(a, bi, threadIdx.x & 63);
+}
+
 // The head of a dense iteration in one launch: workgroups [0, nfobj) take the
 // objective tiles, the rest four column blocks each of the pending dual update
 // and right-hand sides (the two parts are independent).
@@ -769,6 +824,14 @@ void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st) {
   if (njobs <= 0) return;
   hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(256), 0, st, f, x);
+}
+
+void launch_dense_tail(const FactorArgs& f, const VecArgs& a, int nfobj, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_tail, dim3(1 + nfobj), dim3(256), 0, st, f, a, nfobj);
+}
+
+void launch_dense_head(const VecArgs& a, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_head, dim3(1 + (nblk + 3) / 4), dim3(256), 0, st, a, nblk);
 }
 
 void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st) {

@@ -90,6 +90,7 @@ struct PatState {
   int32_t status;      // 0 running, 1 converged, 2 diverged (non-finite)
   int32_t cg_steps;    // CG steps (summed over scenarios) of the last iteration
   int32_t cg_total;
+  int32_t dual_go;     // dense five-launch iteration: the head launch applies the pending dual update
 };
 
 struct IterRecord {
@@ -288,6 +289,10 @@ void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st
                  hipEvent_t e1 = nullptr);
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st);
 void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st);
+// dense five-launch iteration: body scalars beside the objective tiles, then
+// the stopping test beside the dual update and right-hand sides
+void launch_dense_tail(const FactorArgs& f, const VecArgs& a, int nfobj, hipStream_t st);
+void launch_dense_head(const VecArgs& a, int nblk, hipStream_t st);
 void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
                       double* sums, uint32_t* maxkey, hipStream_t st);
 // Allocation-free dose statistics: device address of the fixed scratch array

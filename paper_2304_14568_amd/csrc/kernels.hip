@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "scalars.h"
 
 namespace admmbb {
 
@@ -40,95 +41,6 @@ struct ValT<VAL_F16> {
   using T = _Float16;
   static __device__ __forceinline__ float f(T v) { return static_cast<float>(v); }
 };
-
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-  return x;
-}
-
-// Sum of p[b * 8] for b < count by one wave: lane l adds entries l, l+64, ...
-// then a fixed butterfly; every lane returns the same total.
-__device__ __forceinline__ double wave_strided_sum(const double* p, int count) {
-  double s = 0.0;
-  for (int b = threadIdx.x & 63; b < count; b += 64) s += p[static_cast<int64_t>(b) * 8];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  return s;
-}
-
-// Deterministic block sum of NV doubles over NT threads; result valid in thread 0.
-template <int NV, int NT = kThreads>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
-  constexpr int NW = NT / 64;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double acc = 0.0;
-      for (int w = 0; w < NW; ++w) acc += sh[w * NV + k];
-      v[k] = acc;
-    }
-  }
-  __syncthreads();
-}
-
-// Block sum of a strided list: thread i adds items i, i+256, ... in order,
-// then a fixed tree.  Deterministic for a given count.
-template <class F>
-__device__ __forceinline__ double block_list_sum(int count, F item, double* sh) {
-  double v[1] = {0.0};
-  // four independent loads in flight, added in the same order as one at a time
-  int i = threadIdx.x;
-  for (; i + 3 * kThreads < count; i += 4 * kThreads) {
-    const double e0 = item(i), e1 = item(i + kThreads), e2 = item(i + 2 * kThreads), e3 = item(i + 3 * kThreads);
-    v[0] += e0;
-    v[0] += e1;
-    v[0] += e2;
-    v[0] += e3;
-  }
-  for (; i < count; i += kThreads) v[0] += item(i);
-  block_sum<1>(v, sh);
-  return v[0];
-}
-
-// Two strided lists at once, so that their loads overlap; each is added in
-// the order block_list_sum uses, and block_sum reduces the two independently,
-// so either result equals its own block_list_sum.  Valid in thread 0.
-template <class F1, class F2>
-__device__ __forceinline__ void block_list_sum2(int n1, F1 item1, int n2, F2 item2, double* sh, double& s1,
-                                                double& s2) {
-  double v[2] = {0.0, 0.0};
-  int i = threadIdx.x;
-  for (; i + 3 * kThreads < n1; i += 4 * kThreads) {
-    const double e0 = item1(i), e1 = item1(i + kThreads), e2 = item1(i + 2 * kThreads), e3 = item1(i + 3 * kThreads);
-    v[0] += e0;
-    v[0] += e1;
-    v[0] += e2;
-    v[0] += e3;
-  }
-  for (; i < n1; i += kThreads) v[0] += item1(i);
-  i = threadIdx.x;
-  for (; i + 3 * kThreads < n2; i += 4 * kThreads) {
-    const double e0 = item2(i), e1 = item2(i + kThreads), e2 = item2(i + 2 * kThreads), e3 = item2(i + 3 * kThreads);
-    v[1] += e0;
-    v[1] += e1;
-    v[1] += e2;
-    v[1] += e3;
-  }
-  for (; i < n2; i += kThreads) v[1] += item2(i);
-  block_sum<2>(v, sh);
-  s1 = v[0];
-  s2 = v[1];
-}
 
 // ---------------------------------------------------------------------------
 // the fused pass
@@ -816,81 +728,7 @@ void launch_reduce(int mode, const VecArgs& a, int blk_begin, int nblk, hipStrea
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void k_head_scalars(VecArgs a, int nscen, int cg_setup) {
-  __shared__ double sh[4 * 2];
-  const AlgoParams& P = a.prm;
-  for (int p = 0; p < P.num_pat; ++p) {
-    const Pat pt = a.pat[p];
-    PatState* ps = a.ps + p;
-    const int stopped = ps->stopped;  // read beside the partial sums
-    // objective partials and the blocks' sums of squares of y, loaded together
-    const int sb0 = pt.sblk_begin;
-    auto yitem = [&](int i) { return a.bpart[(int64_t)(sb0 + i) * 8 + 2]; };
-    double fs = 0.0, yy = 0.0;
-    if (a.fpart != nullptr)
-      block_list_sum2(pt.fobj_end - pt.fobj_begin, [&](int i) { return a.fpart[pt.fobj_begin + i]; },
-                      pt.sblk_end - sb0, yitem, sh, fs, yy);
-    else
-      block_list_sum2(pt.tile_end - pt.tile_begin, [&](int i) { return a.objpart[pt.tile_begin + i]; },
-                      pt.sblk_end - sb0, yitem, sh, fs, yy);
-    if (stopped) continue;  // uniform
-    const double f = (a.fpart != nullptr ? pt.fconst : pt.fzero) + fs;
-    if (threadIdx.x == 0) {
-      ps->f_cur = f;
-      if (ps->pending) {
-        const int N = pt.num_scen;
-        const double base = P.eps_abs * sqrt(static_cast<double>(N) * pt.n);
-        ps->eps_dual = base + P.eps_rel * sqrt(yy);
-        const int k = ps->iter;  // iterations completed, >= 1
-        if (a.trace != nullptr && k - 1 < P.trace_cap) {
-          IterRecord rec;
-          rec.iter = k;
-          rec.cg_steps = ps->cg_steps;
-          rec.obj = f;
-          rec.r_prim = ps->r_prim;
-          rec.r_dual = ps->r_dual;
-          rec.eps_prim = ps->eps_prim;
-          rec.eps_dual = ps->eps_dual;
-          rec.tau = ps->tau;
-          a.trace[static_cast<int64_t>(p) * P.trace_cap + (k - 1)] = rec;
-        }
-        if (!isfinite(f) || !isfinite(ps->r_prim)) {
-          ps->stopped = 1;
-          ps->status = 2;
-        } else if (P.stop_enabled) {
-          bool obj_ok = true;
-          if (P.obj_rel_tol > 0.0) obj_ok = (k >= 2) && fabs(f - ps->f_prev) <= P.obj_rel_tol * fabs(ps->f_prev);
-          if (ps->r_prim <= ps->eps_prim && ps->r_dual <= ps->eps_dual && obj_ok) {
-            ps->stopped = 1;
-            ps->status = 1;
-          }
-        }
-        ps->pending = 0;
-      }
-      ps->f_prev = f;
-    }
-    __syncthreads();
-  }
-  if (!cg_setup) return;
-  // per-scenario CG set-up: one thread per scenario, fixed-order sums over its blocks
-  for (int g = threadIdx.x; g < nscen; g += kThreads) {
-    const Scen sc = a.scen[g];
-    const PatState* ps = a.ps + sc.patient;
-    double rz0 = 0.0, cc = 0.0;
-    for (int b = 0; b < sc.nblk; ++b) {
-      rz0 += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 0];
-      cc += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 1];
-    }
-    double eta = P.eta_factor;
-    if (ps->iter > 0) {
-      const double rel = ps->r_prim / fmax(ps->xnorm, 1e-30);
-      eta = fmax(P.eta_floor, P.eta_factor * fmin(1.0, rel));
-    }
-    const double tol2 = eta * eta * cc;
-    a.tol2[g] = tol2;
-    a.rz[g * kRing + 0] = rz0;
-    a.act[g * kRing + 0] = (!ps->stopped && rz0 > tol2 && rz0 > 0.0) ? 1 : 0;
-    a.cgcount[g] = 0;
-  }
+  head_scalars_run<false>(a, nscen, cg_setup);
 }
 
 void launch_head_scalars(const VecArgs& a, int nscen, int cg_setup, hipStream_t st) {
@@ -980,7 +818,7 @@ constexpr int kZCols = 16;
 __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   __shared__ double sacc[kThreads / kZCols][kZCols];
   __shared__ float zsh[kZCols];
-  __shared__ double sred[4][6];
+  __shared__ double sred[4][8];
   const int bi4 = static_cast<int>(blockIdx.x);
   const Blk bk = a.pblk[bi4 >> 2];
   const int p = bk.owner;
@@ -1003,7 +841,8 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   if (stopped) return;  // the whole workgroup: one patient
   sacc[grp][col] = acc;
   __syncthreads();
-  double v[6] = {0, 0, 0, 0, 0, 0};  // ||dz||^2, ||z||^2, ||d||^2, <dd,d_prev>, ||dd||^2, ||x||^2
+  // ||dz||^2, ||z||^2, ||d||^2, <dd,d_prev>, ||dd||^2, ||x||^2, <y,d>, ||y||^2
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (grp == 0) {
     float znf = 0.0f;
     if (valid) {
@@ -1026,6 +865,7 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
     for (int s = grp; s < pt.num_scen; s += kGroups) {
       const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
       const double xv = static_cast<double>(a.x[vi]);
+      const double yv = static_cast<double>(a.y[vi]);
       const double d = xv - znd;
       const double dp = a.dprev[vi];
       const double dd = d - dp;
@@ -1033,17 +873,19 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
       v[3] += dd * dp;
       v[4] += dd * dd;
       v[5] += xv * xv;
+      v[6] += yv * d;
+      v[7] += yv * yv;
       a.dprev[vi] = d;
     }
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  for (int k = 0; k < 8; ++k) v[k] = wave_sum(v[k]);
   if ((tid & 63) == 0)
-    for (int k = 0; k < 6; ++k) sred[tid >> 6][k] = v[k];
+    for (int k = 0; k < 8; ++k) sred[tid >> 6][k] = v[k];
   __syncthreads();
   if (tid == 0) {
     double* bp = a.bpartp + static_cast<int64_t>(bi4) * 8;
-    for (int k = 0; k < 6; ++k) bp[k] = (sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]);
+    for (int k = 0; k < 8; ++k) bp[k] = (sred[0][k] + sred[1][k]) + (sred[2][k] + sred[3][k]);
   }
 }
 
@@ -1052,54 +894,7 @@ void launch_zres(const VecArgs& a, int npblk, hipStream_t st) {
 }
 
 // Residual norms, tolerances and the Barzilai-Borwein dual step per patient.
-__global__ __launch_bounds__(kThreads) void k_body_scalars(VecArgs a) {
-  __shared__ double sh[4 * 6];
-  const AlgoParams& P = a.prm;
-  for (int p = 0; p < P.num_pat; ++p) {
-    const Pat pt = a.pat[p];
-    PatState* ps = a.ps + p;
-    const int stopped = ps->stopped;  // read beside the partial sums
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < 4 * pt.nblk; b += kThreads)
-      for (int k = 0; k < 6; ++k) v[k] += a.bpartp[(int64_t)(4 * pt.blk_begin + b) * 8 + k];
-    // thread 0's inputs from the patient's state, requested before the reduction
-    int cg = 0, iter0 = 0, cgt0 = 0;
-    double rho = 0.0, tau0 = 0.0;
-    if (threadIdx.x == 0) {
-      for (int s = 0; s < pt.num_scen; ++s) cg += a.cgcount[pt.scen_begin + s];
-      rho = ps->rho;
-      tau0 = ps->tau;
-      iter0 = ps->iter;
-      cgt0 = ps->cg_total;
-    }
-    if (stopped) continue;  // uniform
-    block_sum<6>(v, sh);
-    if (threadIdx.x == 0) {
-      const int N = pt.num_scen;
-      const double rp = sqrt(v[2]);
-      const double rd = sqrt(static_cast<double>(N)) * rho * sqrt(v[0]);
-      double tau = rho;
-      if (P.bb && iter0 >= 1 && v[4] > 0.0) {
-        // dy = y^k - y^{k-1} = tau_{k-1} d^k, so <dd, dy> = tau_{k-1} <dd, d^k>
-        const double beta = -tau0 * v[3] / v[4];
-        if (isfinite(beta) && beta > 0.0) tau = beta;
-      }
-      if (P.bb_clamp > 0.0) tau = fmin(fmax(tau, rho / P.bb_clamp), rho * P.bb_clamp);
-      const double base = P.eps_abs * sqrt(static_cast<double>(N) * pt.n);
-      ps->xnorm = sqrt(v[5]);
-      ps->znorm = sqrt(v[1]);
-      ps->eps_prim = base + P.eps_rel * fmax(ps->xnorm, sqrt(static_cast<double>(N)) * ps->znorm);
-      ps->r_prim = rp;
-      ps->r_dual = rd;
-      ps->tau = tau;
-      ps->cg_steps = cg;
-      ps->cg_total = cgt0 + cg;
-      ps->iter = iter0 + 1;
-      ps->pending = 1;
-    }
-    __syncthreads();
-  }
-}
+__global__ __launch_bounds__(kThreads) void k_body_scalars(VecArgs a) { body_scalars_run<false>(a); }
 
 void launch_body_scalars(const VecArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_body_scalars, dim3(1), dim3(kThreads), 0, st, a);

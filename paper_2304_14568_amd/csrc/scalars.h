@@ -1,0 +1,250 @@
+// Device-side reductions and the per-patient scalar steps of an ADMM-BB
+// iteration (objective sum and stopping test; residual norms, tolerances and
+// the Barzilai-Borwein dual step), shared by the launch sequences of the CG
+// and the dense x-updates.  Every sum is in a fixed order.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace admmbb {
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// Sum of p[b * 8] for b < count by one wave: lane l adds entries l, l+64, ...
+// then a fixed butterfly; every lane returns the same total.
+__device__ __forceinline__ double wave_strided_sum(const double* p, int count) {
+  double s = 0.0;
+  for (int b = threadIdx.x & 63; b < count; b += 64) s += p[static_cast<int64_t>(b) * 8];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return s;
+}
+
+// Deterministic block sum of NV doubles over NT threads; result valid in thread 0.
+template <int NV, int NT = kThreads>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
+  constexpr int NW = NT / 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double acc = 0.0;
+      for (int w = 0; w < NW; ++w) acc += sh[w * NV + k];
+      v[k] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Block sum of a strided list: thread i adds items i, i+256, ... in order,
+// then a fixed tree.  Deterministic for a given count.
+template <class F>
+__device__ __forceinline__ double block_list_sum(int count, F item, double* sh) {
+  double v[1] = {0.0};
+  // four independent loads in flight, added in the same order as one at a time
+  int i = threadIdx.x;
+  for (; i + 3 * kThreads < count; i += 4 * kThreads) {
+    const double e0 = item(i), e1 = item(i + kThreads), e2 = item(i + 2 * kThreads), e3 = item(i + 3 * kThreads);
+    v[0] += e0;
+    v[0] += e1;
+    v[0] += e2;
+    v[0] += e3;
+  }
+  for (; i < count; i += kThreads) v[0] += item(i);
+  block_sum<1>(v, sh);
+  return v[0];
+}
+
+// Two strided lists at once, so that their loads overlap; each is added in
+// the order block_list_sum uses, and block_sum reduces the two independently,
+// so either result equals its own block_list_sum.  Valid in thread 0.
+template <class F1, class F2>
+__device__ __forceinline__ void block_list_sum2(int n1, F1 item1, int n2, F2 item2, double* sh, double& s1,
+                                                double& s2) {
+  double v[2] = {0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 3 * kThreads < n1; i += 4 * kThreads) {
+    const double e0 = item1(i), e1 = item1(i + kThreads), e2 = item1(i + 2 * kThreads), e3 = item1(i + 3 * kThreads);
+    v[0] += e0;
+    v[0] += e1;
+    v[0] += e2;
+    v[0] += e3;
+  }
+  for (; i < n1; i += kThreads) v[0] += item1(i);
+  i = threadIdx.x;
+  for (; i + 3 * kThreads < n2; i += 4 * kThreads) {
+    const double e0 = item2(i), e1 = item2(i + kThreads), e2 = item2(i + 2 * kThreads), e3 = item2(i + 3 * kThreads);
+    v[1] += e0;
+    v[1] += e1;
+    v[1] += e2;
+    v[1] += e3;
+  }
+  for (; i < n2; i += kThreads) v[1] += item2(i);
+  block_sum<2>(v, sh);
+  s1 = v[0];
+  s2 = v[1];
+}
+
+// Objective at z, completion of the previous iteration (dual tolerance, trace
+// record, stopping test) and, with cg_setup, the CG set-up; one workgroup of
+// kThreads threads.  DENSE: the dual tolerance was already formed by
+// body_scalars_run from the updated duals' norm, and no CG set-up follows.
+template <bool DENSE>
+__device__ __forceinline__ void head_scalars_run(const VecArgs& a, int nscen, int cg_setup) {
+  __shared__ double sh[4 * 2];
+  const AlgoParams& P = a.prm;
+  for (int p = 0; p < P.num_pat; ++p) {
+    const Pat pt = a.pat[p];
+    PatState* ps = a.ps + p;
+    const int stopped = ps->stopped;  // read beside the partial sums
+    // objective partials and the blocks' sums of squares of y, loaded together
+    const int sb0 = pt.sblk_begin;
+    auto yitem = [&](int i) { return a.bpart[(int64_t)(sb0 + i) * 8 + 2]; };
+    double fs = 0.0, yy = 0.0;
+    if (a.fpart != nullptr)
+      block_list_sum2(pt.fobj_end - pt.fobj_begin, [&](int i) { return a.fpart[pt.fobj_begin + i]; },
+                      DENSE ? 0 : pt.sblk_end - sb0, yitem, sh, fs, yy);
+    else
+      block_list_sum2(pt.tile_end - pt.tile_begin, [&](int i) { return a.objpart[pt.tile_begin + i]; },
+                      pt.sblk_end - sb0, yitem, sh, fs, yy);
+    if (stopped) continue;  // uniform
+    const double f = (a.fpart != nullptr ? pt.fconst : pt.fzero) + fs;
+    if (threadIdx.x == 0) {
+      ps->f_cur = f;
+      if (ps->pending) {
+        const int N = pt.num_scen;
+        if constexpr (!DENSE) {
+          const double base = P.eps_abs * sqrt(static_cast<double>(N) * pt.n);
+          ps->eps_dual = base + P.eps_rel * sqrt(yy);
+        }
+        const int k = ps->iter;  // iterations completed, >= 1
+        if (a.trace != nullptr && k - 1 < P.trace_cap) {
+          IterRecord rec;
+          rec.iter = k;
+          rec.cg_steps = ps->cg_steps;
+          rec.obj = f;
+          rec.r_prim = ps->r_prim;
+          rec.r_dual = ps->r_dual;
+          rec.eps_prim = ps->eps_prim;
+          rec.eps_dual = ps->eps_dual;
+          rec.tau = ps->tau;
+          a.trace[static_cast<int64_t>(p) * P.trace_cap + (k - 1)] = rec;
+        }
+        if (!isfinite(f) || !isfinite(ps->r_prim)) {
+          ps->stopped = 1;
+          ps->status = 2;
+        } else if (P.stop_enabled) {
+          bool obj_ok = true;
+          if (P.obj_rel_tol > 0.0) obj_ok = (k >= 2) && fabs(f - ps->f_prev) <= P.obj_rel_tol * fabs(ps->f_prev);
+          if (ps->r_prim <= ps->eps_prim && ps->r_dual <= ps->eps_dual && obj_ok) {
+            ps->stopped = 1;
+            ps->status = 1;
+          }
+        }
+        ps->pending = 0;
+      }
+      ps->f_prev = f;
+    }
+    __syncthreads();
+  }
+  if (DENSE || !cg_setup) return;
+  // per-scenario CG set-up: one thread per scenario, fixed-order sums over its blocks
+  for (int g = threadIdx.x; g < nscen; g += kThreads) {
+    const Scen sc = a.scen[g];
+    const PatState* ps = a.ps + sc.patient;
+    double rz0 = 0.0, cc = 0.0;
+    for (int b = 0; b < sc.nblk; ++b) {
+      rz0 += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 0];
+      cc += a.bpart[(int64_t)(sc.blk_begin + b) * 8 + 1];
+    }
+    double eta = P.eta_factor;
+    if (ps->iter > 0) {
+      const double rel = ps->r_prim / fmax(ps->xnorm, 1e-30);
+      eta = fmax(P.eta_floor, P.eta_factor * fmin(1.0, rel));
+    }
+    const double tol2 = eta * eta * cc;
+    a.tol2[g] = tol2;
+    a.rz[g * kRing + 0] = rz0;
+    a.act[g * kRing + 0] = (!ps->stopped && rz0 > tol2 && rz0 > 0.0) ? 1 : 0;
+    a.cgcount[g] = 0;
+  }
+}
+
+// Residual norms, tolerances and the Barzilai-Borwein dual step per patient,
+// from the z-update's partial sums; one workgroup of kThreads threads.
+// DENSE: also the dual tolerance, from the norm of the duals after the update
+// y + tau d that the next launch applies (||y||^2 + 2 tau <y, d> + tau^2 ||d||^2
+// from the same partial sums), and the flag dual_go that tells that launch
+// whether to apply it (0 for a patient that has stopped).
+template <bool DENSE>
+__device__ __forceinline__ void body_scalars_run(const VecArgs& a) {
+  __shared__ double sh[4 * 8];
+  const AlgoParams& P = a.prm;
+  for (int p = 0; p < P.num_pat; ++p) {
+    const Pat pt = a.pat[p];
+    PatState* ps = a.ps + p;
+    const int stopped = ps->stopped;  // read beside the partial sums
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < 4 * pt.nblk; b += kThreads)
+      for (int k = 0; k < (DENSE ? 8 : 6); ++k) v[k] += a.bpartp[(int64_t)(4 * pt.blk_begin + b) * 8 + k];
+    // thread 0's inputs from the patient's state, requested before the reduction
+    int cg = 0, iter0 = 0, cgt0 = 0;
+    double rho = 0.0, tau0 = 0.0;
+    if (threadIdx.x == 0) {
+      for (int s = 0; s < pt.num_scen; ++s) cg += a.cgcount[pt.scen_begin + s];
+      rho = ps->rho;
+      tau0 = ps->tau;
+      iter0 = ps->iter;
+      cgt0 = ps->cg_total;
+    }
+    if (stopped) {  // uniform
+      if (DENSE && threadIdx.x == 0) ps->dual_go = 0;
+      continue;
+    }
+    block_sum<8>(v, sh);
+    if (threadIdx.x == 0) {
+      const int N = pt.num_scen;
+      const double rp = sqrt(v[2]);
+      const double rd = sqrt(static_cast<double>(N)) * rho * sqrt(v[0]);
+      double tau = rho;
+      if (P.bb && iter0 >= 1 && v[4] > 0.0) {
+        // dy = y^k - y^{k-1} = tau_{k-1} d^k, so <dd, dy> = tau_{k-1} <dd, d^k>
+        const double beta = -tau0 * v[3] / v[4];
+        if (isfinite(beta) && beta > 0.0) tau = beta;
+      }
+      if (P.bb_clamp > 0.0) tau = fmin(fmax(tau, rho / P.bb_clamp), rho * P.bb_clamp);
+      const double base = P.eps_abs * sqrt(static_cast<double>(N) * pt.n);
+      ps->xnorm = sqrt(v[5]);
+      ps->znorm = sqrt(v[1]);
+      ps->eps_prim = base + P.eps_rel * fmax(ps->xnorm, sqrt(static_cast<double>(N)) * ps->znorm);
+      ps->r_prim = rp;
+      ps->r_dual = rd;
+      ps->tau = tau;
+      ps->cg_steps = cg;
+      ps->cg_total = cgt0 + cg;
+      ps->iter = iter0 + 1;
+      ps->pending = 1;
+      if constexpr (DENSE) {
+        const double yy = fmax(0.0, v[7] + 2.0 * tau * v[6] + tau * tau * v[2]);
+        ps->eps_dual = base + P.eps_rel * sqrt(yy);
+        ps->dual_go = 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace admmbb

@@ -224,6 +224,27 @@ def cmd_batch(args):
     res["cross_check"] = checks
     res["sum_single_fp32_cg_solve_s"] = float(sum(c["single_fp32_cg_solve_s"] for c in checks))
     res["batched_over_single_fp32_time_ratio"] = res["solve_s"] / res["sum_single_fp32_cg_solve_s"]
+    # time to 1e-5: the first iteration at which every patient's objective is
+    # within 1e-5 of its single-patient fp32 solve, then that many iterations
+    # timed from zero
+    S = Solver(Ps, xupdate=args.xupdate, precision=args.precision, max_iter=args.max_iter, stream=stream)
+    S.solve()
+    ks = []
+    for k in range(len(Ps)):
+        f_ref = checks[k]["obj_single_fp32"]
+        ks.append(next((t["iter"] for t in S.trace(k) if (t["obj"] - f_ref) <= 1e-5 * abs(f_ref)), None))
+    if all(v is not None for v in ks):
+        K = max(ks)
+        S.reset()
+        _sync()
+        t0 = time.perf_counter()
+        S.iterate(K)
+        _sync()
+        res["iters_to_1e-5"] = ks
+        res["time_to_1e-5_s"] = time.perf_counter() - t0
+        print(f"[batch] every patient within 1e-5 of its fp32 solve after {K} iterations: "
+              f"{res['time_to_1e-5_s']:.2f} s", flush=True)
+    S.close()
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)
