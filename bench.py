@@ -30,11 +30,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-5 obj (s) & ADMM iters/s, 13 scen.; SpMV HBM GB/s vs ~8 TB/s"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per k_xsym launch on this workload, from rocprofv3 FETCH_SIZE (x 2.0) and
-# WRITE_SIZE (x 1.0) runs (profiles/k_xsym_hn13_fp32.md); valid only while the
-# kernel's source text is the one they were taken with
-XSYM_TRAFFIC = {"source_sha256_16": "d0e8de26be9e4366", "fetch_bytes": 119914.3 * 1024 * 2.0,
-                "write_bytes": 14358.5 * 1024 * 1.0}
+# HBM bytes per launch of the dense x-update kernel (k_dense_x: the packed
+# tiles of every inverse, beside the previous iteration's stopping test) on
+# this workload, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0) runs
+# (profiles/k_dense_x_hn13_fp32.md); valid only while the text of the tile
+# function and of the kernel is the one they were taken with (the two 16-digit
+# hashes of kernel_source_hash)
+XSYM_TRAFFIC = {"source_hashes": "87ed8199d2e9ec3ef5715e5d462dc3f0", "fetch_bytes": 119933.6 * 1024 * 2.0,
+                "write_bytes": 14358.6 * 1024 * 1.0}
 
 
 def kernel_source_hash(path: str, signature: str) -> str:
@@ -188,6 +191,8 @@ def main():
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "sell"],
                     help="layout of A_s for the sparse passes (auto: the set-up autotuner picks)")
     ap.add_argument("--cg-max", type=int, default=8)
+    ap.add_argument("--dense-launches", type=int, default=4, choices=[4, 5],
+                    help="dense x-update: four launches per iteration (default) or the five-launch order")
     ap.add_argument("--xupdate", default="auto", choices=["auto", "cg", "dense"],
                     help="x-update: warm-started CG on the sparse A_s, or the cached dense inverse")
     ap.add_argument("--seed", type=int, default=0)
@@ -239,7 +244,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = A.Solver(P, precision=args.precision, cg_max=args.cg_max, max_iter=2000, stream=stream,
-                 use_graph=1 if args.graph else 0, xupdate=args.xupdate, format=args.format)
+                 use_graph=1 if args.graph else 0, xupdate=args.xupdate, format=args.format,
+                 dense_launches=args.dense_launches)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     xmode, factor_ms = S.xupdate()
@@ -268,9 +274,10 @@ def main():
     S.enable_timing(False)
 
     if xmode == "dense":
-        # x-update roofline (k_xsym): every launch reads each scenario's packed fp32
+        # x-update roofline: every launch reads each scenario's packed fp32
         # inverse once (upper 64 x 64 tiles of M_s, 16 KiB each) and its fp64
-        # right-hand side
+        # right-hand side; in the four-launch order the same launch (k_dense_x)
+        # runs the previous iteration's stopping test in its workgroup 0
         nb = (P.n + 63) // 64
         tiles = nb * (nb + 1) // 2
         bytes_per_launch = float(P.num_scen * (tiles * 64 * 64 * 4 + 8 * P.n))
@@ -278,13 +285,17 @@ def main():
         achieved = bytes_per_launch / (tm["pass_ms"] * 1e-3) / 1e9 if tm["pass_ms"] > 0 else 0.0
         traffic = None
         src = os.path.join(ROOT, "paper_2304_14568_amd", "csrc", "factor.hip")
-        if (args.seed == 0 and os.path.exists(src) and
-                kernel_source_hash(src, "__global__ __launch_bounds__(256) void k_xsym(") ==
-                XSYM_TRAFFIC["source_sha256_16"]):
+        if (args.seed == 0 and args.dense_launches == 4 and os.path.exists(src) and
+                XSYM_TRAFFIC["source_hashes"] is not None and
+                kernel_source_hash(src, "__device__ __forceinline__ void xsym_tile(") +
+                kernel_source_hash(src, "__global__ __launch_bounds__(256) void k_dense_x(") ==
+                XSYM_TRAFFIC["source_hashes"]):
             traffic = XSYM_TRAFFIC["fetch_bytes"] + XSYM_TRAFFIC["write_bytes"]
+        kname = ("k_dense_x (x_s = M_s c_s over the packed upper tiles of the cached fp32 inverses, beside the "
+                 "previous iteration's stopping test)" if args.dense_launches == 4 else
+                 "k_xsym (x_s = M_s c_s over the packed upper tiles of the cached fp32 inverses)")
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_xsym (x_s = M_s c_s over the packed upper tiles of the cached fp32 inverses)",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
                 "avg_launch_ms": tm["pass_ms"], "launches": launches, "bytes_per_launch": bytes_per_launch}
     else:
         # fused CG pass roofline: algorithmic bytes of the scenario passes actually
@@ -316,7 +327,7 @@ def main():
         "config": {"workload": f"head-and-neck-shaped phantom seed {args.seed}: 120x120x80 grid at 2.5 mm, "
                                f"{P.m} body voxels, {P.n} spots (3 beams x 15 layers), 13 scenarios",
                    "m": P.m, "n": P.n, "scenarios": P.num_scen, "nnz": P.nnz, "precision": args.precision,
-                   "cg_max": args.cg_max, "xupdate": xmode,
+                   "cg_max": args.cg_max, "xupdate": xmode, "dense_launches": args.dense_launches,
                    "parallelism": "single GPU, all scenarios per launch"},
         "roofline": roof,
         "instrumented_ms_per_step": 1e3 * t_inst / args.steps,

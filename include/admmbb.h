@@ -133,7 +133,8 @@ typedef struct {
                           -1 = chosen by the set-up autotuner among 1 and 2 */
   int32_t tile_nnz;    /* target nonzeros per workgroup tile; 0 = automatic, per patient
                           (about 2048 tiles each, 8192 .. 4M nonzeros) */
-  int32_t pass_threads; /* fused-pass workgroup size 256 or 512; 0 = chosen by the set-up autotuner */
+  int32_t pass_threads; /* fused-pass workgroup size 256, 512 or 1024 (1024: chunk-row layout
+                          only); 0 = chosen per patient by the set-up autotuner */
   int32_t pass_unroll;  /* 1: row data loaded when the row starts; 2: next row's data in flight during the
                            current row (software pipelined); 0 = chosen by the autotuner */
   int32_t xupdate;     /* x-update of every scenario subproblem:
@@ -154,12 +155,19 @@ typedef struct {
                             their chunks interleaved so that a wave load reads 64 consecutive chunks
                             (16-bit column indices only, n <= 65535);
                           ADMM_FORMAT_AUTO (default): both are built and the set-up autotuner
-                            picks the faster for the CG pass (the chunk-row one when it does not
-                            run: dense x-update, or more than about 5 400 spots in a patient) */
+                            picks the faster for the CG pass (the chunk-row one with the dense
+                            x-update, where the tuner does not run) */
   int32_t deterministic; /* 1: every sum of an iteration is exact or in a fixed order (64-bit
                           fixed-point column accumulators, lds_acc -1 or 2 required), so runs and
                           resumed runs repeat bit for bit; default 0 (the autotuner may pick fp64
                           LDS atomics, whose sums depend on the order of the additions) */
+  int32_t dense_launches; /* dense x-update: 4 (default) = four launches per iteration, the
+                          stopping test of an iteration evaluated beside the next iteration's
+                          x-update (and after the last one in a launch of its own) and the dual
+                          update beside the dual step; 5 = five launches, each iteration
+                          complete at its end.  The iterates, scalars and stopping decisions
+                          are the same bit for bit; with 4 the device computes one more
+                          x-update of a patient that has just stopped, and discards it */
   void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
 } admm_options;
 
@@ -347,6 +355,15 @@ admm_status admm_get_trace(admm_ctx* ctx, int32_t patient, admm_info* buf, int32
  * accumulator kind, and the measured average pass time in ms of the chosen one
  * (all scenarios, fp32 or the CG value precision). */
 admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms);
+/* The sparse-pass configuration of one patient of the context (the passes are
+   launched once per patient, each with its own; the set-up autotuner of the CG
+   x-update chooses it per patient): workgroup size, row pipelining (1 or 2),
+   LDS accumulator (0 fp32, 1 fp64, 2 64-bit fixed point), layout
+   (ADMM_FORMAT_CSR / ADMM_FORMAT_SELL) and the tuned pass time in ms (0 where
+   the tuner did not run).  Any output pointer may be NULL.  ADMM_E_ARG for a
+   NULL ctx or a patient outside [0, num_patients). */
+admm_status admm_get_pass_config(const admm_ctx* ctx, int32_t patient, int32_t* threads, int32_t* unroll,
+                                 int32_t* lds_acc, int32_t* format, double* ms);
 
 /* Layout of A_s the sparse passes read (ADMM_FORMAT_CSR or ADMM_FORMAT_SELL):
  * the one asked for, or the set-up autotuner's pick under ADMM_FORMAT_AUTO. */

@@ -27,7 +27,7 @@ EXPORTS = [
     "admm_default_options", "pgd_default_options", "admm_setup", "admm_setup_batch", "admm_warm_start",
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
-    "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_format", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
+    "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_pass_config", "admm_get_format", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
     "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate", "admm_time_pass",
     "admm_stream_probe", "admm_dose_stats_noalloc",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
@@ -64,7 +64,8 @@ class OptionsC(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("lds_acc", ctypes.c_int32), ("tile_nnz", ctypes.c_int32), ("pass_threads", ctypes.c_int32),
                 ("pass_unroll", ctypes.c_int32), ("xupdate", ctypes.c_int32), ("format", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("deterministic", ctypes.c_int32), ("dense_launches", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class InfoC(ctypes.Structure):
@@ -132,6 +133,7 @@ def _load():
         "admm_get_trace": [P, i32, P, i32, P],
         "admm_get_cg_counts": [P, i32, P],
         "admm_get_tuning": [P, P, P, P, P],
+        "admm_get_pass_config": [P, i32, P, P, P, P, P],
         "admm_get_format": [P, P],
         "admm_get_sizes": [P, i32, P, P, P, P],
         "admm_enable_timing": [P, i32],
@@ -415,13 +417,18 @@ class Solver:
         _check(self.ctx, lib.admm_get_trace(self.ctx, patient, buf, cap, ctypes.byref(cnt)))
         return [buf[i].as_dict() for i in range(cnt.value)]
 
-    def tuning(self):
-        t, u, a = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    def tuning(self, patient: Optional[int] = None):
+        """The sparse-pass configuration: of the context (patient 0's, and the
+        summed tuned pass time), or of one patient."""
+        t, u, a, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ms = ctypes.c_double()
-        _check(self.ctx, lib.admm_get_tuning(self.ctx, ctypes.byref(t), ctypes.byref(u), ctypes.byref(a),
-                                             ctypes.byref(ms)))
-        f = ctypes.c_int32()
-        _check(self.ctx, lib.admm_get_format(self.ctx, ctypes.byref(f)))
+        if patient is None:
+            _check(self.ctx, lib.admm_get_tuning(self.ctx, ctypes.byref(t), ctypes.byref(u), ctypes.byref(a),
+                                                 ctypes.byref(ms)))
+            _check(self.ctx, lib.admm_get_format(self.ctx, ctypes.byref(f)))
+        else:
+            _check(self.ctx, lib.admm_get_pass_config(self.ctx, int(patient), ctypes.byref(t), ctypes.byref(u),
+                                                      ctypes.byref(a), ctypes.byref(f), ctypes.byref(ms)))
         return dict(threads=t.value, unroll=u.value, lds_acc=a.value, pass_ms=ms.value,
                     format="sell" if f.value == 1 else "csr")
 

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadmmbb.so")
-SOURCES = ["kernels.hip", "factor.hip", "dose.hip", "mlp.hip", "pgd_dense.hip", "probe.hip", "context.cpp", "pack.cpp", "validate.cpp"]
+SOURCES = ["pass_cg32.hip", "pass_cglp.hip", "pass_f32.hip", "kernels.hip", "factor.hip", "dose.hip", "mlp.hip", "pgd_dense.hip", "probe.hip", "context.cpp", "pack.cpp", "validate.cpp"]
 ARCH = os.environ.get("ADMMBB_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]

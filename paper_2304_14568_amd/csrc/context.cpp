@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <new>
 #include <string>
@@ -94,6 +95,15 @@ struct admm_ctx {
   int acc = ACC_F64;
   int pass_threads = 512, pass_unroll = 1;
   double tuned_ms = 0.0;
+  // configuration of the sparse passes per patient (workgroup size, row
+  // pipelining, LDS accumulator, layout): the passes are launched once per
+  // patient, each with its own; the members above hold the common default
+  struct PassCfg {
+    int threads, unroll, acc, fmt;
+    double ms;  // tuned pass time (0 where the tuner did not run)
+  };
+  std::vector<PassCfg> pcfg;
+  void set_all_cfg() { pcfg.assign(static_cast<size_t>(P), PassCfg{pass_threads, pass_unroll, acc, fmt, 0.0}); }
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs around the CG passes inside the captured iteration
@@ -212,6 +222,14 @@ struct admm_ctx {
       const int b = std::max(tile_begin, pt.tile_begin), e = std::min(tile_end, pt.tile_end);
       if (e <= b) continue;
       pa.nmax = pt.n;
+      if (static_cast<size_t>(p) < pcfg.size()) {
+        const PassCfg& c = pcfg[static_cast<size_t>(p)];
+        pa.threads = c.threads;
+        pa.unroll = c.unroll;
+        pa.acc = c.acc;
+        const bool sl = c.fmt == FMT_SELL && has_sell;
+        pa.mat = pa.mat.vkind == VAL_F32 ? (sl ? sell32 : csr32) : (sl ? selllp : csrlp);
+      }
       launch_pass(mode, pa, b, e - b, stream, p == first ? e0 : nullptr, p == last ? e1 : nullptr);
     }
   }
@@ -334,15 +352,18 @@ struct admm_ctx {
       lists = total >= 0 && hipMalloc(&bl.p, sizeof(GramEntry) * static_cast<size_t>(std::max<int64_t>(total, 1))) ==
                                 hipSuccess;
       // fixed-point scale of each scenario's tiles: a power of two that keeps
-      // 2 max_j (G_s)_jj, a bound of every partial sum, below 2^62
+      // 2 max_j (G_s)_jj, a bound of every partial sum, below 2^62 (from the
+      // fp64 diagonal).  A diagonal beyond fp64 range, or so small that the
+      // scale would leave it, takes the fp64 atomic path instead.
       std::vector<double> gs(static_cast<size_t>(cs), 1.0);
       for (int s = 0; s < cs; ++s) {
-        const Scen& sc = H.scen[g0 + s];
-        double gmax = 0.0;
-        for (int j = 0; j < pt.n; ++j) gmax = std::max(gmax, static_cast<double>(H.gdiag[sc.vec_base + j]));
+        const double gmax = H.gdiag_max[static_cast<size_t>(g0 + s)];
         int e = 0;
-        if (gmax > 0.0) {
+        if (!(2.0 * gmax <= std::numeric_limits<double>::max())) {
+          lists = false;
+        } else if (gmax > 0.0) {
           (void)std::frexp(2.0 * gmax, &e);  // 2 gmax = f 2^e, 1/2 <= f < 1
+          if (62 - e > 1000) lists = false;
           gs[static_cast<size_t>(s)] = std::ldexp(1.0, std::min(62 - e, 1000));
         }
       }
@@ -411,6 +432,19 @@ struct admm_ctx {
     VecArgs va = vec_args(stop_enabled);
     if (dense) {
       const FactorArgs f = fargs();
+      if (opts.dense_launches == 4) {
+        // the previous iteration's stopping test beside the x-update tiles;
+        // the reduction and z-update; residual norms and dual step beside the
+        // dual update, the next right-hand sides and the objective tiles
+        if (with_events)
+          launch_dense_x(f, va, d_c64, n_xjobs, stream, ev[0], ev[1]);
+        else
+          launch_dense_x(f, va, d_c64, n_xjobs, stream);
+        launch_xsym_reduce(f, d_x, n_rjobs, stream);
+        launch_zres(va, NPB, stream);
+        launch_dense_tail_dual(f, va, n_fjobs, NB, stream);
+        return;
+      }
       if (with_events)
         launch_xsym(f, d_c64, n_xjobs, stream, ev[0], ev[1]);
       else
@@ -499,11 +533,15 @@ struct admm_ctx {
   // Run up to `k` iterations.  With stop_enabled the loop ends early once every
   // patient has stopped.  CG x-update: every iteration starts with its head (the
   // gradient pass at z, completion of the previous iteration, CG set-up) and a
-  // final head completes the bookkeeping of the last one.  Dense x-update: each
-  // iteration ends complete (stopping test, dual update, next right-hand sides),
-  // and one head before the first iteration forms the right-hand sides and the
+  // final head completes the bookkeeping of the last one.  Dense x-update: one
+  // head before the first iteration forms the right-hand sides and the
   // objective of the state the run starts from (completing a pending dual
-  // update, as left by a checkpoint).
+  // update, as left by a checkpoint); in the five-launch order each iteration
+  // then ends complete (stopping test, dual update, next right-hand sides), in
+  // the four-launch order the stopping test of each iteration runs in the
+  // next one's first launch, and a final one follows the loop.  There the host
+  // sees a stop one iteration late; the iteration between is skipped on the
+  // device.
   void run(int k, int stop_enabled) {
     if (timing) {
       check(hipEventRecord(ev_a, stream), "hipEventRecord");
@@ -526,6 +564,7 @@ struct admm_ctx {
       }
     }
     if (!dense) launch_head(stop_enabled, 0);
+    if (dense && opts.dense_launches == 4) launch_dense_head(vec_args(stop_enabled), 0, stream);
     if (timing) {
       check(hipEventRecord(ev_b, stream), "hipEventRecord");
       check(hipEventSynchronize(ev_b), "hipEventSynchronize");
@@ -555,58 +594,60 @@ struct admm_ctx {
     }
   }
 
-  // Time the fused CG pass over every tile for each candidate configuration
-  // and keep the fastest (values of the multiplied vector do not change the work).
+  // Time each patient's fused CG pass (its own launch) for every candidate
+  // configuration and keep that patient's fastest (values of the multiplied
+  // vector do not change the work).
   void autotune() {
-    std::vector<int> th = {256, 512}, un = {1, 2}, ac = {ACC_FIX64, ACC_F64}, fm = {FMT_CSR};
+    std::vector<int> th = {256, 512, 1024}, un = {1, 2}, ac = {ACC_FIX64, ACC_F64}, fm = {FMT_CSR};
     if (opts.pass_threads) th = {opts.pass_threads};
     if (opts.pass_unroll) un = {opts.pass_unroll};
     if (opts.lds_acc >= 0) ac = {opts.lds_acc};
     if (opts.deterministic) ac = {ACC_FIX64};
     if (has_sell) fm = opts.format == FMT_SELL ? std::vector<int>{FMT_SELL} : std::vector<int>{FMT_CSR, FMT_SELL};
-    if (pass_smem_bytes(H.nmax, ac[0]) > 65536) return;
     hipEvent_t e0, e1;
     check(hipEventCreate(&e0), "hipEventCreate");
     check(hipEventCreate(&e1), "hipEventCreate");
-    double best = 1e30;
-    int bt = th[0], bu = un[0], ba = ac[0], bf = fm[0];
+    std::vector<PassCfg> best(static_cast<size_t>(P), PassCfg{th[0], un[0], ac[0], fm[0], 1e30});
     const int reps = 3;
     for (int f : fm)
-    for (int a64 : ac)
-      for (int t : th)
-        for (int u : un) {
-          // the sliced layout has no row pipelining variant
-          if (f == FMT_SELL && u != un[0]) continue;
-          use_format(f);
-          acc = a64;
-          pass_threads = t;
-          pass_unroll = u;
-          PassArgs pa = pass_args(opts.precision == ADMM_PREC_FP32 ? mat32 : matlp);
-          pa.src = d_v;
-          pa.src_per_scen = 1;
-          pa.objpart = nullptr;
-          pass_launch(PASS_CG, pa, 0, T);
-          check(hipEventRecord(e0, stream), "hipEventRecord");
-          for (int r = 0; r < reps; ++r) pass_launch(PASS_CG, pa, 0, T);
-          check(hipEventRecord(e1, stream), "hipEventRecord");
-          check(hipEventSynchronize(e1), "hipEventSynchronize");
-          float ms = 0.0f;
-          check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-          if (ms / reps < best) {
-            best = ms / reps;
-            bt = t;
-            bu = u;
-            ba = a64;
-            bf = f;
+      for (int a64 : ac)
+        for (int t : th)
+          for (int u : un) {
+            // the sliced layout has neither a row pipelining nor a 1024-thread variant
+            if (f == FMT_SELL && (u != un[0] || t > 512)) continue;
+            set_all_cfg();
+            for (auto& c : pcfg) c = PassCfg{t, u, a64, f, 0.0};
+            PassArgs pa = pass_args(opts.precision == ADMM_PREC_FP32 ? csr32 : csrlp);
+            pa.src = d_v;
+            pa.src_per_scen = 1;
+            pa.objpart = nullptr;
+            for (int p = 0; p < P; ++p) {
+              const Pat& pt = H.pat[p];
+              const int tc = pt.tile_end - pt.tile_begin;
+              if (tc <= 0) continue;
+              pass_launch(PASS_CG, pa, pt.tile_begin, tc);
+              check(hipEventRecord(e0, stream), "hipEventRecord");
+              for (int r = 0; r < reps; ++r) pass_launch(PASS_CG, pa, pt.tile_begin, tc);
+              check(hipEventRecord(e1, stream), "hipEventRecord");
+              check(hipEventSynchronize(e1), "hipEventSynchronize");
+              float ms = 0.0f;
+              check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+              if (ms / reps < best[static_cast<size_t>(p)].ms) best[static_cast<size_t>(p)] = PassCfg{t, u, a64, f, ms / reps};
+            }
           }
-        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    use_format(bf);
-    acc = ba;
-    pass_threads = bt;
-    pass_unroll = bu;
-    tuned_ms = best < 1e30 ? best : 0.0;
+    pcfg = best;
+    tuned_ms = 0.0;
+    for (auto& c : pcfg) {
+      if (!(c.ms < 1e30)) c.ms = 0.0;
+      tuned_ms += c.ms;
+    }
+    // the common default (reported by admm_get_tuning): patient 0's
+    use_format(pcfg[0].fmt);
+    acc = pcfg[0].acc;
+    pass_threads = pcfg[0].threads;
+    pass_unroll = pcfg[0].unroll;
   }
 
   void reset_patient(int p, const double* z0, double new_rho) {
@@ -630,6 +671,7 @@ struct admm_ctx {
     PatState st{};
     st.rho = rho[p];
     st.tau = rho[p];
+    st.bb_tau0 = rho[p];
     std::memcpy(h_ps + p, &st, sizeof(st));
     check(hipMemcpyAsync(d_ps + p, h_ps + p, sizeof(PatState), hipMemcpyHostToDevice, stream), "H2D");
     check(hipStreamSynchronize(stream), "sync");
@@ -738,6 +780,7 @@ admm_status admm_default_options(admm_options* o) {
   o->pass_unroll = 0;
   o->format = -1;
   o->deterministic = 0;
+  o->dense_launches = 4;
   o->xupdate = ADMM_XUPDATE_AUTO;
   o->stream = nullptr;
   return ADMM_OK;
@@ -1119,6 +1162,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     for (int p = 0; p < num_patients; ++p) c->reset_patient(p, nullptr, 0.0);
     if (o.pass_threads) c->pass_threads = o.pass_threads;
     if (o.pass_unroll) c->pass_unroll = o.pass_unroll;
+    c->set_all_cfg();
     clk.mark("cached inverses");
     if (!c->dense) c->autotune();  // the dense x-update does not run the CG pass per iteration
     check(hipEventCreate(&c->ev_a), "hipEventCreate");
@@ -1969,6 +2013,8 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
   s.xnorm = scalars[13];
   s.znorm = scalars[14];
   s.cg_steps = static_cast<int32_t>(scalars[15]);
+  s.bb_tau0 = s.tau;
+  s.bb_iter0 = s.iter;
   ctx->h_ps[patient] = s;
   check(hipMemcpy(ctx->d_ps + patient, &s, sizeof(PatState), hipMemcpyHostToDevice), "H2D");
   return ADMM_OK;
@@ -2030,6 +2076,19 @@ admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unro
   if (unroll) *unroll = ctx->pass_unroll;
   if (lds_acc) *lds_acc = ctx->acc;
   if (ms) *ms = ctx->tuned_ms;
+  return ADMM_OK;
+}
+
+admm_status admm_get_pass_config(const admm_ctx* ctx, int32_t patient, int32_t* threads, int32_t* unroll,
+                                 int32_t* lds_acc, int32_t* format, double* ms) {
+  if (!ctx) return ADMM_E_ARG;
+  if (patient < 0 || patient >= ctx->P || static_cast<size_t>(patient) >= ctx->pcfg.size()) return ADMM_E_ARG;
+  const auto& c = ctx->pcfg[static_cast<size_t>(patient)];
+  if (threads) *threads = c.threads;
+  if (unroll) *unroll = c.unroll;
+  if (lds_acc) *lds_acc = c.acc;
+  if (format) *format = (c.fmt == FMT_SELL && ctx->has_sell) ? ADMM_FORMAT_SELL : ADMM_FORMAT_CSR;
+  if (ms) *ms = c.ms;
   return ADMM_OK;
 }
 

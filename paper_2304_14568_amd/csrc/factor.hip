@@ -520,10 +520,10 @@ __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, 
 // has entries of both signs and |M| |c| exceeds |M c| by two orders of
 // magnitude, so fp32 sums would put a floor of about 1e-5 relative under every
 // x-update; the fp32 storage of M itself contributes about 1e-6.
-__global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __restrict__ c) {
+__device__ __forceinline__ void xsym_tile(const FactorArgs& f, const double* __restrict__ c, int idx) {
   __shared__ float tl[kFb][kFb + 1];  // the tile again, read by columns for T^T c_I
   __shared__ double cI[kFb], cJ[kFb];
-  const XTile tj = f.xtiles[blockIdx.x];
+  const XTile tj = f.xtiles[idx];
   const int tid = threadIdx.x;
   const int i = tid >> 2, q = tid & 3;
   // the tile's 16 KB, in flight before anything else
@@ -572,6 +572,10 @@ __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __rest
   if (q == 0) out[kFb + i] = bsum;
 }
 
+__global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __restrict__ c) {
+  xsym_tile(f, c, static_cast<int>(blockIdx.x));
+}
+
 // x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
 // (T_JI^T c_J).  Wave w adds the blocks J = w, w + 4, ...; the four partial
 // sums are then added in a fixed order.
@@ -603,6 +607,20 @@ __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __rest
   }
 }
 
+// The dual update y_s += tau d_s at one spot (when `update`) and the
+// right-hand side c_s = b_s + rho/2 z - y_s/2 of the next x-update there, with
+// the roundings written out, so that every launch order that applies them
+// gives the same bits.  Returns y_s at the spot.
+__device__ __forceinline__ float dual_rhs_at(const VecArgs& a, int64_t vi, bool update, float yv, double dp,
+                                             double bv, float zj, double tau, double rho) {
+  if (update) {
+    yv = static_cast<float>(fma(tau, dp, static_cast<double>(yv)));
+    a.y[vi] = yv;
+  }
+  a.c64[vi] = fma(-0.5, static_cast<double>(yv), fma(0.5 * rho, static_cast<double>(zj), bv));
+  return yv;
+}
+
 // completion of the pending dual update and the right-hand side
 // c_s = b_s + rho/2 z - y_s/2 (one scenario column block of 64 per workgroup)
 // one wave: column block bi of one scenario, lane = column within the block
@@ -626,11 +644,7 @@ __device__ __forceinline__ void fhead_block(const VecArgs& a, int bi, int lane) 
   if (ps->stopped) return;
   double yy = 0.0;
   if (in) {
-    if (ps->pending) {
-      yv = static_cast<float>(static_cast<double>(yv) + ps->tau * dp);
-      a.y[vi] = yv;
-    }
-    a.c64[vi] = bv + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv);
+    yv = dual_rhs_at(a, vi, ps->pending != 0, yv, dp, bv, zj, ps->tau, ps->rho);
     yy = static_cast<double>(yv) * yv;
   }
   yy = wave_sum_d(yy);
@@ -708,11 +722,37 @@ __device__ __forceinline__ void dense_head_block(const VecArgs& a, int bi, int l
   const PatState* ps = a.ps + sc.patient;
   const float zj = in ? a.z[pt.zvec_base + j] : 0.0f;
   if (!ps->dual_go) return;
+  if (in) (void)dual_rhs_at(a, vi, true, yv, dp, bv, zj, ps->tau, ps->rho);
+}
+
+// The same update in the launch that forms tau: every wave forms its
+// patient's tau itself, from the z-update's partial sums in the order of
+// wave_strided_sums and the inputs the last head recorded, which gives the
+// bits the scalar workgroup of that launch (body_scalars_run) stores.
+__device__ __forceinline__ void dense_dual_block(const VecArgs& a, int bi, int lane) {
+  const Blk bk = a.blk[bi];
+  const Scen sc = a.scen[bk.owner];
+  const int j = bk.col0 + lane;
+  const bool in = j < sc.n;
+  const int64_t vi = sc.vec_base + j;
+  float yv = 0.0f;
+  double dp = 0.0, bv = 0.0;
   if (in) {
-    yv = static_cast<float>(static_cast<double>(yv) + ps->tau * dp);
-    a.y[vi] = yv;
-    a.c64[vi] = bv + 0.5 * ps->rho * zj - 0.5 * static_cast<double>(yv);
+    yv = a.y[vi];
+    dp = a.dprev[vi];
+    bv = a.b64[vi];
   }
+  const Pat pt = a.pat[sc.patient];
+  const PatState* ps = a.ps + sc.patient;
+  const float zj = in ? a.z[pt.zvec_base + j] : 0.0f;
+  const int stopped = ps->stopped;
+  const double rho = ps->rho, tau0 = ps->bb_tau0;
+  const int it0 = ps->bb_iter0;
+  double v[2];
+  wave_strided_sums<2>(a.bpartp + static_cast<int64_t>(4 * pt.blk_begin) * 8, 4 * pt.nblk, 3, v);
+  if (stopped) return;
+  const double tau = bb_dual_step(a.prm, rho, tau0, it0, v[0], v[1]);
+  if (in) (void)dual_rhs_at(a, vi, true, yv, dp, bv, zj, tau, rho);
 }
 
 __global__ __launch_bounds__(256) void k_dense_tail(FactorArgs f, VecArgs a, int nfobj) {
@@ -732,6 +772,41 @@ __global__ __launch_bounds__(256) void k_dense_head(VecArgs a, int nblk) {
   }
   const int bi = 4 * (b - 1) + static_cast<int>(threadIdx.x >> 6);
   if (bi < nblk) dense_head_block(a, bi, threadIdx.x & 63);
+}
+
+// The four-launch dense iteration (the reduction and the z-update between them):
+//   x:    workgroup 0 the objective sums and stopping test of the previous
+//         iteration (head_scalars_run), the others the x-update tiles.  The
+//         tiles read the stop flag that workgroup 0 may be setting: a tile of
+//         a patient that stops there writes partial sums that nothing reads
+//         (the reduction and the z-update read the flag after the launch);
+//   tail: workgroup 0 the residual norms, tolerances and dual step
+//         (body_scalars_run), then the dual update with the next right-hand
+//         sides (each wave forms tau itself, dense_dual_block), then the
+//         objective tiles at the new z.
+// Every value equals the five-launch order's; the stopping test of the last
+// iteration of a run follows in a launch of its own.
+__global__ __launch_bounds__(256) void k_dense_x(FactorArgs f, VecArgs a, const double* __restrict__ c) {
+  if (blockIdx.x == 0) {
+    head_scalars_run<true>(a, 0, 0);
+    return;
+  }
+  xsym_tile(f, c, static_cast<int>(blockIdx.x) - 1);
+}
+
+__global__ __launch_bounds__(256) void k_dense_tail_dual(FactorArgs f, VecArgs a, int nfobj, int nblk) {
+  const int b = static_cast<int>(blockIdx.x);
+  if (b == 0) {
+    body_scalars_run<true>(a);
+    return;
+  }
+  const int ndual = (nblk + 3) / 4;
+  if (b - 1 < ndual) {
+    const int bi = 4 * (b - 1) + static_cast<int>(threadIdx.x >> 6);
+    if (bi < nblk) dense_dual_block(a, bi, threadIdx.x & 63);
+    return;
+  }
+  if (b - 1 - ndual < nfobj) fobj_tile(f, a.z, b - 1 - ndual);
 }
 
 // The head of a dense iteration in one launch: workgroups [0, nfobj) take the
@@ -832,6 +907,20 @@ void launch_dense_tail(const FactorArgs& f, const VecArgs& a, int nfobj, hipStre
 
 void launch_dense_head(const VecArgs& a, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(k_dense_head, dim3(1 + (nblk + 3) / 4), dim3(256), 0, st, a, nblk);
+}
+
+void launch_dense_x(const FactorArgs& f, const VecArgs& a, const double* c, int njobs, hipStream_t st, hipEvent_t e0,
+                    hipEvent_t e1) {
+  const dim3 grid(static_cast<unsigned>(1 + njobs));
+  if (e0 != nullptr)
+    hipExtLaunchKernelGGL(k_dense_x, grid, dim3(256), 0, st, e0, e1, 0, f, a, c);
+  else
+    hipLaunchKernelGGL(k_dense_x, grid, dim3(256), 0, st, f, a, c);
+}
+
+void launch_dense_tail_dual(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st) {
+  const int grid = 1 + (nblk + 3) / 4 + nfobj;
+  hipLaunchKernelGGL(k_dense_tail_dual, dim3(static_cast<unsigned>(grid)), dim3(256), 0, st, f, a, nfobj, nblk);
 }
 
 void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st) {

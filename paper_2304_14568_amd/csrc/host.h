@@ -67,6 +67,7 @@ struct Packed {
   std::vector<float> dinv;        // Jacobi inverse diagonal (stacked), filled when requested
   std::vector<float> gdiag;       // (A_s^T c_s W A_s)_jj per scenario (stacked)
   std::vector<double> gdiag_mean; // per patient: mean over scenarios and spots of (A_s^T c_s W A_s)_jj
+  std::vector<double> gdiag_max;  // per scenario: max_j (A_s^T c_s W A_s)_jj in fp64
   std::vector<std::vector<double>> g0;  // per patient: 2 sum_s b_s
   std::vector<float> lb, ub;      // per patient stacked
   int64_t vec_total = 0, zvec_total = 0, part_total = 0, nnz_total = 0, rows_total = 0;

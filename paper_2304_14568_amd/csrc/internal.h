@@ -91,6 +91,8 @@ struct PatState {
   int32_t cg_steps;    // CG steps (summed over scenarios) of the last iteration
   int32_t cg_total;
   int32_t dual_go;     // dense five-launch iteration: the head launch applies the pending dual update
+  int32_t bb_iter0;    // iter and tau as the last head left them: the inputs of the next
+  double bb_tau0;      // dual step, stable while the dense iteration's tail forms it
 };
 
 struct IterRecord {
@@ -293,6 +295,12 @@ void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk,
 // the stopping test beside the dual update and right-hand sides
 void launch_dense_tail(const FactorArgs& f, const VecArgs& a, int nfobj, hipStream_t st);
 void launch_dense_head(const VecArgs& a, int nblk, hipStream_t st);
+// dense four-launch iteration: the stopping test of the previous iteration
+// beside the x-update tiles; the reduction; the z-update; body scalars beside
+// the dual update with the next right-hand sides and the objective tiles
+void launch_dense_x(const FactorArgs& f, const VecArgs& a, const double* c, int njobs, hipStream_t st,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_dense_tail_dual(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st);
 void launch_dose_hist(const float* dose, const uint8_t* grp, int m, int G, int nbins, float inv_w, uint32_t* counts,
                       double* sums, uint32_t* maxkey, hipStream_t st);
 // Allocation-free dose statistics: device address of the fixed scratch array

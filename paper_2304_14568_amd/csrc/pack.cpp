@@ -490,13 +490,16 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         P.scen_nnz.push_back(A.nnz);
         pt.fzero += r.fzero;
         pt.fconst += r.fconst;
+        double gdmax = 0.0;
         for (int j = 0; j < n; ++j) {
           P.gdiag.push_back(static_cast<float>(r.gdiag[j]));
+          gdmax = std::max(gdmax, r.gdiag[j]);
           P.b.push_back(static_cast<float>(r.b[j]));
           P.b64.push_back(r.b[j]);
           g0[j] += 2.0 * r.b[j];
           gsum += r.gdiag[j];
         }
+        P.gdiag_max.push_back(gdmax);
         P.vec_total += n;
       }
       pt.sblk_end = blk_s;

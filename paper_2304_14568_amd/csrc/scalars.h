@@ -25,6 +25,39 @@ __device__ __forceinline__ double wave_strided_sum(const double* p, int count) {
   return s;
 }
 
+// NV interleaved sums by one wave: v[k] = sum over b < count of p[b * 8 + k0 + k],
+// lane l adding entries l, l + 64, ... in order, then a fixed butterfly; every
+// lane returns the totals.  Any subset of k gives the same bits for its sums.
+template <int NV>
+__device__ __forceinline__ void wave_strided_sums(const double* p, int count, int k0, double (&v)[NV]) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x & 63; b < count; b += 64) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += p[static_cast<int64_t>(b) * 8 + k0 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  }
+}
+
+// Dual step of Sec. 2.2: the Barzilai-Borwein value beta = -<dd, dy> / ||dd||^2
+// when it is positive and finite (after the first iteration), else rho, then
+// the optional clamp.  dy = y^k - y^{k-1} = tau_{k-1} d^k, so <dd, dy> =
+// tau_{k-1} <dd, d^k> with <dd, d^k> = dd_dp and ||dd||^2 = dd2.
+__device__ __forceinline__ double bb_dual_step(const AlgoParams& P, double rho, double tau0, int iter0, double dd_dp,
+                                               double dd2) {
+  double tau = rho;
+  if (P.bb && iter0 >= 1 && dd2 > 0.0) {
+    const double beta = -tau0 * dd_dp / dd2;
+    if (isfinite(beta) && beta > 0.0) tau = beta;
+  }
+  if (P.bb_clamp > 0.0) tau = fmin(fmax(tau, rho / P.bb_clamp), rho * P.bb_clamp);
+  return tau;
+}
+
 // Deterministic block sum of NV doubles over NT threads; result valid in thread 0.
 template <int NV, int NT = kThreads>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* sh) {
@@ -157,6 +190,10 @@ __device__ __forceinline__ void head_scalars_run(const VecArgs& a, int nscen, in
         ps->pending = 0;
       }
       ps->f_prev = f;
+      // inputs of the next dual step, stable while the launch that forms it
+      // runs (the dense x-update forms it in several workgroups at once)
+      ps->bb_tau0 = ps->tau;
+      ps->bb_iter0 = ps->iter;
     }
     __syncthreads();
   }
@@ -185,10 +222,13 @@ __device__ __forceinline__ void head_scalars_run(const VecArgs& a, int nscen, in
 
 // Residual norms, tolerances and the Barzilai-Borwein dual step per patient,
 // from the z-update's partial sums; one workgroup of kThreads threads.
-// DENSE: also the dual tolerance, from the norm of the duals after the update
-// y + tau d that the next launch applies (||y||^2 + 2 tau <y, d> + tau^2 ||d||^2
-// from the same partial sums), and the flag dual_go that tells that launch
-// whether to apply it (0 for a patient that has stopped).
+// DENSE: the partial sums are added by wave 0 in the order of
+// wave_strided_sums, and the step from the inputs the last head recorded
+// (bb_tau0, bb_iter0), so that a workgroup that forms the same step in the
+// same launch gets the same bits; also the dual tolerance, from the norm of
+// the duals after the update y + tau d (||y||^2 + 2 tau <y, d> + tau^2 ||d||^2
+// from the same partial sums), and the flag dual_go for a launch that applies
+// that update after this one (0 for a patient that has stopped).
 template <bool DENSE>
 __device__ __forceinline__ void body_scalars_run(const VecArgs& a) {
   __shared__ double sh[4 * 8];
@@ -198,15 +238,20 @@ __device__ __forceinline__ void body_scalars_run(const VecArgs& a) {
     PatState* ps = a.ps + p;
     const int stopped = ps->stopped;  // read beside the partial sums
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < 4 * pt.nblk; b += kThreads)
-      for (int k = 0; k < (DENSE ? 8 : 6); ++k) v[k] += a.bpartp[(int64_t)(4 * pt.blk_begin + b) * 8 + k];
+    if constexpr (DENSE) {
+      if (threadIdx.x < 64) wave_strided_sums<8>(a.bpartp + (int64_t)(4 * pt.blk_begin) * 8, 4 * pt.nblk, 0, v);
+    } else {
+      for (int b = threadIdx.x; b < 4 * pt.nblk; b += kThreads)
+        for (int k = 0; k < 6; ++k) v[k] += a.bpartp[(int64_t)(4 * pt.blk_begin + b) * 8 + k];
+    }
     // thread 0's inputs from the patient's state, requested before the reduction
-    int cg = 0, iter0 = 0, cgt0 = 0;
+    int cg = 0, iter0 = 0, cgt0 = 0, itb = 0;
     double rho = 0.0, tau0 = 0.0;
     if (threadIdx.x == 0) {
       for (int s = 0; s < pt.num_scen; ++s) cg += a.cgcount[pt.scen_begin + s];
       rho = ps->rho;
-      tau0 = ps->tau;
+      tau0 = DENSE ? ps->bb_tau0 : ps->tau;
+      itb = DENSE ? ps->bb_iter0 : ps->iter;
       iter0 = ps->iter;
       cgt0 = ps->cg_total;
     }
@@ -214,18 +259,12 @@ __device__ __forceinline__ void body_scalars_run(const VecArgs& a) {
       if (DENSE && threadIdx.x == 0) ps->dual_go = 0;
       continue;
     }
-    block_sum<8>(v, sh);
+    if constexpr (!DENSE) block_sum<8>(v, sh);
     if (threadIdx.x == 0) {
       const int N = pt.num_scen;
       const double rp = sqrt(v[2]);
       const double rd = sqrt(static_cast<double>(N)) * rho * sqrt(v[0]);
-      double tau = rho;
-      if (P.bb && iter0 >= 1 && v[4] > 0.0) {
-        // dy = y^k - y^{k-1} = tau_{k-1} d^k, so <dd, dy> = tau_{k-1} <dd, d^k>
-        const double beta = -tau0 * v[3] / v[4];
-        if (isfinite(beta) && beta > 0.0) tau = beta;
-      }
-      if (P.bb_clamp > 0.0) tau = fmin(fmax(tau, rho / P.bb_clamp), rho * P.bb_clamp);
+      const double tau = bb_dual_step(P, rho, tau0, itb, v[3], v[4]);
       const double base = P.eps_abs * sqrt(static_cast<double>(N) * pt.n);
       ps->xnorm = sqrt(v[5]);
       ps->znorm = sqrt(v[1]);

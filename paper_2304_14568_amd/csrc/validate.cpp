@@ -134,8 +134,10 @@ admm_status validate_options(const admm_options* o, std::string* msg) {
   if (o->check_every < 1) return fail(msg, ADMM_E_ARG, "check_every must be >= 1");
   if (o->lds_acc < -1 || o->lds_acc > 2) return fail(msg, ADMM_E_ARG, "lds_acc must be -1, 0, 1 or 2");
   if (o->tile_nnz < 0) return fail(msg, ADMM_E_ARG, "tile_nnz < 0");
-  if (o->pass_threads != 0 && o->pass_threads != 256 && o->pass_threads != 512)
-    return fail(msg, ADMM_E_ARG, "pass_threads must be 0, 256 or 512");
+  if (o->pass_threads != 0 && o->pass_threads != 256 && o->pass_threads != 512 && o->pass_threads != 1024)
+    return fail(msg, ADMM_E_ARG, "pass_threads must be 0, 256, 512 or 1024");
+  if (o->pass_threads == 1024 && o->format == 1)
+    return fail(msg, ADMM_E_ARG, "the sliced layout has no 1024-thread pass (pass_threads 0, 256 or 512)");
   if (o->pass_unroll != 0 && o->pass_unroll != 1 && o->pass_unroll != 2)
     return fail(msg, ADMM_E_ARG, "pass_unroll must be 0, 1 or 2");
   if (o->format < -1 || o->format > 1) return fail(msg, ADMM_E_ARG, "format must be -1, 0 or 1");
@@ -143,6 +145,7 @@ admm_status validate_options(const admm_options* o, std::string* msg) {
   if (o->deterministic && o->lds_acc >= 0 && o->lds_acc != 2)
     return fail(msg, ADMM_E_ARG, "deterministic needs lds_acc -1 or 2 (64-bit fixed-point column sums)");
   if (o->xupdate < -1 || o->xupdate > 1) return fail(msg, ADMM_E_ARG, "xupdate must be -1, 0 or 1");
+  if (o->dense_launches != 4 && o->dense_launches != 5) return fail(msg, ADMM_E_ARG, "dense_launches must be 4 or 5");
   return ADMM_OK;
 }
 

@@ -138,7 +138,8 @@ def test_bad_options_rejected_before_device_work():
     P = _tiny()
     for kw in (dict(cg_max=0), dict(cg_max=65), dict(z_mode=2), dict(lds_acc=3), dict(pass_threads=128),
                dict(pass_unroll=3), dict(max_iter=-1), dict(check_every=0), dict(precision=7),
-               dict(xupdate=2), dict(format=2), dict(deterministic=2), dict(deterministic=1, lds_acc=1)):
+               dict(xupdate=2), dict(format=2), dict(deterministic=2), dict(deterministic=1, lds_acc=1),
+               dict(dense_launches=3)):
         with pytest.raises(A.AdmmError) as e:
             A.Solver(P, **kw)
         assert e.value.code == -1, kw

@@ -35,10 +35,20 @@ def probs():
 
 @pytest.mark.parametrize("which", [0, 1])
 def test_dense_iterates_follow_the_oracle(probs, which):
+    """z after k iterations, and every scalar of the first K iterations (the
+    objective, the Barzilai-Borwein step tau, both residuals and both
+    tolerances of Sec. 2.2), against the oracle's history.  The device keeps
+    the inverses in fp32 and the iterates in fp32; over the first ten
+    iterations it was measured within 1.4e-5 (tau), 2.7e-6 (r_prim), 7.3e-7
+    (r_dual) and 2.1e-8 (objective) of the oracle; the bounds leave 4-8x."""
     import paper_2304_14568_amd as A
     P, W, xs, fs = probs[which]
     K = 12
     zr, fr = _oracle_path(W, K)
+    # the paper's tolerances: the stopping test is evaluated, and does not
+    # pass, within K iterations
+    hist = oadmm.admm_bb(W, max_iter=K, record=True).history
+    assert len(hist) == K
     with A.Solver(P, xupdate="dense", max_iter=1000) as S:
         assert S.xupdate()[0] == "dense"
         assert abs(S.rho() - wls.default_rho(W)) <= 1e-6 * S.rho()
@@ -48,11 +58,16 @@ def test_dense_iterates_follow_the_oracle(probs, which):
             z = S.z()
             # fp32 inverse and fp32 iterates against fp64 Cholesky solves
             err = np.linalg.norm(z - zr[k - 1]) / max(1e-30, np.linalg.norm(zr[k - 1]))
-            assert err <= 2e-4 * k, (k, err)
+            assert err <= 2e-5 * k, (k, err)
         tr = S.trace()
+        assert len(tr) >= K
         for t in tr[:K]:
-            f_ref = fr[t["iter"] - 1]
-            assert abs(t["obj"] - f_ref) <= 1e-4 * f_ref
+            k = t["iter"]
+            h = hist[k - 1]
+            assert abs(t["obj"] - fr[k - 1]) <= 1e-7 * fr[k - 1]
+            for key, tol in (("obj", 1e-7), ("tau", 1e-4), ("r_prim", 2e-5), ("r_dual", 2e-5),
+                             ("eps_prim", 2e-5), ("eps_dual", 1e-4)):
+                assert abs(t[key] - h[key]) <= tol * abs(h[key]), (k, key, t[key], h[key])
         # the objective from the quadratic form (fp64 Gram matrix, fp64 p) equals the
         # sparse-pass objective at the same z up to the fp32 rounding of p in the pass
         assert abs(tr[K - 1]["obj"] - S.objective(S.z())) <= 1e-7 * tr[K - 1]["obj"]
@@ -238,3 +253,39 @@ def test_dense_set_up_and_iterations_are_bitwise_reproducible(monkeypatch):
     (z0, y0, d0, f0), (z1, y1, d1, f1) = states
     assert np.array_equal(z0, z1) and np.array_equal(y0, y1) and np.array_equal(d0, d1)
     assert f0 == f1
+
+
+def _run_both_orders(Ps, **kw):
+    import paper_2304_14568_amd as A
+    out = {}
+    for nl in (5, 4):
+        with A.Solver(Ps, xupdate="dense", dense_launches=nl, max_iter=3000, **kw) as S:
+            S.iterate(7)
+            st7 = [S.get_state(p) for p in range(len(Ps))]
+            S.reset()
+            zs, info, status = S.solve()
+            out[nl] = (st7, zs, info, [S.trace(p) for p in range(len(Ps))], status)
+    return out[5], out[4]
+
+
+@pytest.mark.parametrize("case", ["tiny", "hn_small", "batch_of_both", "no_graph"])
+def test_four_launch_iteration_equals_five_launch_order(probs, case):
+    """The four-launch dense iteration (the stopping test of an iteration
+    beside the next x-update, the dual update beside the Barzilai-Borwein step
+    that every wave forms itself) against the five-launch order: the same
+    duals, differences and scalars after 7 iterations, and the same solve
+    (iterates, trace and stopping decision of every patient), bit for bit.
+    The batch stops its two patients at different iterations."""
+    Ps = {"tiny": [probs[0][0]], "hn_small": [probs[1][0]], "batch_of_both": [probs[0][0], probs[1][0]],
+          "no_graph": [probs[1][0]]}[case]
+    a, b = _run_both_orders(Ps, **({"use_graph": 0} if case == "no_graph" else {}))
+    for sa, sb in zip(a[0], b[0]):
+        for key in ("z", "y", "d", "scalars"):
+            assert np.array_equal(sa[key], sb[key]), key
+    for za, zb in zip(a[1], b[1]):
+        assert np.array_equal(za, zb)
+    assert a[2] == b[2]
+    assert a[3] == b[3]
+    assert a[4] == b[4]
+    if case == "batch_of_both":
+        assert a[2][0]["iter"] != a[2][1]["iter"]
