@@ -492,6 +492,14 @@ __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_beg
       A[static_cast<int64_t>(i0 + 4 * ti + q) * npad + j0 + tj + 16 * r] = a_old[q][r] - acc[q][r];
 }
 
+// Position of entry (r, c) inside a stored 64 x 64 tile of M_s.  Thread t of
+// the x-update holds row t / 4, columns 16 (t % 4) .. + 15 as four float4
+// (k = 0..3); float4 k of thread t is stored at k * 256 + t, so that every
+// wave load instruction of the x-update reads 1 KiB contiguous.
+__host__ __device__ __forceinline__ int xtile_pos(int r, int c) {
+  return 4 * (((c >> 2) & 3) * 256 + 4 * r + (c >> 4)) + (c & 3);
+}
+
 // packed M = -A (upper tiles) in fp32, for the chunk of scenarios starting at scen_begin
 __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, int scen_begin, int npad) {
   const Pat pt = f.pat[patient];
@@ -503,7 +511,7 @@ __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, 
     const int i = static_cast<int>(idx / npad), j = static_cast<int>(idx % npad);
     const int I = i / kFb, J = j / kFb;
     if (I <= J)
-      f.Mp[sc.mpack_off + tile_index(I, J, pt.nbk) * kFb * kFb + (i % kFb) * kFb + (j % kFb)] =
+      f.Mp[sc.mpack_off + tile_index(I, J, pt.nbk) * kFb * kFb + xtile_pos(i % kFb, j % kFb)] =
           static_cast<float>(-A[idx]);
   }
 }
@@ -514,7 +522,8 @@ __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, 
 
 // One packed tile T = M_s[I, J] (I <= J) per workgroup: a = T c_J and, off
 // the diagonal, b = T^T c_I (the tile's contribution to the rows of block J).
-// Thread t holds row t/4, columns 16 (t%4) .. +15 (four float4 loads).  The
+// Thread t holds row t/4, columns 16 (t%4) .. +15 (four float4 loads, each a
+// 1 KiB contiguous read per wave in the stored order of xtile_pos).  The
 // tile table entry carries every address, so the tile load depends on one
 // table read only.  The right-hand side and all sums are fp64: the inverse
 // has entries of both signs and |M| |c| exceeds |M c| by two orders of
@@ -530,7 +539,7 @@ __device__ __forceinline__ void xsym_tile(const FactorArgs& f, const double* __r
   const float4* T = reinterpret_cast<const float4*>(f.Mp + tj.moff);
   float4 m[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) m[k] = T[tid * 4 + k];
+  for (int k = 0; k < 4; ++k) m[k] = T[k * 256 + tid];
   if (f.ps[tj.patient].stopped) return;
   if (tid < kFb) {
     const int jc = tj.J * kFb + tid, ic = tj.I * kFb + tid;
