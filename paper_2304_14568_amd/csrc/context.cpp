@@ -61,6 +61,8 @@ struct admm_ctx {
   Pat* d_pat = nullptr;
   Tile* d_tiles = nullptr;
   Blk* d_blk = nullptr;
+  ColJob* d_cjobs = nullptr;
+  ZJob* d_zjobs = nullptr;
   Blk* d_pblk = nullptr;
   // the sparse passes read mat32 / matlp (the layout in use); the Gram
   // kernels of the dense set-up read the chunk-row layout csr32
@@ -255,6 +257,8 @@ struct admm_ctx {
     a.pat = d_pat;
     a.blk = d_blk;
     a.pblk = d_pblk;
+    a.cjobs = d_cjobs;
+    a.zjobs = d_zjobs;
     a.tiles = d_tiles;
     a.part = d_part;
     a.objpart = d_objpart;
@@ -1059,6 +1063,29 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->d_pat = c->upload(H.pat);
     c->d_tiles = c->upload(H.tiles);
     c->d_blk = c->upload(H.blk);
+    {
+      std::vector<ColJob> cj(H.blk.size());
+      for (size_t b = 0; b < H.blk.size(); ++b) {
+        const Scen& sc = H.scen[static_cast<size_t>(H.blk[b].owner)];
+        ColJob& j = cj[b];
+        j = ColJob{};
+        j.ntiles = sc.tile_end - sc.tile_begin;
+        j.part_off = j.ntiles > 0 ? H.tiles[static_cast<size_t>(sc.tile_begin)].part_off : 0;
+        j.vec_base = sc.vec_base;
+        j.zvec_base = H.pat[static_cast<size_t>(sc.patient)].zvec_base;
+        j.n = sc.n;
+        j.col0 = H.blk[b].col0;
+        j.scen = H.blk[b].owner;
+        j.patient = sc.patient;
+      }
+      c->d_cjobs = c->upload(cj);
+      std::vector<ZJob> zj(H.pblk.size());
+      for (size_t b = 0; b < H.pblk.size(); ++b) {
+        const Pat& pt = H.pat[static_cast<size_t>(H.pblk[b].owner)];
+        zj[b] = ZJob{pt.vec_base, pt.zvec_base, pt.n, pt.num_scen, H.pblk[b].col0, H.pblk[b].owner};
+      }
+      c->d_zjobs = c->upload(zj);
+    }
     c->d_pblk = c->upload(H.pblk);
     const uint32_t* d_rp = c->upload(H.rp);
     const void* d_col = H.col16_used ? static_cast<const void*>(c->upload(H.col16))

@@ -158,11 +158,30 @@ struct PassArgs {
   int32_t unroll;          // rows per lane group in flight: 1, 2 or 4
 };
 
+// Column reduction of the tile partials: one column block of one scenario,
+// with every address its loads need
+struct ColJob {
+  int64_t part_off;   // the scenario's first tile partials
+  int64_t vec_base;   // the scenario in the stacked n-vectors
+  int64_t zvec_base;  // its patient in the per-patient n-vectors
+  int32_t ntiles, n, col0, scen;
+  int32_t patient, pad;
+};
+
+// z-update: one patient column block, with every address its loads need
+struct ZJob {
+  int64_t vec_base;   // the patient's first scenario in the stacked n-vectors
+  int64_t zvec_base;  // the patient in the per-patient n-vectors
+  int32_t n, N, col0, patient;
+};
+
 struct VecArgs {
   const Scen* scen;
   const Pat* pat;
   const Blk* blk;           // scenario column blocks
   const Blk* pblk;          // patient column blocks
+  const ColJob* cjobs;      // one per scenario column block (blk)
+  const ZJob* zjobs;        // one per patient column block (pblk)
   const Tile* tiles;
   const float* part;
   const double* objpart;

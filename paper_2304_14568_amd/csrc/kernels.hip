@@ -40,47 +40,53 @@ void launch_pass(int mode, const PassArgs& a, int tile_begin, int tile_count, hi
 // ---------------------------------------------------------------------------
 
 // Sum of the partial column sums of tiles [0, ntiles) (tile t's partials at
-// part[t * n + j]) for column j: the four waves of the block take every fourth
-// tile, four loads in flight each, then wave 0 adds the four results in a
-// fixed order.  Returns the total in wave 0 (lane = column offset).
+// part[t * n + j]) for column j: the NW waves of the block take every NW-th
+// tile, four loads in flight each, then wave 0 adds the NW results pairwise
+// in a fixed order.  Returns the total in wave 0 (lane = column offset).
+template <int NW>
 __device__ __forceinline__ double tile_column_sum(const float* __restrict__ part, int ntiles, int n, int j,
                                                   double (*red)[64]) {
+  static_assert(NW == 4 || NW == 16, "pairwise tree over 4 or 16 waves");
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (j < n) {
     int t = w;
-    for (; t + 12 < ntiles; t += 16) {
+    for (; t + 3 * NW < ntiles; t += 4 * NW) {
       s0 += static_cast<double>(part[static_cast<int64_t>(t) * n + j]);
-      s1 += static_cast<double>(part[static_cast<int64_t>(t + 4) * n + j]);
-      s2 += static_cast<double>(part[static_cast<int64_t>(t + 8) * n + j]);
-      s3 += static_cast<double>(part[static_cast<int64_t>(t + 12) * n + j]);
+      s1 += static_cast<double>(part[static_cast<int64_t>(t + NW) * n + j]);
+      s2 += static_cast<double>(part[static_cast<int64_t>(t + 2 * NW) * n + j]);
+      s3 += static_cast<double>(part[static_cast<int64_t>(t + 3 * NW) * n + j]);
     }
-    for (; t < ntiles; t += 4) s0 += static_cast<double>(part[static_cast<int64_t>(t) * n + j]);
+    for (; t < ntiles; t += NW) s0 += static_cast<double>(part[static_cast<int64_t>(t) * n + j]);
   }
   red[w][lane] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  return (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  auto q4 = [&](int b) { return (red[b][lane] + red[b + 1][lane]) + (red[b + 2][lane] + red[b + 3][lane]); };
+  if constexpr (NW == 4) return q4(0);
+  else return (q4(0) + q4(4)) + (q4(8) + q4(12));
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, int mode) {
-  __shared__ double red[4][64];
+constexpr int kRedWaves = 16;  // waves per column block of k_reduce
+
+// One workgroup of kRedWaves waves per scenario column block; every address
+// comes from the block's job entry, and the partial sums are requested
+// before the skip test (a skipped block's partials are read and discarded).
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduce(VecArgs a, int blk_begin, int mode) {
+  __shared__ double red[kRedWaves][64];
   const int bi = blk_begin + static_cast<int>(blockIdx.x);
-  const Blk bk = a.blk[bi];
-  const int g = bk.owner;
-  const Scen sc = a.scen[g];
-  const Pat pt = a.pat[sc.patient];
-  PatState* ps = a.ps + sc.patient;
+  const ColJob cj = a.cjobs[bi];
+  PatState* ps = a.ps + cj.patient;
+  bool skip = false;
   if (mode == RED_HEAD || mode == RED_CG) {
-    if (ps->stopped) return;
-    if (mode == RED_CG && !a.act[g * kRing + a.step]) return;
+    skip = ps->stopped != 0;
+    if (mode == RED_CG) skip = skip || !a.act[cj.scen * kRing + a.step];
   }
-  const int j = bk.col0 + static_cast<int>(threadIdx.x & 63);
-  const float* part = a.part + a.tiles[sc.tile_begin].part_off;
-  const double s = tile_column_sum(part, sc.tile_end - sc.tile_begin, sc.n, j, red);
-  if (threadIdx.x >= 64) return;
+  const int j = cj.col0 + static_cast<int>(threadIdx.x & 63);
+  const double s = tile_column_sum<kRedWaves>(a.part + cj.part_off, cj.ntiles, cj.n, j, red);
+  if (skip || threadIdx.x >= 64) return;
   double loc[3] = {0.0, 0.0, 0.0};
-  if (j < sc.n) {
-    const int64_t vi = sc.vec_base + j;
+  if (j < cj.n) {
+    const int64_t vi = cj.vec_base + j;
     if (mode == RED_HEAD) {
       const double rho = ps->rho;
       float yv = a.y[vi];
@@ -88,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, i
         yv = static_cast<float>(static_cast<double>(yv) + ps->tau * a.dprev[vi]);
         a.y[vi] = yv;
       }
-      const float zj = a.z[pt.zvec_base + j];
+      const float zj = a.z[cj.zvec_base + j];
       // residual of B_s x = c_s at x = z:  c_s - B_s z = -A_s^T c_s W (A_s z - p) - y_s / 2
       const float rf = static_cast<float>(-s - 0.5 * static_cast<double>(yv));
       a.r[vi] = rf;
@@ -131,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(VecArgs a, int blk_begin, i
 
 void launch_reduce(int mode, const VecArgs& a, int blk_begin, int nblk, hipStream_t st) {
   if (nblk <= 0) return;
-  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(kThreads), 0, st, a, blk_begin, mode);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(64 * kRedWaves), 0, st, a, blk_begin, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,9 +227,10 @@ void launch_cg_dir(const VecArgs& a, int nblk, hipStream_t st) {
 // workgroup (every quantity is columnwise until the final sums)
 // ---------------------------------------------------------------------------
 
-// One workgroup per 16 columns of a patient block: thread (g, c) = (tid / 16,
-// tid % 16) takes column c and the scenarios s = g, g + 16, ... (one each for
-// N <= 16), so every load of x, y and d_prev is independent of the others.
+// One workgroup per 16 columns of a patient block (addresses from the block's
+// job entry): thread (g, c) = (tid / 16, tid % 16) takes column c and the
+// scenarios s = g, g + 16, ... (one each for N <= 16), so every load of x, y
+// and d_prev is independent of the others.
 // Partial sums over scenarios and columns are combined in a fixed order, so
 // the result does not depend on timing.  Partials: bpartp[(4 * pblk + sub) * 8 + k].
 constexpr int kZCols = 16;
@@ -232,20 +239,18 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   __shared__ float zsh[kZCols];
   __shared__ double sred[4][8];
   const int bi4 = static_cast<int>(blockIdx.x);
-  const Blk bk = a.pblk[bi4 >> 2];
-  const int p = bk.owner;
-  const Pat pt = a.pat[p];
-  const PatState* ps = a.ps + p;
+  const ZJob pt = a.zjobs[bi4 >> 2];
+  const PatState* ps = a.ps + pt.patient;
   const int stopped = ps->stopped;  // read beside the loads below; checked before any write
   const double rho = ps->rho;
   const int tid = threadIdx.x;
   const int col = tid % kZCols, grp = tid / kZCols;
   constexpr int kGroups = kThreads / kZCols;
-  const int j = bk.col0 + (bi4 & 3) * kZCols + col;
+  const int j = pt.col0 + (bi4 & 3) * kZCols + col;
   const bool valid = j < pt.n && (bi4 & 3) * kZCols + col < kColBlock;
   double acc = 0.0;
   if (valid)
-    for (int s = grp; s < pt.num_scen; s += kGroups) {
+    for (int s = grp; s < pt.N; s += kGroups) {
       const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
       acc += static_cast<double>(a.x[vi]);
       if (a.prm.z_mode == 0) acc += static_cast<double>(a.y[vi]) / rho;
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
       double sum = 0.0;
       for (int g = 0; g < kGroups; ++g) sum += sacc[g][col];
       const int64_t zi = pt.zvec_base + j;
-      double zn = sum / pt.num_scen;
+      double zn = sum / pt.N;
       zn = fmin(fmax(zn, static_cast<double>(a.lb[zi])), static_cast<double>(a.ub[zi]));
       znf = static_cast<float>(zn);
       const double dz = static_cast<double>(znf) - static_cast<double>(a.z[zi]);
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   __syncthreads();
   if (valid) {
     const double znd = static_cast<double>(zsh[col]);
-    for (int s = grp; s < pt.num_scen; s += kGroups) {
+    for (int s = grp; s < pt.N; s += kGroups) {
       const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
       const double xv = static_cast<double>(a.x[vi]);
       const double yv = static_cast<double>(a.y[vi]);
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void k_gsum(const Scen* scen, const Pat* 
   const Blk bk = pblk[blk_begin + blockIdx.x];
   const Pat pt = pat[bk.owner];
   const int j = bk.col0 + static_cast<int>(threadIdx.x & 63);
-  const double s = tile_column_sum(part + tiles[pt.tile_begin].part_off, pt.tile_end - pt.tile_begin, pt.n, j, red);
+  const double s = tile_column_sum<4>(part + tiles[pt.tile_begin].part_off, pt.tile_end - pt.tile_begin, pt.n, j, red);
   if (threadIdx.x < 64 && j < pt.n) out[j] = static_cast<float>(scale * s);
 }
 
