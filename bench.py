@@ -80,6 +80,23 @@ def spmv_bytes(P) -> dict:
     return out
 
 
+def host_triad() -> dict:
+    """The host's memory roofline: a STREAM-style triad a = b + s c over three
+    1 GiB float64 arrays with PyTorch's CPU thread pool, best of three; 24
+    bytes per element (two reads, one write)."""
+    import torch
+    n = 1 << 27
+    b = torch.full((n,), 1.0, dtype=torch.float64)
+    c = torch.full((n,), 2.0, dtype=torch.float64)
+    a = torch.empty_like(b)
+    best = float("inf")
+    for _ in range(3):
+        t0 = time.perf_counter()
+        torch.add(b, c, alpha=3.0, out=a)
+        best = min(best, time.perf_counter() - t0)
+    return {"GB/s": 24.0 * n / best / 1e9, "threads": torch.get_num_threads()}
+
+
 def cpu_baseline(P, fstar, budget_s: float = 90.0, progress: bool = False) -> dict:
     """Time the FP64 oracle's ADMM-BB (the paper's algorithm: cached Cholesky
     x-updates, Appendix A) on the whole workload, all 13 scenarios, on this
@@ -144,7 +161,7 @@ def cpu_baseline(P, fstar, budget_s: float = 90.0, progress: bool = False) -> di
             "time_to_1e-5_s": (t_setup + solve_s) if reached else None,
             "time_to_1e-5_solve_only_s": solve_s if reached else None,
             "reached_1e-5": bool(reached), "blas_threads": int(blas_threads),
-            "cpu_busy_cores": busy, "iter_per_s_1_thread": rate1}
+            "cpu_busy_cores": busy, "iter_per_s_1_thread": rate1, "host_triad": host_triad()}
 
 
 def cpu_scaling(args):
