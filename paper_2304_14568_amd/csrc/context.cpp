@@ -833,6 +833,17 @@ struct SetupClock {
 
 }  // namespace
 
+// Device bytes the dense set-up's fp64 matrices (Gram and sweep, npad^2 each
+// per scenario) may take at once: 8 GiB, or ADMMBB_DENSE_CHUNK_MB.
+static int64_t dense_chunk_bytes() {
+  int64_t b = int64_t(8) << 30;
+  if (const char* env = std::getenv("ADMMBB_DENSE_CHUNK_MB")) {
+    const long long mb = std::atoll(env);
+    if (mb > 0) b = static_cast<int64_t>(mb) << 20;
+  }
+  return b;
+}
+
 admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, const admm_options* opts,
                              admm_ctx** out) {
   SetupClock clk;
@@ -914,8 +925,44 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
   }
   c->opts = o;
   clk.mark("validate");
+  // the x-update form, decided before packing (it needs only the sizes and the
+  // free device memory): the dense form runs no CG pass per iteration, so
+  // under the automatic layout choice it gets the chunk-row layout alone
+  {
+    int ndev = 0;
+    (void)hipGetLastError();  // report only this call's errors
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+      return set_err(nullptr, ADMM_E_HIP, "no HIP device available");
+    const int64_t kChunkBytes = dense_chunk_bytes();
+    int64_t need = 0, chunk_need = 0;
+    bool fits_n = true;
+    for (int p = 0; p < num_patients; ++p) {
+      const int64_t n = probs[p].n, N = probs[p].num_scen;
+      const int64_t npad = (n + 63) / 64 * 64, nb = npad / 64, tiles = nb * (nb + 1) / 2;
+      fits_n = fits_n && n <= 8128;
+      const int64_t per_scen = 16 * npad * npad;
+      const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kChunkBytes / per_scen));
+      chunk_need = std::max(chunk_need, chunk * per_scen);
+      // every iteration: packed fp32 inverses, packed fp64 sum of G, tile partials; U, R panels
+      need += tiles * 4096 * (4 * N + 8) + tiles * 1024 * N + 2 * 8 * 64 * npad * N;
+    }
+    need += chunk_need;
+    size_t free_b = 0, total_b = 0;
+    const hipError_t e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return set_err(nullptr, ADMM_E_HIP, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+    if (o.xupdate == ADMM_XUPDATE_DENSE) {
+      if (!fits_n) return set_err(nullptr, ADMM_E_ARG, "dense x-update needs n <= 8128 for every patient");
+      if (static_cast<size_t>(need) > free_b)
+        return set_err(nullptr, ADMM_E_OOM, "dense x-update matrices do not fit in device memory");
+      c->dense = true;
+    } else if (o.xupdate == ADMM_XUPDATE_AUTO) {
+      c->dense = fits_n && static_cast<size_t>(need) <= free_b / 4;
+    }
+  }
+  admm_options po = o;
+  if (c->dense && o.format == ADMM_FORMAT_AUTO) po.format = ADMM_FORMAT_CSR;
   try {
-    st = pack_problems(probs, num_patients, o, &c->H, &msg);
+    st = pack_problems(probs, num_patients, po, &c->H, &msg);
   } catch (const std::bad_alloc&) {
     return set_err(nullptr, ADMM_E_OOM, "host allocation failed");
   } catch (const std::exception& e) {
@@ -924,10 +971,6 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
   if (st != ADMM_OK) return set_err(nullptr, st, msg);
   clk.mark("pack");
   try {
-    int ndev = 0;
-    (void)hipGetLastError();  // report only this call's errors
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
-      return set_err(nullptr, ADMM_E_HIP, "no HIP device available");
     Packed& H = c->H;
     c->P = num_patients;
     c->G = static_cast<int>(H.scen.size());
@@ -958,36 +1001,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     std::vector<XTile> xtiles;
     // dense set-up works on chunks of scenarios: G and the sweep matrix (fp64,
     // npad^2 each) for at most kChunkBytes at a time
-    int64_t kChunkBytes = int64_t(8) << 30;
-    if (const char* env = std::getenv("ADMMBB_DENSE_CHUNK_MB")) {
-      const long long mb = std::atoll(env);
-      if (mb > 0) kChunkBytes = static_cast<int64_t>(mb) << 20;
-    }
-    {
-      int64_t need = 0, chunk_need = 0;
-      bool fits_n = true;
-      for (const Pat& pt : H.pat) {
-        const int64_t npad = (pt.n + 63) / 64 * 64, nb = npad / 64, tiles = nb * (nb + 1) / 2;
-        fits_n = fits_n && pt.n <= 8128;
-        const int64_t per_scen = 16 * npad * npad;
-        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(pt.num_scen, kChunkBytes / per_scen));
-        chunk_need = std::max(chunk_need, chunk * per_scen);
-        // every iteration: packed fp32 inverses, packed fp64 sum of G, tile partials; U, R panels
-        need += tiles * 4096 * (4 * static_cast<int64_t>(pt.num_scen) + 8) + tiles * 1024 * pt.num_scen +
-                2 * 8 * 64 * npad * pt.num_scen;
-      }
-      need += chunk_need;
-      size_t free_b = 0, total_b = 0;
-      check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
-      if (o.xupdate == ADMM_XUPDATE_DENSE) {
-        if (!fits_n) return set_err(nullptr, ADMM_E_ARG, "dense x-update needs n <= 8128 for every patient");
-        if (static_cast<size_t>(need) > free_b)
-          return set_err(nullptr, ADMM_E_OOM, "dense x-update matrices do not fit in device memory");
-        c->dense = true;
-      } else if (o.xupdate == ADMM_XUPDATE_AUTO) {
-        c->dense = fits_n && static_cast<size_t>(need) <= free_b / 4;
-      }
-    }
+    const int64_t kChunkBytes = dense_chunk_bytes();
     if (c->dense) {
       int64_t chunk_elems = 0, moff = 0, goff = 0;
       c->chunk_scen.assign(num_patients, 1);

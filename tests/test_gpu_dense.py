@@ -111,9 +111,25 @@ def test_dense_batch_and_cg_agree_on_the_minimum(probs):
 
 
 def test_auto_selects_dense_for_small_problems(probs):
+    """The form is chosen before packing: the dense form gets the chunk-row
+    layout alone under the automatic layout choice, the sliced one only when
+    asked for (its passes then agree with the chunk-row ones)."""
     import paper_2304_14568_amd as A
-    with A.Solver(probs[0][0], xupdate="auto") as S:
+    P, W = probs[1][0], probs[1][1]
+    with A.Solver(P, xupdate="auto") as S:
         assert S.xupdate()[0] == "dense"
+        assert S.tuning()["format"] == "csr"
+        v = np.linspace(0.1, 1.0, P.n).astype(np.float32)
+        q_csr = S.normal_apply(v, 1)
+        rho = S.rho()
+    with A.Solver(P, xupdate="auto", format="sell") as S:
+        assert S.xupdate()[0] == "dense"
+        assert S.tuning()["format"] == "sell"
+        q_sell = S.normal_apply(v, 1)
+    ref = wls.normal_apply(W, 1, v, rho)
+    scale = wls.normal_apply_abs(W, 1, v, rho)
+    assert np.all(np.abs(q_csr - ref) <= 1e-6 * scale)
+    assert np.all(np.abs(q_sell - ref) <= 1e-6 * scale)
     with A.Solver(probs[0][0], xupdate="cg") as S:
         assert S.xupdate()[0] == "cg"
 
