@@ -154,9 +154,10 @@ typedef struct {
                           ADMM_FORMAT_SELL: sliced, the rows of a tile in slices of 64 / L rows with
                             their chunks interleaved so that a wave load reads 64 consecutive chunks
                             (16-bit column indices only, n <= 65535);
-                          ADMM_FORMAT_AUTO (default): both are built and the set-up autotuner
-                            picks the faster for the CG pass (the chunk-row one with the dense
-                            x-update, where the tuner does not run) */
+                          ADMM_FORMAT_AUTO (default): with the CG x-update both are built and
+                            the set-up autotuner picks the faster for each patient's CG pass;
+                            with the dense x-update, where the tuner does not run, only the
+                            chunk-row one is built */
   int32_t deterministic; /* 1: every sum of an iteration is exact or in a fixed order (64-bit
                           fixed-point column accumulators, lds_acc -1 or 2 required), so runs and
                           resumed runs repeat bit for bit; default 0 (the autotuner may pick fp64
@@ -351,9 +352,10 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
 admm_status admm_get_trace(admm_ctx* ctx, int32_t patient, admm_info* buf, int32_t cap, int32_t* count);
 
 /* Fused-pass configuration in use (picked by the set-up autotuner unless fixed
- * in the options): workgroup size, rows in flight per lane group, LDS
- * accumulator kind, and the measured average pass time in ms of the chosen one
- * (all scenarios, fp32 or the CG value precision). */
+ * in the options), of patient 0 (admm_get_pass_config gives every patient's):
+ * workgroup size, rows in flight per lane group, LDS accumulator kind, and the
+ * measured average pass time in ms of the chosen configurations summed over
+ * the patients (all scenarios, fp32 or the CG value precision). */
 admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms);
 /* The sparse-pass configuration of one patient of the context (the passes are
    launched once per patient, each with its own; the set-up autotuner of the CG
@@ -365,8 +367,9 @@ admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unro
 admm_status admm_get_pass_config(const admm_ctx* ctx, int32_t patient, int32_t* threads, int32_t* unroll,
                                  int32_t* lds_acc, int32_t* format, double* ms);
 
-/* Layout of A_s the sparse passes read (ADMM_FORMAT_CSR or ADMM_FORMAT_SELL):
- * the one asked for, or the set-up autotuner's pick under ADMM_FORMAT_AUTO. */
+/* Layout of A_s the sparse passes of patient 0 read (ADMM_FORMAT_CSR or
+ * ADMM_FORMAT_SELL): the one asked for, or under ADMM_FORMAT_AUTO the set-up
+ * autotuner's pick (chunk-row with the dense x-update). */
 admm_status admm_get_format(const admm_ctx* ctx, int32_t* format);
 
 /* CG steps performed per scenario of a patient since its last reset
