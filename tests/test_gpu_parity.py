@@ -64,6 +64,52 @@ def test_matvec_rmatvec_parity(tiny, small, tile_nnz, fmt):
                 _spmv_check(S.rmatvec(t, s), wls.rmatvec(W, s, t), wls.rmatvec_abs(W, s, t))
 
 
+def test_every_pass_configuration_gives_the_same_bits(small):
+    """Every workgroup size (256, 512, 1024) and row pipelining of the
+    chunk-row pass, with 64-bit fixed-point column sums: each row's dot is
+    formed by the same lanes in the same order and the column sums are exact,
+    so B_s v is the same bit for bit in every configuration, and within the
+    per-entry bound of the fp64 product."""
+    P, W, _, _ = small
+    rng = np.random.default_rng(12)
+    vs = [rng.normal(size=P.n).astype(np.float32) for _ in range(2)]
+    outs = {}
+    for threads in (256, 512, 1024):
+        for unroll in (1, 2):
+            with _solver(P, pass_threads=threads, pass_unroll=unroll, lds_acc=2, format="csr", xupdate="cg") as S:
+                cfg = S.tuning(0)
+                assert (cfg["threads"], cfg["unroll"], cfg["lds_acc"], cfg["format"]) == (threads, unroll, 2, "csr")
+                rho = S.rho()
+                outs[(threads, unroll)] = [S.normal_apply(v, s) for v in vs for s in (0, P.num_scen - 1)]
+    first = outs[(256, 1)]
+    for key, got in outs.items():
+        for a, b in zip(first, got):
+            assert np.array_equal(a, b), key
+    k = 0
+    for v in vs:
+        for s in (0, P.num_scen - 1):
+            _spmv_check(first[k], wls.normal_apply(W, s, v, rho), wls.normal_apply_abs(W, s, v, rho))
+            k += 1
+
+
+def test_pass_configuration_chosen_per_patient(tiny, small):
+    """The set-up autotuner keeps a configuration per patient of a batch, each
+    one of the measured candidates, with its pass time."""
+    import paper_2304_14568_amd as A
+    with _solver([tiny[0], small[0]], xupdate="cg") as S:
+        for p in (0, 1):
+            cfg = S.tuning(p)
+            assert cfg["threads"] in (256, 512, 1024)
+            assert cfg["unroll"] in (1, 2)
+            assert cfg["lds_acc"] in (1, 2)
+            assert cfg["format"] in ("csr", "sell")
+            assert cfg["pass_ms"] > 0.0
+            if cfg["format"] == "sell":
+                assert cfg["threads"] <= 512 and cfg["unroll"] == 1
+        with pytest.raises(A.AdmmError):
+            S.tuning(2)
+
+
 @pytest.mark.parametrize("fmt", ["csr", "sell"])
 @pytest.mark.parametrize("lds_acc", [0, 1, 2])
 def test_normal_apply_parity(small, lds_acc, fmt):
