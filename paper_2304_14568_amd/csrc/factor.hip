@@ -586,10 +586,12 @@ __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __rest
 }
 
 // x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
-// (T_JI^T c_J).  Wave w adds the blocks J = w, w + 4, ...; the four partial
-// sums are then added in a fixed order.
-__global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
-  __shared__ double part[4][kFb];
+// (T_JI^T c_J).  Wave w of kXrWaves adds the blocks J = w, w + kXrWaves, ...;
+// the wave sums are then added pairwise in a fixed order.
+constexpr int kXrWaves = 8;  // the final sum below adds eight wave sums
+static_assert(kXrWaves == 8, "the pairwise sum of the wave sums is written out for eight waves");
+__global__ __launch_bounds__(64 * kXrWaves) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
+  __shared__ double part[kXrWaves][kFb];
   const RJob job = f.rjobs[blockIdx.x];
   const int I = job.I, nb = job.nb;
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
@@ -601,18 +603,20 @@ __global__ __launch_bounds__(256) void k_xsym_reduce(FactorArgs f, float* __rest
     return (J < I) ? base[tile_index(J, I, nb) * (2 * kFb) + kFb + i] : base[tile_index(I, J, nb) * (2 * kFb) + i];
   };
   int J = w;
-  for (; J + 12 < nb; J += 16) {
+  for (; J + 3 * kXrWaves < nb; J += 4 * kXrWaves) {
     s0 += ld(J);
-    s1 += ld(J + 4);
-    s2 += ld(J + 8);
-    s3 += ld(J + 12);
+    s1 += ld(J + kXrWaves);
+    s2 += ld(J + 2 * kXrWaves);
+    s3 += ld(J + 3 * kXrWaves);
   }
-  for (; J < nb; J += 4) s0 += ld(J);
+  for (; J < nb; J += kXrWaves) s0 += ld(J);
   part[w][i] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   if (w == 0 && !stopped) {
     const int row = I * kFb + i;
-    if (row < job.n) x[job.vbase + row] = static_cast<float>((part[0][i] + part[1][i]) + (part[2][i] + part[3][i]));
+    if (row < job.n)
+      x[job.vbase + row] = static_cast<float>(((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) +
+                                              ((part[4][i] + part[5][i]) + (part[6][i] + part[7][i])));
   }
 }
 
@@ -907,7 +911,7 @@ void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st
 
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st) {
   if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(256), 0, st, f, x);
+  hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(64 * kXrWaves), 0, st, f, x);
 }
 
 void launch_dense_tail(const FactorArgs& f, const VecArgs& a, int nfobj, hipStream_t st) {

@@ -248,12 +248,29 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
   constexpr int kGroups = kThreads / kZCols;
   const int j = pt.col0 + (bi4 & 3) * kZCols + col;
   const bool valid = j < pt.n && (bi4 & 3) * kZCols + col < kColBlock;
+  // every input of the thread's first scenario (s = grp) and of the
+  // projection, requested at once
+  const bool first = valid && grp < pt.N;
+  const int64_t vi0 = pt.vec_base + static_cast<int64_t>(grp) * pt.n + j;
+  const int64_t zi = pt.zvec_base + j;
+  float x0 = 0.0f, y0 = 0.0f, lbv = 0.0f, ubv = 0.0f, zold = 0.0f;
+  double dp0 = 0.0;
+  if (first) {
+    x0 = a.x[vi0];
+    y0 = a.y[vi0];
+    dp0 = a.dprev[vi0];
+  }
+  if (valid && grp == 0) {
+    lbv = a.lb[zi];
+    ubv = a.ub[zi];
+    zold = a.z[zi];
+  }
   double acc = 0.0;
   if (valid)
     for (int s = grp; s < pt.N; s += kGroups) {
       const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
-      acc += static_cast<double>(a.x[vi]);
-      if (a.prm.z_mode == 0) acc += static_cast<double>(a.y[vi]) / rho;
+      acc += static_cast<double>(s == grp ? x0 : a.x[vi]);
+      if (a.prm.z_mode == 0) acc += static_cast<double>(s == grp ? y0 : a.y[vi]) / rho;
     }
   if (stopped) return;  // the whole workgroup: one patient
   sacc[grp][col] = acc;
@@ -265,11 +282,10 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
     if (valid) {
       double sum = 0.0;
       for (int g = 0; g < kGroups; ++g) sum += sacc[g][col];
-      const int64_t zi = pt.zvec_base + j;
       double zn = sum / pt.N;
-      zn = fmin(fmax(zn, static_cast<double>(a.lb[zi])), static_cast<double>(a.ub[zi]));
+      zn = fmin(fmax(zn, static_cast<double>(lbv)), static_cast<double>(ubv));
       znf = static_cast<float>(zn);
-      const double dz = static_cast<double>(znf) - static_cast<double>(a.z[zi]);
+      const double dz = static_cast<double>(znf) - static_cast<double>(zold);
       a.z[zi] = znf;
       v[0] = dz * dz;
       v[1] = static_cast<double>(znf) * znf;
@@ -281,10 +297,10 @@ __global__ __launch_bounds__(kThreads) void k_zres(VecArgs a) {
     const double znd = static_cast<double>(zsh[col]);
     for (int s = grp; s < pt.N; s += kGroups) {
       const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
-      const double xv = static_cast<double>(a.x[vi]);
-      const double yv = static_cast<double>(a.y[vi]);
+      const double xv = static_cast<double>(s == grp ? x0 : a.x[vi]);
+      const double yv = static_cast<double>(s == grp ? y0 : a.y[vi]);
       const double d = xv - znd;
-      const double dp = a.dprev[vi];
+      const double dp = s == grp ? dp0 : a.dprev[vi];
       const double dd = d - dp;
       v[2] += d * d;
       v[3] += dd * dp;
