@@ -64,31 +64,36 @@ def test_matvec_rmatvec_parity(tiny, small, tile_nnz, fmt):
                 _spmv_check(S.rmatvec(t, s), wls.rmatvec(W, s, t), wls.rmatvec_abs(W, s, t))
 
 
-def test_every_pass_configuration_gives_the_same_bits(small):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_every_pass_configuration_gives_the_same_bits(small, precision):
     """Every workgroup size (256, 512, 1024) and row pipelining of the
     chunk-row pass, with 64-bit fixed-point column sums: each row's dot is
     formed by the same lanes in the same order and the column sums are exact,
     so B_s v is the same bit for bit in every configuration, and within the
-    per-entry bound of the fp64 product."""
+    per-entry bound of the fp64 product (for bf16 values, the bound of their
+    rounding: 2.5 units of 2^-8)."""
     P, W, _, _ = small
     rng = np.random.default_rng(12)
     vs = [rng.normal(size=P.n).astype(np.float32) for _ in range(2)]
     outs = {}
     for threads in (256, 512, 1024):
         for unroll in (1, 2):
-            with _solver(P, pass_threads=threads, pass_unroll=unroll, lds_acc=2, format="csr", xupdate="cg") as S:
+            with _solver(P, pass_threads=threads, pass_unroll=unroll, lds_acc=2, format="csr", xupdate="cg",
+                         precision=precision) as S:
                 cfg = S.tuning(0)
                 assert (cfg["threads"], cfg["unroll"], cfg["lds_acc"], cfg["format"]) == (threads, unroll, 2, "csr")
                 rho = S.rho()
-                outs[(threads, unroll)] = [S.normal_apply(v, s) for v in vs for s in (0, P.num_scen - 1)]
+                outs[(threads, unroll)] = [S.normal_apply(v, s, precision=precision)
+                                           for v in vs for s in (0, P.num_scen - 1)]
     first = outs[(256, 1)]
     for key, got in outs.items():
         for a, b in zip(first, got):
             assert np.array_equal(a, b), key
+    tol = SPMV_TOL if precision == "fp32" else 2.5 * 2.0 ** -8
     k = 0
     for v in vs:
         for s in (0, P.num_scen - 1):
-            _spmv_check(first[k], wls.normal_apply(W, s, v, rho), wls.normal_apply_abs(W, s, v, rho))
+            _spmv_check(first[k], wls.normal_apply(W, s, v, rho), wls.normal_apply_abs(W, s, v, rho), tol=tol)
             k += 1
 
 

@@ -67,15 +67,19 @@ def test_reduced_precision_reaches_fp32_objective(patients, precision):
         assert np.all(np.abs(got - ref) <= 2.5 * u * scale + floor + 1e-30)
 
 
-def test_large_spot_count_uses_extended_lds():
-    """n > 5461 needs more than 64 KB of LDS for the column accumulators."""
+@pytest.mark.parametrize("threads", [0, 512, 1024])
+def test_large_spot_count_uses_extended_lds(threads):
+    """n > 5461 needs more than 64 KB of LDS for the column accumulators: one
+    workgroup per CU, of 512 or 1024 threads (0: the autotuner's choice)."""
     import paper_2304_14568_amd as A
     P = synth.make_hn(seed=7, grid=(64, 64, 40), body_semi_vox=(28, 22, 16), target_size=0.8, num_layers=14,
                       spot_spacing=2.5, num_scen=2)
     assert 12 * P.n > 65536
     W = wls.from_problem(P)
     rng = np.random.default_rng(4)
-    with A.Solver(P, max_iter=400, lds_acc=2, xupdate="cg") as S:
+    with A.Solver(P, max_iter=400, lds_acc=2, xupdate="cg", pass_threads=threads) as S:
+        if threads:
+            assert S.tuning(0)["threads"] == threads
         for s in range(P.num_scen):
             v = rng.normal(size=P.n).astype(np.float32)
             got = S.normal_apply(v, s)
