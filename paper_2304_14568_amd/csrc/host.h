@@ -12,9 +12,24 @@
 
 namespace admmbb {
 
+// Host memory of the packed arrays: page-locked (hipHostMalloc) while a
+// packing has pinned budget left and the block is large, so that its upload
+// runs at the link's DMA rate; otherwise (or when no device is there) the
+// ordinary heap.  host_free releases either kind.
+void* host_alloc(size_t bytes);
+void host_free(void* p) noexcept;
+// Pinned budget of the packing on this thread (bytes; 0 = none), restored on
+// scope exit.
+struct PinnedBudget {
+  explicit PinnedBudget(size_t bytes);
+  ~PinnedBudget();
+  size_t saved;
+};
+
 // Allocator whose value-less construct leaves elements uninitialised: for the
 // large packed arrays, every element of which the (parallel) packing writes,
-// so that growing them costs no single-threaded zero fill.
+// so that growing them costs no single-threaded zero fill.  Storage from
+// host_alloc.
 template <class T>
 struct NoInit : std::allocator<T> {
   template <class U>
@@ -24,6 +39,8 @@ struct NoInit : std::allocator<T> {
   NoInit() = default;
   template <class U>
   NoInit(const NoInit<U>&) {}
+  T* allocate(size_t n) { return static_cast<T*>(host_alloc(n * sizeof(T))); }
+  void deallocate(T* p, size_t) noexcept { host_free(p); }
   template <class U, class... Args>
   void construct(U* p, Args&&... args) {
     if constexpr (sizeof...(Args) == 0)
@@ -32,6 +49,14 @@ struct NoInit : std::allocator<T> {
       ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
   }
 };
+template <class T, class U>
+bool operator==(const NoInit<T>&, const NoInit<U>&) {
+  return true;
+}
+template <class T, class U>
+bool operator!=(const NoInit<T>&, const NoInit<U>&) {
+  return false;
+}
 template <class T>
 using RawVec = std::vector<T, NoInit<T>>;
 

@@ -18,11 +18,58 @@
 #include <numeric>
 #include <stdexcept>
 #include <system_error>
+#include <mutex>
+#include <new>
 #include <thread>
+#include <unordered_set>
 
 #include "host.h"
 
 namespace admmbb {
+
+namespace {
+std::atomic<int64_t> g_pin_budget{0};  // bytes the packing may still place in pinned memory
+std::mutex g_pin_mu;
+std::unordered_set<void*> g_pinned;  // blocks from hipHostMalloc
+constexpr size_t kPinMin = size_t{1} << 20;
+}  // namespace
+
+void* host_alloc(size_t bytes) {
+  if (bytes >= kPinMin) {
+    int64_t left = g_pin_budget.load();
+    while (left >= static_cast<int64_t>(bytes) &&
+           !g_pin_budget.compare_exchange_weak(left, left - static_cast<int64_t>(bytes))) {
+    }
+    if (left >= static_cast<int64_t>(bytes)) {
+      void* p = nullptr;
+      if (hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess && p != nullptr) {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        g_pinned.insert(p);
+        return p;
+      }
+      (void)hipGetLastError();  // no device or no pinned memory: the heap serves
+      g_pin_budget.fetch_add(static_cast<int64_t>(bytes));
+    }
+  }
+  return ::operator new(bytes);
+}
+
+void host_free(void* p) noexcept {
+  if (p == nullptr) return;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pinned.find(p);
+    if (it != g_pinned.end()) {
+      g_pinned.erase(it);
+      (void)hipHostFree(p);
+      return;
+    }
+  }
+  ::operator delete(p);
+}
+
+PinnedBudget::PinnedBudget(size_t bytes) : saved(static_cast<size_t>(g_pin_budget.exchange(static_cast<int64_t>(bytes)))) {}
+PinnedBudget::~PinnedBudget() { g_pin_budget.store(static_cast<int64_t>(saved)); }
 
 uint16_t to_bf16_bits(float v) {
   uint32_t u;
@@ -187,6 +234,9 @@ void parallel_for(int count, F&& fn) {
 admm_status pack_problems(const admm_problem* probs, int num_patients, const admm_options& o, Packed* out,
                           std::string* msg) {
   Packed& P = *out;
+  // the packed arrays go to the device next: up to 4 GiB of them in pinned
+  // memory, which the upload reads at the link's DMA rate
+  PinnedBudget pin(size_t{4} << 30);
   int64_t nnz_all = 0;
   for (int p = 0; p < num_patients; ++p)
     for (int s = 0; s < probs[p].num_scen; ++s) nnz_all += probs[p].A[s].nnz;
@@ -344,7 +394,20 @@ admm_status pack_problems(const admm_problem* probs, int num_patients, const adm
         t.cmax = round_up(cm);
         r.tiles.push_back(t);
       };
+      // rows are visited in the sorted order, so their source entries are
+      // scattered: the entries of the row kPrefetch places ahead are requested
+      // early, and the row pointers of the one twice as far
+      constexpr int64_t kPrefetch = 8;
       for (int64_t q = 0; q < r.rows; ++q) {
+        if (q + 2 * kPrefetch < r.rows) __builtin_prefetch(A.row_ptr + order[static_cast<size_t>(q + 2 * kPrefetch)]);
+        if (q + kPrefetch < r.rows) {
+          const int ia = order[static_cast<size_t>(q + kPrefetch)];
+          const int64_t ba = A.row_ptr[ia], ea = A.row_ptr[ia + 1];
+          for (int64_t t = ba; t < ea; t += 16) __builtin_prefetch(A.col + t);
+          for (int64_t t = ba; t < ea; t += 16) __builtin_prefetch(A.val + t);
+          __builtin_prefetch(pr.presc + ia);
+          __builtin_prefetch(pr.struct_id + ia);
+        }
         const int i = order[static_cast<size_t>(q)];
         const int64_t b = A.row_ptr[i], e = A.row_ptr[i + 1];
         const int64_t len = e - b, len4 = (len + 3) & ~int64_t(3);
