@@ -12,6 +12,7 @@
 #include <limits>
 #include <memory>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <system_error>
 #include <thread>
@@ -121,7 +122,7 @@ struct admm_ctx {
   double* d_rw64 = nullptr;
   RJob* d_rjobs = nullptr;
   XJob* d_fjobs = nullptr;
-  int64_t* d_fobj_off = nullptr;
+  uint32_t* d_Gq = nullptr;
   XTile* d_xtiles = nullptr;
   int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
   int64_t gp_elems = 0;
@@ -319,7 +320,7 @@ struct admm_ctx {
     f.nxtiles = n_xjobs;
     f.rjobs = d_rjobs;
     f.fjobs = d_fjobs;
-    f.fobj_off = d_fobj_off;
+    f.Gq = d_Gq;
     f.fpart = d_fpart;
     f.npmax = ld_max;
     return f;
@@ -997,7 +998,6 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     // dense x-update: sizes, offsets and work lists (before the tables go to the device)
     std::vector<RJob> rjobs;
     std::vector<XJob> fjobs;
-    std::vector<int64_t> fobj_off;
     std::vector<XTile> xtiles;
     // dense set-up works on chunks of scenarios: G and the sweep matrix (fp64,
     // npad^2 each) for at most kChunkBytes at a time
@@ -1021,7 +1021,10 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
         for (int I = 0; I < pt.nbk; ++I)
           for (int J = I; J < pt.nbk; ++J) {
             // the upper tiles in row-major order: the job's rank is the tile's index
-            fobj_off.push_back(pt.gpack_off + static_cast<int64_t>(fjobs.size() - pt.fobj_begin) * 4096);
+            // objective job k is the tile stored at 4096 k of Gp (6144 k words of Gq)
+            if (pt.gpack_off + static_cast<int64_t>(fjobs.size() - pt.fobj_begin) * 4096 !=
+                static_cast<int64_t>(fjobs.size()) * 4096)
+              throw std::logic_error("objective tile list out of storage order");
             fjobs.push_back(XJob{p, I * 65536 + J});
           }
         pt.fobj_end = static_cast<int32_t>(fjobs.size());
@@ -1034,9 +1037,9 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
             for (int J = I; J < pt.nbk; ++J) {
               XTile xt{};
               const int64_t t = static_cast<int64_t>(I) * pt.nbk - static_cast<int64_t>(I) * (I - 1) / 2 + (J - I);
-              xt.moff = sc.mpack_off + t * 4096;
+              if (sc.mpack_off / 4096 + t != static_cast<int64_t>(xtiles.size()))
+                throw std::logic_error("dense tile table out of storage order");
               xt.vbase = sc.vec_base;
-              xt.pidx = sc.mpack_off / 4096 + t;
               xt.n = pt.n;
               xt.patient = p;
               xt.I = I;
@@ -1064,7 +1067,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       c->d_xtiles = c->upload(xtiles);
       c->d_rjobs = c->upload(rjobs);
       c->d_fjobs = c->upload(fjobs);
-      c->d_fobj_off = c->upload(fobj_off);
+      c->d_Gq = c->alloc<uint32_t>(static_cast<size_t>(goff / 4096) * 6144);
       std::vector<double> g0all(static_cast<size_t>(H.zvec_total));
       for (int p = 0; p < num_patients; ++p)
         std::copy(H.g0[p].begin(), H.g0[p].end(), g0all.begin() + H.pat[p].zvec_base);
@@ -1192,6 +1195,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       check(hipEventRecord(f0, c->stream), "hipEventRecord");
       launch_fill_f64(c->d_Gp, 0.0, c->gp_elems, c->stream);
       for (int p = 0; p < num_patients; ++p) c->factorize(p, true);
+      launch_gq_pack(c->d_Gp, c->d_Gq, c->gp_elems / 4096, c->stream);
       check(hipEventRecord(f1, c->stream), "hipEventRecord");
       check(hipEventSynchronize(f1), "hipEventSynchronize");
       float ms = 0.0f;

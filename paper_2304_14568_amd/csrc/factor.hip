@@ -28,6 +28,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.h"
@@ -493,11 +494,12 @@ __global__ __launch_bounds__(256) void k_sweep_update(FactorArgs f, int scen_beg
 }
 
 // Position of entry (r, c) inside a stored 64 x 64 tile of M_s.  Thread t of
-// the x-update holds row t / 4, columns 16 (t % 4) .. + 15 as four float4
-// (k = 0..3); float4 k of thread t is stored at k * 256 + t, so that every
-// wave load instruction of the x-update reads 1 KiB contiguous.
+// the x-update holds the 4 x 4 block of rows 4 (t / 16) .. + 3 and columns
+// 4 (t % 16) .. + 3 as four float4 (row k = 0..3 of the block); float4 k of
+// thread t is stored at k * 256 + t, so that every wave load instruction of
+// the x-update reads 1 KiB contiguous.
 __host__ __device__ __forceinline__ int xtile_pos(int r, int c) {
-  return 4 * (((c >> 2) & 3) * 256 + 4 * r + (c >> 4)) + (c & 3);
+  return 4 * ((r & 3) * 256 + (r >> 2) * 16 + (c >> 2)) + (c & 3);
 }
 
 // packed M = -A (upper tiles) in fp32, for the chunk of scenarios starting at scen_begin
@@ -520,69 +522,119 @@ __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, 
 // per-iteration kernels
 // ---------------------------------------------------------------------------
 
+// x from lane (lane ^ 1) or (lane ^ 2) of the same quad, or from lane
+// (lane - n) mod 16 of the same row of 16 lanes: one DPP move per 32-bit half,
+// no LDS.
+constexpr int kDppXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppRor4 = 0x124;
+constexpr int kDppRor8 = 0x128;
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(v >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
 // One packed tile T = M_s[I, J] (I <= J) per workgroup: a = T c_J and, off
 // the diagonal, b = T^T c_I (the tile's contribution to the rows of block J).
-// Thread t holds row t/4, columns 16 (t%4) .. +15 (four float4 loads, each a
-// 1 KiB contiguous read per wave in the stored order of xtile_pos).  The
-// tile table entry carries every address, so the tile load depends on one
-// table read only.  The right-hand side and all sums are fp64: the inverse
-// has entries of both signs and |M| |c| exceeds |M c| by two orders of
-// magnitude, so fp32 sums would put a floor of about 1e-5 relative under every
-// x-update; the fp32 storage of M itself contributes about 1e-6.
+// Thread t holds the 4 x 4 block at rows 4 rb, columns 4 cb (rb = t / 16,
+// cb = t % 16; four float4 loads, each a 1 KiB contiguous read per wave in
+// the stored order of xtile_pos), so both products use the registers as
+// loaded: the row sums are reduced over the 16 lanes of a DPP row, the column
+// sums over the wave's four rows by shuffles and over the four waves in
+// shared memory.  The tile table entry carries every address, so the tile
+// load depends on one table read only.  The right-hand side and all sums are
+// fp64: the inverse has entries of both signs and |M| |c| exceeds |M c| by two
+// orders of magnitude, so fp32 sums would put a floor of about 1e-5 relative
+// under every x-update; the fp32 storage of M itself contributes about 1e-6.
 __device__ __forceinline__ void xsym_tile(const FactorArgs& f, const double* __restrict__ c, int idx) {
-  __shared__ float tl[kFb][kFb + 1];  // the tile again, read by columns for T^T c_I
-  __shared__ double cI[kFb], cJ[kFb];
-  const XTile tj = f.xtiles[idx];
+  __shared__ double2 cI[kFb / 2], cJ[kFb / 2];
+  __shared__ double bpart[4][kFb];  // column sums of each wave
   const int tid = threadIdx.x;
-  const int i = tid >> 2, q = tid & 3;
-  // the tile's 16 KB, in flight before anything else
-  const float4* T = reinterpret_cast<const float4*>(f.Mp + tj.moff);
+  const int rb = tid >> 4, cb = tid & 15, lane = tid & 63;
+  // the tile's 16 KB (tile idx of the table is stored at Mp + 4096 idx) does
+  // not wait for the table; the empty statement keeps the compiler from moving
+  // the loads below the early exit
+  const float4* T = reinterpret_cast<const float4*>(f.Mp) + static_cast<int64_t>(idx) * 1024;
   float4 m[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) m[k] = T[k * 256 + tid];
-  if (f.ps[tj.patient].stopped) return;
+  const XTile tj = f.xtiles[idx];
+  const bool stopped = f.ps[tj.patient].stopped != 0;
+  asm volatile("" ::: "memory");
+  if (stopped) return;
   if (tid < kFb) {
     const int jc = tj.J * kFb + tid, ic = tj.I * kFb + tid;
-    cJ[tid] = jc < tj.n ? c[tj.vbase + jc] : 0.0;
-    cI[tid] = ic < tj.n ? c[tj.vbase + ic] : 0.0;
-  }
-  const bool offdiag = tj.I != tj.J;
-  if (offdiag) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int j0 = 16 * q + 4 * k;
-      tl[i][j0 + 0] = m[k].x;
-      tl[i][j0 + 1] = m[k].y;
-      tl[i][j0 + 2] = m[k].z;
-      tl[i][j0 + 3] = m[k].w;
-    }
+    reinterpret_cast<double*>(cJ)[tid] = jc < tj.n ? c[tj.vbase + jc] : 0.0;
+    reinterpret_cast<double*>(cI)[tid] = ic < tj.n ? c[tj.vbase + ic] : 0.0;
   }
   __syncthreads();
-  double a = 0.0;
+  // a: row 4 rb + k over this block's four columns
+  const double2 j01 = cJ[2 * cb], j23 = cJ[2 * cb + 1];
+  double a[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int j0 = 16 * q + 4 * k;
-    a = fma(static_cast<double>(m[k].x), cJ[j0 + 0], a);
-    a = fma(static_cast<double>(m[k].y), cJ[j0 + 1], a);
-    a = fma(static_cast<double>(m[k].z), cJ[j0 + 2], a);
-    a = fma(static_cast<double>(m[k].w), cJ[j0 + 3], a);
+    double v = static_cast<double>(m[k].x) * j01.x;
+    v = fma(static_cast<double>(m[k].y), j01.y, v);
+    v = fma(static_cast<double>(m[k].z), j23.x, v);
+    a[k] = fma(static_cast<double>(m[k].w), j23.y, v);
   }
-  a += __shfl_xor(a, 1, 64);
-  a += __shfl_xor(a, 2, 64);
-  double* out = f.xpart + tj.pidx * (2 * kFb);
-  if (q == 0) out[i] = a;
-  if (!offdiag) return;
-  // b over rows 16 q .. 16 q + 15 of column i
-  double bsum = 0.0;
+  // sum over the 16 column blocks (the lanes of one DPP row), scattered so
+  // that lane cb ends with row 4 rb + (cb % 4): lane pairs (xor 1) keep rows of
+  // their own parity, quad pairs (xor 2) one row each, then the four lanes of
+  // a row add up by rotations of 4 and 8
+  const bool b0 = (cb & 1) != 0, b1 = (cb & 2) != 0;
+  double k0 = b0 ? a[1] : a[0], k1 = b0 ? a[3] : a[2];
+  k0 += dpp_f64<kDppXor1>(b0 ? a[0] : a[1]);
+  k1 += dpp_f64<kDppXor1>(b0 ? a[2] : a[3]);
+  double r = (b1 ? k1 : k0) + dpp_f64<kDppXor2>(b1 ? k0 : k1);
+  r += dpp_f64<kDppRor8>(r);
+  r += dpp_f64<kDppRor4>(r);
+  double* out = f.xpart + static_cast<int64_t>(idx) * (2 * kFb);
+  if (cb < 4) out[4 * rb + cb] = r;
+  if (tj.I == tj.J) return;
+  // b: column 4 cb + j over this block's four rows
+  const double2 i01 = cI[2 * rb], i23 = cI[2 * rb + 1];
+  double bv[4];
+  {
+    const float* m0 = reinterpret_cast<const float*>(&m[0]);
+    const float* m1 = reinterpret_cast<const float*>(&m[1]);
+    const float* m2 = reinterpret_cast<const float*>(&m[2]);
+    const float* m3 = reinterpret_cast<const float*>(&m[3]);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) bsum = fma(static_cast<double>(tl[16 * q + r][i]), cI[16 * q + r], bsum);
-  bsum += __shfl_xor(bsum, 1, 64);
-  bsum += __shfl_xor(bsum, 2, 64);
-  if (q == 0) out[kFb + i] = bsum;
+    for (int j = 0; j < 4; ++j) {
+      double v = static_cast<double>(m0[j]) * i01.x;
+      v = fma(static_cast<double>(m1[j]), i01.y, v);
+      v = fma(static_cast<double>(m2[j]), i23.x, v);
+      bv[j] = fma(static_cast<double>(m3[j]), i23.y, v);
+    }
+  }
+  // sum over the wave's four row blocks (lane bits 4 and 5), scattered so
+  // that the lane ends with column 4 cb + lane / 16
+  const bool g0 = (lane & 16) != 0, g1 = (lane & 32) != 0;
+  double h0 = g0 ? bv[1] : bv[0], h1 = g0 ? bv[3] : bv[2];
+  h0 += __shfl_xor(g0 ? bv[0] : bv[1], 16, 64);
+  h1 += __shfl_xor(g0 ? bv[2] : bv[3], 16, 64);
+  const double u = (g1 ? h1 : h0) + __shfl_xor(g1 ? h0 : h1, 32, 64);
+  bpart[tid >> 6][4 * cb + (lane >> 4)] = u;
+  __syncthreads();
+  if (tid < kFb) out[kFb + tid] = (bpart[0][tid] + bpart[1][tid]) + (bpart[2][tid] + bpart[3][tid]);
+}
+
+// Table index of the tile that workgroup b of an x-update launch takes: the
+// order reverses from one iteration to the next (by the parity of the first
+// patient's iteration count, which only the previous launches write), so that
+// an iteration starts on the tiles the last one read most recently, while
+// they may still sit in the memory-side cache.  Every tile is taken once
+// either way, and the results do not depend on the order.
+__device__ __forceinline__ int xsym_order(const FactorArgs& f, int b) {
+  return (f.ps[0].iter & 1) ? f.nxtiles - 1 - b : b;
 }
 
 __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __restrict__ c) {
-  xsym_tile(f, c, static_cast<int>(blockIdx.x));
+  xsym_tile(f, c, xsym_order(f, static_cast<int>(blockIdx.x)));
 }
 
 // x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
@@ -669,19 +721,47 @@ __device__ __forceinline__ void fhead_block(const VecArgs& a, int bi, int lane) 
   }
 }
 
+// The objective tiles read sum_s G_s rounded to 48 bits (sign, exponent and
+// the leading 36 of the 52 fraction bits, to nearest): 24 KB a tile instead of
+// 32 KB, relative error at most 2^-37 per entry.  Thread t of fobj_tile takes
+// the 16 entries e = 0..15 at (row 8 (e / 2) + t / 32, column 2 (t % 32) +
+// e % 2) of the tile; their upper 32 bits are four 16-byte words at
+// 256 k + t (k = 0..3, entries 4k .. 4k + 3) of the tile's first 16 KB, their
+// next 16 bits two 16-byte words at 256 k + t (k = 0..1, entries 8k .. 8k + 7)
+// of its last 8 KB, so every wave load reads 1 KiB contiguous.
+constexpr int kGqWords = 6144;  // 32-bit words of one tile
+__global__ __launch_bounds__(256) void k_gq_pack(const double* __restrict__ Gp, uint32_t* __restrict__ Gq,
+                                                 int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < n; idx += stride) {
+    const int64_t tile = idx >> 12;
+    const int L = static_cast<int>(idx & 4095);  // row-major within the tile: 512 (e / 2) + 2 t + e % 2
+    const int t = (L & 511) >> 1, e = 2 * (L >> 9) + (L & 1);
+    const unsigned long long r = static_cast<unsigned long long>(__double_as_longlong(Gp[idx])) + 0x8000ull;
+    uint32_t* q = Gq + tile * kGqWords;
+    q[((e >> 2) * 256 + t) * 4 + (e & 3)] = static_cast<uint32_t>(r >> 32);
+    reinterpret_cast<uint16_t*>(q + 4096)[((e >> 3) * 256 + t) * 8 + (e & 7)] =
+        static_cast<uint16_t>((r >> 16) & 0xffffu);
+  }
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4& v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
 // objective partial of one packed tile T of sum_s G_s: z_I^T T z_J, doubled off
-// the diagonal; a diagonal tile also carries -g0_I^T z_I.  fp64.  The tile's
-// 32 KB are requested first, from its offset alone (each wave instruction
-// reads 1 KiB contiguous); thread t then holds rows 8 k + t / 32 (k = 0..7),
-// columns 2 (t % 32) and 2 (t % 32) + 1, and the quadratic form is summed
-// element by element.
+// the diagonal; a diagonal tile also carries -g0_I^T z_I.  fp64 arithmetic on
+// the 48-bit entries above.  The tile's 24 KB are requested first, from its
+// list index alone.
 __device__ __forceinline__ void fobj_tile(const FactorArgs& f, const float* __restrict__ z, int jb) {
   __shared__ double zI[kFb], zJ[kFb], red[4];
   const int tid = threadIdx.x;
-  const double2* T = reinterpret_cast<const double2*>(f.Gp + f.fobj_off[jb]);
-  double2 g[8];
+  const uint4* Q = reinterpret_cast<const uint4*>(f.Gq + static_cast<int64_t>(jb) * kGqWords);
+  uint4 hi[4], lo[2];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) g[k] = T[k * 256 + tid];
+  for (int k = 0; k < 4; ++k) hi[k] = Q[k * 256 + tid];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) lo[k] = Q[1024 + k * 256 + tid];
   const XJob job = f.fjobs[jb];
   if (f.ps[job.g].stopped) return;
   const Pat pt = f.pat[job.g];
@@ -692,10 +772,17 @@ __device__ __forceinline__ void fobj_tile(const FactorArgs& f, const float* __re
     zI[tid] = ic < pt.n ? static_cast<double>(z[pt.zvec_base + ic]) : 0.0;
   }
   __syncthreads();
+  auto entry = [&](int e) {
+    const uint32_t h = word_of(hi[e >> 2], e & 3);
+    const uint32_t l2 = word_of(lo[e >> 3], (e & 7) >> 1);
+    const uint32_t l = (e & 1) ? (l2 >> 16) : (l2 & 0xffffu);
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(h) << 32) |
+                                                       (static_cast<unsigned long long>(l) << 16)));
+  };
   const int c = 2 * (tid & 31), r0 = tid >> 5;
   double a = 0.0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) a = fma(zI[8 * k + r0], fma(g[k].x, zJ[c], g[k].y * zJ[c + 1]), a);
+  for (int k = 0; k < 8; ++k) a = fma(zI[8 * k + r0], fma(entry(2 * k), zJ[c], entry(2 * k + 1) * zJ[c + 1]), a);
   double v = (I == J ? 1.0 : 2.0) * a;
   if (I == J && tid < kFb) {
     const int row = I * kFb + tid;
@@ -792,7 +879,8 @@ __global__ __launch_bounds__(256) void k_dense_head(VecArgs a, int nblk) {
 //         iteration (head_scalars_run), the others the x-update tiles.  The
 //         tiles read the stop flag that workgroup 0 may be setting: a tile of
 //         a patient that stops there writes partial sums that nothing reads
-//         (the reduction and the z-update read the flag after the launch);
+//         (the reduction and the z-update read the flag after the launch),
+//         and none writes the iteration count that orders the tiles;
 //   tail: workgroup 0 the residual norms, tolerances and dual step
 //         (body_scalars_run), then the dual update with the next right-hand
 //         sides (each wave forms tau itself, dense_dual_block), then the
@@ -804,7 +892,7 @@ __global__ __launch_bounds__(256) void k_dense_x(FactorArgs f, VecArgs a, const 
     head_scalars_run<true>(a, 0, 0);
     return;
   }
-  xsym_tile(f, c, static_cast<int>(blockIdx.x) - 1);
+  xsym_tile(f, c, xsym_order(f, static_cast<int>(blockIdx.x) - 1));
 }
 
 __global__ __launch_bounds__(256) void k_dense_tail_dual(FactorArgs f, VecArgs a, int nfobj, int nblk) {
@@ -891,6 +979,13 @@ void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0
   hipLaunchKernelGGL(k_sweep_pivot, dim3(nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
   hipLaunchKernelGGL(k_sweep_panel, dim3(nbk, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
   hipLaunchKernelGGL(k_sweep_update, dim3(nbk * (nbk + 1) / 2, nscen), dim3(256), 0, st, f, scen_begin, npad, k0);
+}
+
+void launch_gq_pack(const double* Gp, uint32_t* Gq, int64_t ntiles, hipStream_t st) {
+  if (ntiles <= 0) return;
+  const int64_t n = ntiles * 4096;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 65536));
+  hipLaunchKernelGGL(k_gq_pack, dim3(grid), dim3(256), 0, st, Gp, Gq, n);
 }
 
 void launch_sweep_store(FactorArgs f, int patient, int scen_begin, int nscen, int npad, hipStream_t st) {

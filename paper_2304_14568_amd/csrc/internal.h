@@ -218,10 +218,10 @@ struct VecArgs {
 // Dense x-update (cached inverse of every B_s): device arrays and work tables.
 // One packed tile of an inverse M_s, with everything its x-update workgroup
 // needs to address it (no dependent table lookups before the tile load).
+// Tile k of the table is stored at Mp + 4096 k and its partial pair at
+// xpart + 128 k (the scenarios' packed inverses follow each other).
 struct XTile {
-  int64_t moff;    // float offset of the tile in Mp
   int64_t vbase;   // vec_base of the scenario
-  int64_t pidx;    // index of the tile's partial pair in xpart (units of 2 x 64 doubles)
   int32_t n;       // spots of the patient
   int32_t patient;
   int32_t I, J;    // block row and block column
@@ -260,7 +260,7 @@ struct FactorArgs {
   int32_t nxtiles;
   const RJob* rjobs;  // x-update reduction: one per block row of every scenario
   const XJob* fjobs;  // objective: one per packed tile of every patient
-  const int64_t* fobj_off;  // objective: offset in Gp of each of those tiles
+  uint32_t* Gq;       // objective: Gp rounded to 48 bits, tile k of fjobs at 6144 k (layout in fobj_tile)
   double* fpart;      // objective partial per objective job
   int32_t npmax;      // largest npad
   int32_t pad;
@@ -306,6 +306,7 @@ void launch_gram_finish(FactorArgs f, int patient, int scen_begin, int nscen, in
                         int accumulate_gsum, hipStream_t st);
 void launch_sweep_step(FactorArgs f, int scen_begin, int nscen, int npad, int k0, hipStream_t st);
 void launch_sweep_store(FactorArgs f, int patient, int scen_begin, int nscen, int npad, hipStream_t st);
+void launch_gq_pack(const double* Gp, uint32_t* Gq, int64_t ntiles, hipStream_t st);
 void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st);
