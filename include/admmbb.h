@@ -357,15 +357,27 @@ admm_status admm_get_trace(admm_ctx* ctx, int32_t patient, admm_info* buf, int32
  * measured average pass time in ms of the chosen configurations summed over
  * the patients (all scenarios, fp32 or the CG value precision). */
 admm_status admm_get_tuning(const admm_ctx* ctx, int32_t* threads, int32_t* unroll, int32_t* lds_acc, double* ms);
-/* The sparse-pass configuration of one patient of the context (the passes are
-   launched once per patient, each with its own; the set-up autotuner of the CG
-   x-update chooses it per patient): workgroup size, row pipelining (1 or 2),
+/* The sparse-pass configuration of one patient of the context for the CG
+   operator and the gradient pass (the passes are launched once per patient,
+   each with its own; the set-up autotuner of the CG x-update chooses it per
+   patient): workgroup size, row pipelining (1 or 2),
    LDS accumulator (0 fp32, 1 fp64, 2 64-bit fixed point), layout
    (ADMM_FORMAT_CSR / ADMM_FORMAT_SELL) and the tuned pass time in ms (0 where
    the tuner did not run).  Any output pointer may be NULL.  ADMM_E_ARG for a
    NULL ctx or a patient outside [0, num_patients). */
 admm_status admm_get_pass_config(const admm_ctx* ctx, int32_t patient, int32_t* threads, int32_t* unroll,
                                  int32_t* lds_acc, int32_t* format, double* ms);
+/* The configuration of one patient's other sparse products (the forward
+   product A_s z with the objective, Sec. 2; admm_matvec; the transpose product
+   A_s^T t): workgroup size (512 or 1024) and row pipelining (1 or 2), chosen at
+   set-up, with either x-update, as the fastest forward product over the
+   patient's matrices unless the options fix them, and that product's time in
+   ms over all its scenarios.  Results do not depend on the choice except the
+   objective's last bits (its per-tile sums follow the workgroup size).  Any
+   output pointer may be NULL.  ADMM_E_ARG for a NULL ctx or a patient outside
+   [0, num_patients). */
+admm_status admm_get_forward_config(const admm_ctx* ctx, int32_t patient, int32_t* threads, int32_t* unroll,
+                                    double* ms);
 
 /* Layout of A_s the sparse passes of patient 0 read (ADMM_FORMAT_CSR or
  * ADMM_FORMAT_SELL): the one asked for, or under ADMM_FORMAT_AUTO the set-up

@@ -27,7 +27,7 @@ EXPORTS = [
     "admm_default_options", "pgd_default_options", "admm_setup", "admm_setup_batch", "admm_warm_start",
     "admm_reset", "admm_iterate", "admm_solve", "pgd_solve", "admm_objective", "admm_gradient", "admm_kkt",
     "admm_matvec", "admm_rmatvec", "admm_normal_apply", "admm_get_rho", "admm_get_z", "admm_get_state",
-    "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_pass_config", "admm_get_format", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
+    "admm_set_state", "admm_get_trace", "admm_get_cg_counts", "admm_get_tuning", "admm_get_pass_config", "admm_get_forward_config", "admm_get_format", "admm_get_sizes", "admm_enable_timing", "admm_get_timing",
     "admm_last_error", "admm_destroy", "admm_validate", "admm_spot_features", "admm_dose_stats", "admm_get_xupdate", "admm_time_pass",
     "admm_stream_probe", "admm_dose_stats_noalloc",
     "mlp_create", "mlp_destroy", "mlp_num_params", "mlp_get_params", "mlp_set_params", "mlp_forward",
@@ -134,6 +134,7 @@ def _load():
         "admm_get_cg_counts": [P, i32, P],
         "admm_get_tuning": [P, P, P, P, P],
         "admm_get_pass_config": [P, i32, P, P, P, P, P],
+        "admm_get_forward_config": [P, i32, P, P, P],
         "admm_get_format": [P, P],
         "admm_get_sizes": [P, i32, P, P, P, P],
         "admm_enable_timing": [P, i32],
@@ -431,6 +432,14 @@ class Solver:
                                                       ctypes.byref(a), ctypes.byref(f), ctypes.byref(ms)))
         return dict(threads=t.value, unroll=u.value, lds_acc=a.value, pass_ms=ms.value,
                     format="sell" if f.value == 1 else "csr")
+
+    def forward_config(self, patient: int = 0):
+        """Workgroup size, row pipelining and tuned time (ms) of one patient's
+        forward, objective and transpose products."""
+        t, u, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(self.ctx, lib.admm_get_forward_config(self.ctx, int(patient), ctypes.byref(t), ctypes.byref(u),
+                                                     ctypes.byref(ms)))
+        return dict(threads=t.value, unroll=u.value, pass_ms=ms.value)
 
     def cg_counts(self, patient: int = 0):
         c = np.zeros(self.num_scen[patient], dtype=np.int64)

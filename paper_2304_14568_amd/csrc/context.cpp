@@ -80,6 +80,7 @@ struct admm_ctx {
   float *d_x = nullptr, *d_r = nullptr, *d_v = nullptr, *d_q = nullptr, *d_zp = nullptr, *d_y = nullptr;
   float *d_b = nullptr, *d_dinv = nullptr, *d_z = nullptr, *d_lb = nullptr, *d_ub = nullptr;
   float *d_pvec = nullptr, *d_pvec2 = nullptr, *d_pvec3 = nullptr, *d_mvec = nullptr;
+  float* d_tmax = nullptr;  // kAbsMaxBlocks partial maxima of the transpose product's input
   double* d_dprev = nullptr;
   float* d_part = nullptr;
   double* d_objpart = nullptr;
@@ -104,9 +105,17 @@ struct admm_ctx {
   struct PassCfg {
     int threads, unroll, acc, fmt;
     double ms;  // tuned pass time (0 where the tuner did not run)
+    // the products other than the CG operator and the gradient pass (forward
+    // product and objective, transpose product): workgroup size, row
+    // pipelining and the tuned forward-product time
+    int fthreads, funroll;
+    double fms;
   };
   std::vector<PassCfg> pcfg;
-  void set_all_cfg() { pcfg.assign(static_cast<size_t>(P), PassCfg{pass_threads, pass_unroll, acc, fmt, 0.0}); }
+  void set_all_cfg() {
+    pcfg.assign(static_cast<size_t>(P),
+                PassCfg{pass_threads, pass_unroll, acc, fmt, 0.0, pass_threads, pass_unroll, 0.0});
+  }
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs around the CG passes inside the captured iteration
@@ -227,14 +236,25 @@ struct admm_ctx {
       pa.nmax = pt.n;
       if (static_cast<size_t>(p) < pcfg.size()) {
         const PassCfg& c = pcfg[static_cast<size_t>(p)];
-        pa.threads = c.threads;
-        pa.unroll = c.unroll;
+        const bool fwd = mode == PASS_OBJ || mode == PASS_MATVEC || mode == PASS_RMATVEC;
+        pa.threads = fwd ? c.fthreads : c.threads;
+        pa.unroll = fwd ? c.funroll : c.unroll;
         pa.acc = c.acc;
         const bool sl = c.fmt == FMT_SELL && has_sell;
         pa.mat = pa.mat.vkind == VAL_F32 ? (sl ? sell32 : csr32) : (sl ? selllp : csrlp);
       }
       launch_pass(mode, pa, b, e - b, stream, p == first ? e0 : nullptr, p == last ? e1 : nullptr);
     }
+  }
+
+  // Transpose product A_s^T t over tiles [tile_begin, tile_begin + tile_count)
+  // of one patient (t: its m-vector): max |t_i| first, which bounds the
+  // fixed-point column sums of every tile.
+  void rmatvec_launch(PassArgs pa, const float* t, int64_t m, int tile_begin, int tile_count) {
+    launch_absmax(t, m, d_tmax, stream);
+    pa.tin = t;
+    pa.tmax = d_tmax;
+    pass_launch(PASS_RMATVEC, pa, tile_begin, tile_count);
   }
 
   PassArgs pass_args(const MatDev& m) const {
@@ -612,7 +632,14 @@ struct admm_ctx {
     hipEvent_t e0, e1;
     check(hipEventCreate(&e0), "hipEventCreate");
     check(hipEventCreate(&e1), "hipEventCreate");
-    std::vector<PassCfg> best(static_cast<size_t>(P), PassCfg{th[0], un[0], ac[0], fm[0], 1e30});
+    std::vector<PassCfg> best = pcfg;
+    for (auto& b : best) {
+      b.threads = th[0];
+      b.unroll = un[0];
+      b.acc = ac[0];
+      b.fmt = fm[0];
+      b.ms = 1e30;
+    }
     const int reps = 3;
     for (int f : fm)
       for (int a64 : ac)
@@ -620,8 +647,12 @@ struct admm_ctx {
           for (int u : un) {
             // the sliced layout has neither a row pipelining nor a 1024-thread variant
             if (f == FMT_SELL && (u != un[0] || t > 512)) continue;
-            set_all_cfg();
-            for (auto& c : pcfg) c = PassCfg{t, u, a64, f, 0.0};
+            for (auto& c : pcfg) {
+              c.threads = t;
+              c.unroll = u;
+              c.acc = a64;
+              c.fmt = f;
+            }
             PassArgs pa = pass_args(opts.precision == ADMM_PREC_FP32 ? csr32 : csrlp);
             pa.src = d_v;
             pa.src_per_scen = 1;
@@ -637,7 +668,14 @@ struct admm_ctx {
               check(hipEventSynchronize(e1), "hipEventSynchronize");
               float ms = 0.0f;
               check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-              if (ms / reps < best[static_cast<size_t>(p)].ms) best[static_cast<size_t>(p)] = PassCfg{t, u, a64, f, ms / reps};
+              PassCfg& b = best[static_cast<size_t>(p)];
+              if (ms / reps < b.ms) {
+                b.threads = t;
+                b.unroll = u;
+                b.acc = a64;
+                b.fmt = f;
+                b.ms = ms / reps;
+              }
             }
           }
     (void)hipEventDestroy(e0);
@@ -653,6 +691,63 @@ struct admm_ctx {
     acc = pcfg[0].acc;
     pass_threads = pcfg[0].threads;
     pass_unroll = pcfg[0].unroll;
+  }
+
+  // Per patient, the workgroup size and row pipelining of the products other
+  // than the CG operator: the fastest forward product (objective pass at z,
+  // fp32 values) of 512 or 1024 threads, with or without pipelining, in the
+  // patient's layout (the sliced layout has 512 threads at most and no
+  // pipelining).  Options that fix either keep it.
+  void tune_forward() {
+    std::vector<int> th = {512, 1024}, un = {1, 2};
+    if (opts.pass_threads) th = {opts.pass_threads};
+    if (opts.pass_unroll) un = {opts.pass_unroll};
+    hipEvent_t e0, e1;
+    check(hipEventCreate(&e0), "hipEventCreate");
+    check(hipEventCreate(&e1), "hipEventCreate");
+    const int reps = 3;
+    try {
+      for (int p = 0; p < P; ++p) {
+        const Pat& pt = H.pat[p];
+        const int tc = pt.tile_end - pt.tile_begin;
+        PassCfg& c = pcfg[static_cast<size_t>(p)];
+        if (tc <= 0) continue;
+        const bool sl = c.fmt == FMT_SELL && has_sell;
+        int bt = c.fthreads, bu = c.funroll;
+        double bms = 1e30;
+        for (int t : th)
+          for (int u : un) {
+            if (sl && (t > 512 || u != un[0])) continue;
+            c.fthreads = t;
+            c.funroll = u;
+            PassArgs pa = pass_args(mat32);
+            pa.src = d_z;
+            pa.src_per_scen = 0;
+            pa.part = nullptr;
+            pass_launch(PASS_OBJ, pa, pt.tile_begin, tc);
+            check(hipEventRecord(e0, stream), "hipEventRecord");
+            for (int r = 0; r < reps; ++r) pass_launch(PASS_OBJ, pa, pt.tile_begin, tc);
+            check(hipEventRecord(e1, stream), "hipEventRecord");
+            check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (ms / reps < bms) {
+              bms = ms / reps;
+              bt = t;
+              bu = u;
+            }
+          }
+        c.fthreads = bt;
+        c.funroll = bu;
+        c.fms = bms < 1e30 ? bms : 0.0;
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
 
   void reset_patient(int p, const double* z0, double new_rho) {
@@ -1163,6 +1258,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->d_pvec2 = c->alloc<float>(H.zvec_total);
     c->d_pvec3 = c->alloc<float>(H.zvec_total);
     c->d_mvec = c->alloc<float>(H.mmax);
+    c->d_tmax = c->alloc<float>(kAbsMaxBlocks);
     c->d_part = c->alloc<float>(static_cast<size_t>(H.part_total));
     c->d_objpart = c->alloc<double>(c->T);
     c->d_bpart = c->alloc<double>(static_cast<size_t>(c->NB) * 8);
@@ -1210,6 +1306,7 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->set_all_cfg();
     clk.mark("cached inverses");
     if (!c->dense) c->autotune();  // the dense x-update does not run the CG pass per iteration
+    c->tune_forward();
     check(hipEventCreate(&c->ev_a), "hipEventCreate");
     check(hipEventCreate(&c->ev_b), "hipEventCreate");
     check(hipStreamSynchronize(c->stream), "setup sync");
@@ -1320,9 +1417,8 @@ admm_status admm_spot_features(admm_ctx* ctx, int32_t patient, const uint8_t* vo
       const Scen& sc = ctx->H.scen[pt.scen_begin + s];
       for (int c = 0; c < 3; ++c) {
         PassArgs pa = ctx->pass_args(ctx->mat32);
-        pa.tin = d_ind + static_cast<size_t>(c) * m;
         pa.objpart = nullptr;
-        ctx->pass_launch(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
+        ctx->rmatvec_launch(pa, d_ind + static_cast<size_t>(c) * m, m, sc.tile_begin, sc.tile_end - sc.tile_begin);
         VecArgs va = ctx->vec_args(0);
         va.out = ctx->d_pvec2 + pt.zvec_base;
         launch_reduce(RED_RMAT, va, sc.blk_begin, sc.nblk, ctx->stream);
@@ -1696,9 +1792,8 @@ admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const flo
   const Scen& sc = ctx->H.scen[g];
   check(hipMemcpyAsync(ctx->d_mvec, t, sizeof(float) * pt.m, hipMemcpyHostToDevice, ctx->stream), "H2D");
   PassArgs pa = ctx->pass_args(ctx->mat32);
-  pa.tin = ctx->d_mvec;
   pa.objpart = nullptr;
-  ctx->pass_launch(PASS_RMATVEC, pa, sc.tile_begin, sc.tile_end - sc.tile_begin);
+  ctx->rmatvec_launch(pa, ctx->d_mvec, pt.m, sc.tile_begin, sc.tile_end - sc.tile_begin);
   VecArgs va = ctx->vec_args(0);
   va.out = ctx->d_pvec2 + pt.zvec_base;
   launch_reduce(RED_RMAT, va, sc.blk_begin, sc.nblk, ctx->stream);
@@ -2079,7 +2174,6 @@ admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms
   } else if (kind == 1) {
     mode = PASS_RMATVEC;
     launch_fill_f32(ctx->d_mvec, 1.0f, ctx->H.mmax, ctx->stream);
-    pa.tin = ctx->d_mvec;
     pa.objpart = nullptr;
   } else {
     pa.src = ctx->d_v;
@@ -2090,10 +2184,17 @@ admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms
   check(hipEventCreate(&e0), "hipEventCreate");
   check(hipEventCreate(&e1), "hipEventCreate");
   float ms = 0.0f;
+  // every pass over all tiles; the transpose product with its max |t| launch
+  auto one = [&]() {
+    if (mode == PASS_RMATVEC)
+      ctx->rmatvec_launch(pa, ctx->d_mvec, ctx->H.mmax, 0, ctx->T);
+    else
+      ctx->pass_launch(mode, pa, 0, ctx->T);
+  };
   try {
-    ctx->pass_launch(mode, pa, 0, ctx->T);  // warm
+    one();  // warm
     check(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-    for (int r = 0; r < reps; ++r) ctx->pass_launch(mode, pa, 0, ctx->T);
+    for (int r = 0; r < reps; ++r) one();
     check(hipEventRecord(e1, ctx->stream), "hipEventRecord");
     check(hipEventSynchronize(e1), "hipEventSynchronize");
     check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
@@ -2134,6 +2235,17 @@ admm_status admm_get_pass_config(const admm_ctx* ctx, int32_t patient, int32_t* 
   if (lds_acc) *lds_acc = c.acc;
   if (format) *format = (c.fmt == FMT_SELL && ctx->has_sell) ? ADMM_FORMAT_SELL : ADMM_FORMAT_CSR;
   if (ms) *ms = c.ms;
+  return ADMM_OK;
+}
+
+admm_status admm_get_forward_config(const admm_ctx* ctx, int32_t patient, int32_t* threads, int32_t* unroll,
+                                    double* ms) {
+  if (!ctx) return ADMM_E_ARG;
+  if (patient < 0 || patient >= ctx->P || static_cast<size_t>(patient) >= ctx->pcfg.size()) return ADMM_E_ARG;
+  const auto& c = ctx->pcfg[static_cast<size_t>(patient)];
+  if (threads) *threads = c.fthreads;
+  if (unroll) *unroll = c.funroll;
+  if (ms) *ms = c.fms;
   return ADMM_OK;
 }
 

@@ -151,6 +151,8 @@ struct PassArgs {
   float* part;             // tile partial column sums
   double* objpart;         // per-tile objective partial (GRAD / OBJ)
   const float* tin;        // RMATVEC input (m-vector of the scenario)
+  const float* tmax;       // RMATVEC: kAbsMaxBlocks partial maxima of |tin| (launch_absmax); nullptr: each
+                           // tile takes the maximum over its own rows first
   float* tout;             // MATVEC output (m-vector of the scenario)
   int32_t nmax;
   int32_t acc;             // LDS column accumulators: ACC_F32, ACC_F64 or ACC_FIX64
@@ -284,6 +286,9 @@ void launch_pgd_trial(const float* x, const float* g, const float* lb, const flo
                       int n, double* dotpart, hipStream_t st);
 void launch_dot_sum(const double* part, int count, double* out, hipStream_t st);
 void launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
+// max |x_i| over x[0, n) as kAbsMaxBlocks partial maxima (NaN entries ignored)
+constexpr int kAbsMaxBlocks = 256;
+void launch_absmax(const float* x, int64_t n, float* out, hipStream_t st);
 void launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st);
 int pass_smem_bytes(int nmax, int acc);

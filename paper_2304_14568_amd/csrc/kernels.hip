@@ -409,6 +409,29 @@ static void fill(T* p, T v, int64_t count, hipStream_t st) {
   hipLaunchKernelGGL(k_fill<T>, dim3(static_cast<unsigned>(nb)), dim3(kThreads), 0, st, p, v, count);
 }
 
+__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int64_t n, float* __restrict__ out) {
+  __shared__ float wm[4];
+  // four loads in flight per thread
+  constexpr int64_t S = int64_t{kAbsMaxBlocks} * 256;
+  float v = 0.0f;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += 4 * S) {
+    float q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = i + u * S < n ? x[i + u * S] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v = fmaxf(v, fabsf(q[u]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+}
+
+void launch_absmax(const float* x, int64_t n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_absmax, dim3(kAbsMaxBlocks), dim3(256), 0, st, x, n, out);
+}
+
 void launch_fill_f32(float* p, float v, int64_t count, hipStream_t st) { fill<float>(p, v, count, st); }
 void launch_fill_f64(double* p, double v, int64_t count, hipStream_t st) { fill<double>(p, v, count, st); }
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t st) { fill<uint8_t>(p, v, count, st); }

@@ -203,6 +203,15 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
   int r = t.row_begin + grp;
   uint32_t s = r < rend ? rp[r] : 0u;
   uint32_t e = r < rend ? rp[r + 1] : 0u;
+  // transpose product: the row's t_i, two dependent loads with nothing to
+  // hide them before the scatter needs it, is requested one row ahead and
+  // its original index two rows ahead
+  float tin_cur = 0.0f;
+  int32_t ro_next = 0;
+  if constexpr (MODE == PASS_RMATVEC) {
+    tin_cur = r < rend ? a.tin[a.mat.rorig[rb + r]] : 0.0f;
+    ro_next = r + G < rend ? a.mat.rorig[rb + r + G] : 0;
+  }
   float vv[K][4];
   CCk cc[K];
   if constexpr (PIPE) load_row(s, e, vv, cc);
@@ -211,7 +220,7 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
     float rw;
     float aux = 0.0f;
     if constexpr (MODE == PASS_RMATVEC) {
-      rw = a.tin[a.mat.rorig[rb + r]];
+      rw = tin_cur;
     } else if constexpr (MODE == PASS_MATVEC) {
       rw = 0.0f;
     } else {
@@ -227,6 +236,10 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
     const int rn = r + G;
     const uint32_t sn = rn < rend ? rp[rn] : 0u;
     const uint32_t en = rn < rend ? rp[rn + 1] : 0u;
+    if constexpr (MODE == PASS_RMATVEC) {
+      tin_cur = rn < rend ? a.tin[ro_next] : 0.0f;
+      ro_next = rn + G < rend ? a.mat.rorig[rb + rn + G] : 0;
+    }
     float vn[K][4];
     CCk cn[K];
     if constexpr (PIPE) load_row(sn, en, vn, cn);
@@ -422,6 +435,7 @@ __device__ __forceinline__ void pass_slices(const PassArgs& a, const Tile& t, co
 
 template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE, int FMT>
 __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
+  static_assert(NT >= kAbsMaxBlocks, "one thread per partial maximum of |t|");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float vmax_sh[NT / 64];
   constexpr bool kScatter = MODE == PASS_GRAD || MODE == PASS_CG || MODE == PASS_RMATVEC;
@@ -451,10 +465,15 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
       for (int j = threadIdx.x; j < n; j += NT) static_cast<unsigned long long*>(qacc)[j] = 0ull;
   }
   if constexpr (MODE == PASS_RMATVEC && ACC == ACC_FIX64) {
-    // the given t bounds the contributions: max |t_i| over the tile's rows
-    const int rb0 = static_cast<int>(sc.row_base);
-    for (int r = t.row_begin + static_cast<int>(threadIdx.x); r < t.row_end; r += NT)
-      vmax = fmaxf(vmax, fabsf(a.tin[a.mat.rorig[rb0 + r]]));
+    // the given t bounds the contributions: max |t_i| over the whole vector,
+    // formed beforehand, or over the tile's rows
+    if (a.tmax != nullptr) {
+      if (threadIdx.x < kAbsMaxBlocks) vmax = a.tmax[threadIdx.x];
+    } else {
+      const int rb0 = static_cast<int>(sc.row_base);
+      for (int r = t.row_begin + static_cast<int>(threadIdx.x); r < t.row_end; r += NT)
+        vmax = fmaxf(vmax, fabsf(a.tin[a.mat.rorig[rb0 + r]]));
+    }
   }
   // fixed-point scale: every partial column sum of this tile, and every single
   // contribution, is below cmax * (wmax * max|v| + pmax) < 2^50 / 2^F (for the
@@ -530,7 +549,9 @@ __global__ __launch_bounds__(NT) void k_pass(PassArgs a, int tile_begin) {
 template <int VK, bool C16, int MODE, int ACC, int NT, bool PIPE, int FMT>
 static void launch_k(const PassArgs& a, int tile_begin, int tile_count, hipStream_t st, hipEvent_t e0,
                      hipEvent_t e1) {
-  const int smem = pass_smem_bytes(a.nmax, ACC);
+  // passes without a scatter need the multiplied vector only, no column accumulators
+  constexpr bool kScatter = MODE == PASS_GRAD || MODE == PASS_CG || MODE == PASS_RMATVEC;
+  const int smem = kScatter ? pass_smem_bytes(a.nmax, ACC) : ((a.nmax * 4 + 15) & ~15);
   auto kern = k_pass<VK, C16, MODE, ACC, NT, PIPE, FMT>;
   static bool attr_done = false;
   if (!attr_done && smem > 65536) {

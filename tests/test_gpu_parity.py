@@ -115,6 +115,39 @@ def test_pass_configuration_chosen_per_patient(tiny, small):
             S.tuning(2)
 
 
+def test_forward_configuration_tuned_per_patient_and_exact(tiny, small):
+    """The forward, objective and transpose products take a configuration of
+    their own per patient (the fastest forward product at set-up, with either
+    x-update).  Each row's dot is formed by the same lanes in the same order
+    and the transpose product's fixed-point column sums are exact, so both
+    products are the same bit for bit in every configuration, and within the
+    per-entry bound of the fp64 products."""
+    P, W, _, _ = small
+    for xupdate in ("dense", "cg"):
+        with _solver([tiny[0], P], xupdate=xupdate) as S:
+            for p in (0, 1):
+                fc = S.forward_config(p)
+                assert fc["threads"] in (512, 1024) and fc["unroll"] in (1, 2) and fc["pass_ms"] > 0.0
+    rng = np.random.default_rng(21)
+    v = rng.uniform(0.0, 1.0, P.n).astype(np.float32)
+    t = rng.normal(size=P.m).astype(np.float32)
+    t[rng.uniform(size=P.m) < 0.5] *= 1e-3  # entries far below the largest
+    outs = {}
+    for threads in (512, 1024):
+        for unroll in (1, 2):
+            with _solver(P, pass_threads=threads, pass_unroll=unroll, lds_acc=2, format="csr") as S:
+                assert (S.forward_config(0)["threads"], S.forward_config(0)["unroll"]) == (threads, unroll)
+                outs[(threads, unroll)] = [S.matvec(v, s) for s in (0, P.num_scen - 1)] + \
+                                          [S.rmatvec(t, s) for s in (0, P.num_scen - 1)]
+    first = outs[(512, 1)]
+    for key, got in outs.items():
+        for a, b in zip(first, got):
+            assert np.array_equal(a, b), key
+    for k, s in enumerate((0, P.num_scen - 1)):
+        _spmv_check(first[k], wls.matvec(W, s, v), wls.matvec_abs(W, s, v))
+        _spmv_check(first[2 + k], wls.rmatvec(W, s, t), wls.rmatvec_abs(W, s, t))
+
+
 @pytest.mark.parametrize("fmt", ["csr", "sell"])
 @pytest.mark.parametrize("lds_acc", [0, 1, 2])
 def test_normal_apply_parity(small, lds_acc, fmt):
