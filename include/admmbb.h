@@ -369,13 +369,16 @@ admm_status admm_get_pass_config(const admm_ctx* ctx, int32_t patient, int32_t* 
                                  int32_t* lds_acc, int32_t* format, double* ms);
 /* The configuration of one patient's other sparse products (the forward
    product A_s z with the objective, Sec. 2; admm_matvec; the transpose product
-   A_s^T t): workgroup size (512 or 1024) and row pipelining (1 or 2), chosen at
-   set-up, with either x-update, as the fastest forward product over the
-   patient's matrices unless the options fix them, and that product's time in
-   ms over all its scenarios.  Results do not depend on the choice except the
-   objective's last bits (its per-tile sums follow the workgroup size).  Any
-   output pointer may be NULL.  ADMM_E_ARG for a NULL ctx or a patient outside
-   [0, num_patients). */
+   A_s^T t): workgroup size (512 or 1024) and row pipelining (1 or 2), chosen
+   with either x-update as the fastest forward product over the patient's
+   matrices unless the options fix them, and that product's time in ms over all
+   its scenarios (0 until chosen).  The choice is made once, on the context's
+   first admm_objective, admm_matvec, admm_rmatvec, admm_spot_features, sparse
+   pgd_solve or admm_time_pass call (the iterations use none of these
+   products; until then they run with the options' pass configuration).
+   Results do not depend on the choice except the objective's last bits (its
+   per-tile sums follow the workgroup size).  Any output pointer may be NULL.
+   ADMM_E_ARG for a NULL ctx or a patient outside [0, num_patients). */
 admm_status admm_get_forward_config(const admm_ctx* ctx, int32_t patient, int32_t* threads, int32_t* unroll,
                                     double* ms);
 

@@ -16,6 +16,7 @@
 #include <string>
 #include <system_error>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "host.h"
@@ -697,15 +698,23 @@ struct admm_ctx {
   // than the CG operator: the fastest forward product (objective pass at z,
   // fp32 values) of 512 or 1024 threads, with or without pipelining, in the
   // patient's layout (the sliced layout has 512 threads at most and no
-  // pipelining).  Options that fix either keep it.
+  // pipelining).  Options that fix either keep it.  Run once, before the
+  // context's first such product (the iterations use none).
+  bool fwd_tuned = false;
+  void ensure_forward_tuned() {
+    if (!fwd_tuned) tune_forward();
+  }
   void tune_forward() {
+    fwd_tuned = true;
     std::vector<int> th = {512, 1024}, un = {1, 2};
     if (opts.pass_threads) th = {opts.pass_threads};
     if (opts.pass_unroll) un = {opts.pass_unroll};
     hipEvent_t e0, e1;
     check(hipEventCreate(&e0), "hipEventCreate");
     check(hipEventCreate(&e1), "hipEventCreate");
-    const int reps = 3;
+    // the candidates differ by a few per cent: each is timed over 4 passes in
+    // each of 3 rounds taken in turn, and keeps its best round
+    const int reps = 4, rounds = 3;
     try {
       for (int p = 0; p < P; ++p) {
         const Pat& pt = H.pat[p];
@@ -713,17 +722,19 @@ struct admm_ctx {
         PassCfg& c = pcfg[static_cast<size_t>(p)];
         if (tc <= 0) continue;
         const bool sl = c.fmt == FMT_SELL && has_sell;
-        int bt = c.fthreads, bu = c.funroll;
-        double bms = 1e30;
+        std::vector<std::pair<int, int>> cand;
         for (int t : th)
-          for (int u : un) {
-            if (sl && (t > 512 || u != un[0])) continue;
-            c.fthreads = t;
-            c.funroll = u;
-            PassArgs pa = pass_args(mat32);
-            pa.src = d_z;
-            pa.src_per_scen = 0;
-            pa.part = nullptr;
+          for (int u : un)
+            if (!(sl && (t > 512 || u != un[0]))) cand.emplace_back(t, u);
+        std::vector<double> best(cand.size(), 1e30);
+        PassArgs pa = pass_args(mat32);
+        pa.src = d_z;
+        pa.src_per_scen = 0;
+        pa.part = nullptr;
+        for (int round = 0; round < rounds; ++round)
+          for (size_t k = 0; k < cand.size(); ++k) {
+            c.fthreads = cand[k].first;
+            c.funroll = cand[k].second;
             pass_launch(PASS_OBJ, pa, pt.tile_begin, tc);
             check(hipEventRecord(e0, stream), "hipEventRecord");
             for (int r = 0; r < reps; ++r) pass_launch(PASS_OBJ, pa, pt.tile_begin, tc);
@@ -731,15 +742,14 @@ struct admm_ctx {
             check(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.0f;
             check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-            if (ms / reps < bms) {
-              bms = ms / reps;
-              bt = t;
-              bu = u;
-            }
+            best[k] = std::min(best[k], static_cast<double>(ms) / reps);
           }
-        c.fthreads = bt;
-        c.funroll = bu;
-        c.fms = bms < 1e30 ? bms : 0.0;
+        size_t kb = 0;
+        for (size_t k = 1; k < cand.size(); ++k)
+          if (best[k] < best[kb]) kb = k;
+        c.fthreads = cand[kb].first;
+        c.funroll = cand[kb].second;
+        c.fms = best[kb] < 1e30 ? best[kb] : 0.0;
       }
     } catch (...) {
       (void)hipEventDestroy(e0);
@@ -788,6 +798,7 @@ struct admm_ctx {
 
   // f(x) and (optionally) grad f(x) for patient p, x already in d_pvec at zvec_base
   double objective_dev(int p, float* grad_dev) {
+    if (!grad_dev) ensure_forward_tuned();
     const Pat& pt = H.pat[p];
     PassArgs pa = pass_args(mat32);
     pa.src = d_pvec;
@@ -1306,7 +1317,6 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->set_all_cfg();
     clk.mark("cached inverses");
     if (!c->dense) c->autotune();  // the dense x-update does not run the CG pass per iteration
-    c->tune_forward();
     check(hipEventCreate(&c->ev_a), "hipEventCreate");
     check(hipEventCreate(&c->ev_b), "hipEventCreate");
     check(hipStreamSynchronize(c->stream), "setup sync");
@@ -1400,6 +1410,7 @@ admm_status admm_spot_features(admm_ctx* ctx, int32_t patient, const uint8_t* vo
   for (int i = 0; i < pt.m; ++i)
     if (voxel_class[i] > 2) return set_err(ctx, ADMM_E_ARG, "voxel_class entries must be 0, 1 or 2");
   GUARD_BEGIN
+  ctx->ensure_forward_tuned();
   const int n = pt.n, m = pt.m, N = pt.num_scen;
   // indicator vectors of targets, organs at risk and all voxels
   std::vector<float> ind(static_cast<size_t>(3) * m);
@@ -1620,6 +1631,7 @@ admm_status admm_matvec(admm_ctx* ctx, int32_t patient, int32_t scen, const floa
   if (st != ADMM_OK) return st;
   if (!v || !out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
   GUARD_BEGIN
+  ctx->ensure_forward_tuned();
   const Pat& pt = ctx->H.pat[patient];
   const Scen& sc = ctx->H.scen[g];
   check(hipMemcpyAsync(ctx->d_pvec + pt.zvec_base, v, sizeof(float) * pt.n, hipMemcpyHostToDevice, ctx->stream), "H2D");
@@ -1788,6 +1800,7 @@ admm_status admm_rmatvec(admm_ctx* ctx, int32_t patient, int32_t scen, const flo
   if (st != ADMM_OK) return st;
   if (!t || !out) return set_err(ctx, ADMM_E_ARG, "NULL argument");
   GUARD_BEGIN
+  ctx->ensure_forward_tuned();
   const Pat& pt = ctx->H.pat[patient];
   const Scen& sc = ctx->H.scen[g];
   check(hipMemcpyAsync(ctx->d_mvec, t, sizeof(float) * pt.m, hipMemcpyHostToDevice, ctx->stream), "H2D");
@@ -1958,6 +1971,7 @@ admm_status pgd_solve_impl(admm_ctx* ctx, const pgd_options* popts, int32_t pati
     GUARD_END(ctx)
   }
   GUARD_BEGIN
+  ctx->ensure_forward_tuned();
   const Pat& pt = ctx->H.pat[patient];
   const int n = pt.n;
   float* x = ctx->d_pvec + pt.zvec_base;
@@ -2164,6 +2178,7 @@ admm_status admm_set_state(admm_ctx* ctx, int32_t patient, const double* z, cons
 admm_status admm_time_pass(admm_ctx* ctx, int32_t kind, int32_t reps, double* ms_out) {
   if (!ctx || !ms_out || kind < 0 || kind > 2 || reps < 1) return set_err(ctx, ADMM_E_ARG, "bad argument");
   GUARD_BEGIN
+  ctx->ensure_forward_tuned();
   PassArgs pa = ctx->pass_args(ctx->mat32);
   int mode = PASS_CG;
   if (kind == 0) {

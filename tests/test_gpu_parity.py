@@ -117,14 +117,16 @@ def test_pass_configuration_chosen_per_patient(tiny, small):
 
 def test_forward_configuration_tuned_per_patient_and_exact(tiny, small):
     """The forward, objective and transpose products take a configuration of
-    their own per patient (the fastest forward product at set-up, with either
-    x-update).  Each row's dot is formed by the same lanes in the same order
-    and the transpose product's fixed-point column sums are exact, so both
-    products are the same bit for bit in every configuration, and within the
-    per-entry bound of the fp64 products."""
+    their own per patient (the fastest forward product, chosen on the first
+    such product, with either x-update).  Each row's dot is formed by the same
+    lanes in the same order and the transpose product's fixed-point column
+    sums are exact, so both products are the same bit for bit in every
+    configuration, and within the per-entry bound of the fp64 products."""
     P, W, _, _ = small
     for xupdate in ("dense", "cg"):
         with _solver([tiny[0], P], xupdate=xupdate) as S:
+            assert S.forward_config(1)["pass_ms"] == 0.0  # not chosen before the first product
+            S.matvec(np.ones(P.n, dtype=np.float32), 0, patient=1)
             for p in (0, 1):
                 fc = S.forward_config(p)
                 assert fc["threads"] in (512, 1024) and fc["unroll"] in (1, 2) and fc["pass_ms"] > 0.0
