@@ -19,10 +19,13 @@
 //        A_:K = U, A_K: = U^T, A_KK = -P;
 //     after the last block A = -B_s^-1.  The sweep matrix stays symmetric, so
 //     only its upper 64 x 64 tiles are updated (half the work).  k_sweep_store writes M_s = B_s^-1 in fp32.
-//  4. every iteration: k_fheadobj (pending dual update and right-hand sides
-//     c_s, and the objective at z from the quadratic form, in one launch),
-//     k_xsym + k_xsym_reduce
-//     (x_s = M_s c_s).
+//  4. k_gq_pack: sum_s G_s rounded to 48 bits for the objective tiles.
+//  5. every iteration, four launches: k_dense_x (x_s = M_s c_s tile by tile,
+//     the previous iteration's stopping test in workgroup 0), k_xsym_reduce,
+//     the z-update, k_dense_tail_dual (residual norms and dual step, the dual
+//     update with the next right-hand sides c_s, the objective at the new z
+//     from the quadratic form).  k_fheadobj forms the right-hand sides and the
+//     objective of the state a run starts from.
 // The symmetric matrices used in every iteration (M_s and sum_s G_s) are stored
 // as their upper 64 x 64 tiles only, which halves the bytes each iteration reads.
 #include <hip/hip_ext.h>
