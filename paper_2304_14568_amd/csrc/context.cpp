@@ -344,6 +344,7 @@ struct admm_ctx {
     f.Gq = d_Gq;
     f.fpart = d_fpart;
     f.npmax = ld_max;
+    f.npat = P;
     return f;
   }
 

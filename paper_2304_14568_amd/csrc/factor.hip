@@ -552,22 +552,34 @@ __device__ __forceinline__ double dpp_f64(double x) {
 // fp64: the inverse has entries of both signs and |M| |c| exceeds |M c| by two
 // orders of magnitude, so fp32 sums would put a floor of about 1e-5 relative
 // under every x-update; the fp32 storage of M itself contributes about 1e-6.
+// kLoadsFirst (a context of one patient): the tile's 16 KB (tile idx of the
+// table is stored at Mp + 4096 idx) are requested before the table and
+// stop-flag reads, and the empty statement keeps the compiler from moving the
+// loads below the early exit (a stopped patient ends the run within an
+// iteration).  Otherwise (a batch, whose other patients go on iterating) the
+// flag is read first and a stopped patient's tiles are not loaded at all.
+template <bool kLoadsFirst>
 __device__ __forceinline__ void xsym_tile(const FactorArgs& f, const double* __restrict__ c, int idx) {
   __shared__ double2 cI[kFb / 2], cJ[kFb / 2];
   __shared__ double bpart[4][kFb];  // column sums of each wave
   const int tid = threadIdx.x;
   const int rb = tid >> 4, cb = tid & 15, lane = tid & 63;
-  // the tile's 16 KB (tile idx of the table is stored at Mp + 4096 idx) does
-  // not wait for the table; the empty statement keeps the compiler from moving
-  // the loads below the early exit
   const float4* T = reinterpret_cast<const float4*>(f.Mp) + static_cast<int64_t>(idx) * 1024;
   float4 m[4];
+  XTile tj;
+  if constexpr (kLoadsFirst) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) m[k] = T[k * 256 + tid];
-  const XTile tj = f.xtiles[idx];
-  const bool stopped = f.ps[tj.patient].stopped != 0;
-  asm volatile("" ::: "memory");
-  if (stopped) return;
+    for (int k = 0; k < 4; ++k) m[k] = T[k * 256 + tid];
+    tj = f.xtiles[idx];
+    const bool stopped = f.ps[tj.patient].stopped != 0;
+    asm volatile("" ::: "memory");
+    if (stopped) return;
+  } else {
+    tj = f.xtiles[idx];
+    if (f.ps[tj.patient].stopped) return;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = T[k * 256 + tid];
+  }
   if (tid < kFb) {
     const int jc = tj.J * kFb + tid, ic = tj.I * kFb + tid;
     reinterpret_cast<double*>(cJ)[tid] = jc < tj.n ? c[tj.vbase + jc] : 0.0;
@@ -636,8 +648,9 @@ __device__ __forceinline__ int xsym_order(const FactorArgs& f, int b) {
   return (f.ps[0].iter & 1) ? f.nxtiles - 1 - b : b;
 }
 
+template <bool kLoadsFirst>
 __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __restrict__ c) {
-  xsym_tile(f, c, xsym_order(f, static_cast<int>(blockIdx.x)));
+  xsym_tile<kLoadsFirst>(f, c, xsym_order(f, static_cast<int>(blockIdx.x)));
 }
 
 // x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
@@ -890,12 +903,13 @@ __global__ __launch_bounds__(256) void k_dense_head(VecArgs a, int nblk) {
 //         objective tiles at the new z.
 // Every value equals the five-launch order's; the stopping test of the last
 // iteration of a run follows in a launch of its own.
+template <bool kLoadsFirst>
 __global__ __launch_bounds__(256) void k_dense_x(FactorArgs f, VecArgs a, const double* __restrict__ c) {
   if (blockIdx.x == 0) {
     head_scalars_run<true>(a, 0, 0);
     return;
   }
-  xsym_tile(f, c, xsym_order(f, static_cast<int>(blockIdx.x) - 1));
+  xsym_tile<kLoadsFirst>(f, c, xsym_order(f, static_cast<int>(blockIdx.x) - 1));
 }
 
 __global__ __launch_bounds__(256) void k_dense_tail_dual(FactorArgs f, VecArgs a, int nfobj, int nblk) {
@@ -1001,10 +1015,11 @@ void launch_sweep_store(FactorArgs f, int patient, int scen_begin, int nscen, in
 void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   if (njobs <= 0) return;
   const int grid = njobs;
+  auto kern = f.npat == 1 ? k_xsym<true> : k_xsym<false>;
   if (e0 != nullptr)
-    hipExtLaunchKernelGGL(k_xsym, dim3(grid), dim3(256), 0, st, e0, e1, 0, f, c);
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, e0, e1, 0, f, c);
   else
-    hipLaunchKernelGGL(k_xsym, dim3(grid), dim3(256), 0, st, f, c);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, f, c);
 }
 
 void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st) {
@@ -1023,10 +1038,11 @@ void launch_dense_head(const VecArgs& a, int nblk, hipStream_t st) {
 void launch_dense_x(const FactorArgs& f, const VecArgs& a, const double* c, int njobs, hipStream_t st, hipEvent_t e0,
                     hipEvent_t e1) {
   const dim3 grid(static_cast<unsigned>(1 + njobs));
+  auto kern = f.npat == 1 ? k_dense_x<true> : k_dense_x<false>;
   if (e0 != nullptr)
-    hipExtLaunchKernelGGL(k_dense_x, grid, dim3(256), 0, st, e0, e1, 0, f, a, c);
+    hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, st, e0, e1, 0, f, a, c);
   else
-    hipLaunchKernelGGL(k_dense_x, grid, dim3(256), 0, st, f, a, c);
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, f, a, c);
 }
 
 void launch_dense_tail_dual(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st) {

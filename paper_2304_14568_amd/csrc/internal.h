@@ -265,7 +265,7 @@ struct FactorArgs {
   uint32_t* Gq;       // objective: Gp rounded to 48 bits, tile k of fjobs at 6144 k (layout in fobj_tile)
   double* fpart;      // objective partial per objective job
   int32_t npmax;      // largest npad
-  int32_t pad;
+  int32_t npat;       // patients of the context
 };
 
 // ---- launchers (kernels.hip) ----
