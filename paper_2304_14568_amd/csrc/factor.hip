@@ -47,11 +47,7 @@ __host__ __device__ __forceinline__ int64_t tile_index(int I, int J, int nb) {
   return static_cast<int64_t>(I) * nb - static_cast<int64_t>(I) * (I - 1) / 2 + (J - I);
 }
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum_d(double v) { return group_allsum<64>(v); }
 
 // ---------------------------------------------------------------------------
 // Gram matrix
@@ -525,20 +521,10 @@ __global__ __launch_bounds__(256) void k_sweep_store(FactorArgs f, int patient, 
 // per-iteration kernels
 // ---------------------------------------------------------------------------
 
-// x from lane (lane ^ 1) or (lane ^ 2) of the same quad, or from lane
-// (lane - n) mod 16 of the same row of 16 lanes: one DPP move per 32-bit half,
-// no LDS.
-constexpr int kDppXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
-constexpr int kDppXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+// Row rotations by DPP for the x-update's row sums (the pair and quad
+// exchanges are those of scalars.h).
 constexpr int kDppRor4 = 0x124;
 constexpr int kDppRor8 = 0x128;
-template <int kCtrl>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(v), kCtrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(v >> 32), kCtrl, 0xF, 0xF, false);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
 
 // One packed tile T = M_s[I, J] (I <= J) per workgroup: a = T c_J and, off
 // the diagonal, b = T^T c_I (the tile's contribution to the rows of block J).
@@ -602,11 +588,11 @@ __device__ __forceinline__ void xsym_tile(const FactorArgs& f, const double* __r
   // a row add up by rotations of 4 and 8
   const bool b0 = (cb & 1) != 0, b1 = (cb & 2) != 0;
   double k0 = b0 ? a[1] : a[0], k1 = b0 ? a[3] : a[2];
-  k0 += dpp_f64<kDppXor1>(b0 ? a[0] : a[1]);
-  k1 += dpp_f64<kDppXor1>(b0 ? a[2] : a[3]);
-  double r = (b1 ? k1 : k0) + dpp_f64<kDppXor2>(b1 ? k0 : k1);
-  r += dpp_f64<kDppRor8>(r);
-  r += dpp_f64<kDppRor4>(r);
+  k0 += dpp_move<kDppXor1>(b0 ? a[0] : a[1]);
+  k1 += dpp_move<kDppXor1>(b0 ? a[2] : a[3]);
+  double r = (b1 ? k1 : k0) + dpp_move<kDppXor2>(b1 ? k0 : k1);
+  r += dpp_move<kDppRor8>(r);
+  r += dpp_move<kDppRor4>(r);
   double* out = f.xpart + static_cast<int64_t>(idx) * (2 * kFb);
   if (cb < 4) out[4 * rb + cb] = r;
   if (tj.I == tj.J) return;

@@ -255,8 +255,7 @@ __device__ __forceinline__ void pass_rows(const PassArgs& a, const Tile& t, cons
         ld(c, v4, c4);
         dot4(c4, v4, dot);
       }
-#pragma unroll
-      for (int off = L / 2; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+      dot = group_allsum<L>(dot);
       if constexpr (MODE == PASS_MATVEC) {
         if (lane == 0) a.tout[a.mat.rorig[rb + r]] = static_cast<float>(dot);
       } else if constexpr (kDot64) {
@@ -404,8 +403,7 @@ __device__ __forceinline__ void pass_slices(const PassArgs& a, const Tile& t, co
         ld(c, v4, c4);
         dot4(c4, v4, dot);
       }
-#pragma unroll
-      for (int off = L / 2; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+      dot = group_allsum<L>(dot);
       if constexpr (MODE == PASS_MATVEC) {
         if (real && (lane % L) == 0) a.tout[a.mat.rorig[rb + r]] = static_cast<float>(dot);
       } else if constexpr (kDot64) {

@@ -9,24 +9,56 @@
 
 namespace admmbb {
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+// Lane exchanges inside a row of 16 lanes by DPP moves (vector ALU, no LDS):
+// pairs (kDppXor1), pairs of pairs (kDppXor2), lane 7 - i of each half-row
+// (kDppHalfMirror) and lane 15 - i of the row (kDppMirror).
+constexpr int kDppXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), kCtrl, 0xF, 0xF, false));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(v >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Sum over aligned groups of L lanes (L a power of two, at most 64; every lane
+// of a group active), every lane of a group getting the same bits: at each
+// step the two partners add the same two values.  Pairs and quads exchange by
+// DPP; after that every lane of a quad holds the quad's sum, so the mirror of
+// a half-row pairs whole quads and the mirror of a row whole half-rows; rows
+// exchange by shuffles.  A fixed order: the same inputs give the same bits.
+template <int L, class T>
+__device__ __forceinline__ T group_allsum(T x) {
+  static_assert(L >= 1 && L <= 64 && (L & (L - 1)) == 0, "L a power of two up to 64");
+  if constexpr (L >= 2) x += dpp_move<kDppXor1>(x);
+  if constexpr (L >= 4) x += dpp_move<kDppXor2>(x);
+  if constexpr (L >= 8) x += dpp_move<kDppHalfMirror>(x);
+  if constexpr (L >= 16) x += dpp_move<kDppMirror>(x);
+  if constexpr (L >= 32) x += __shfl_xor(x, 16, 64);
+  if constexpr (L >= 64) x += __shfl_xor(x, 32, 64);
   return x;
 }
 
+// Sum over the wave; every lane returns it.
+__device__ __forceinline__ double wave_sum(double x) { return group_allsum<64>(x); }
+
 // Sum of p[b * 8] for b < count by one wave: lane l adds entries l, l+64, ...
-// then a fixed butterfly; every lane returns the same total.
+// then group_allsum; every lane returns the same total.
 __device__ __forceinline__ double wave_strided_sum(const double* p, int count) {
   double s = 0.0;
   for (int b = threadIdx.x & 63; b < count; b += 64) s += p[static_cast<int64_t>(b) * 8];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  return s;
+  return group_allsum<64>(s);
 }
 
 // NV interleaved sums by one wave: v[k] = sum over b < count of p[b * 8 + k0 + k],
-// lane l adding entries l, l + 64, ... in order, then a fixed butterfly; every
+// lane l adding entries l, l + 64, ... in order, then group_allsum; every
 // lane returns the totals.  Any subset of k gives the same bits for its sums.
 template <int NV>
 __device__ __forceinline__ void wave_strided_sums(const double* p, int count, int k0, double (&v)[NV]) {
@@ -37,10 +69,7 @@ __device__ __forceinline__ void wave_strided_sums(const double* p, int count, in
     for (int k = 0; k < NV; ++k) v[k] += p[static_cast<int64_t>(b) * 8 + k0 + k];
   }
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-  }
+  for (int k = 0; k < NV; ++k) v[k] = group_allsum<64>(v[k]);
 }
 
 // Dual step of Sec. 2.2: the Barzilai-Borwein value beta = -<dd, dy> / ||dd||^2
