@@ -28,12 +28,48 @@ __device__ __forceinline__ double dpp_move(double x) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
+// x[l] + x[l ^ 16] (k = 16) or x[l] + x[l ^ 32] (k = 32) in every lane, by the
+// gfx950 lane swaps: v_permlane16_swap of (x, x) leaves rows 0 and 2 of x in
+// the first result and rows 1 and 3 in the second, each beside its partner
+// row, and v_permlane32_swap the lower and the upper half likewise; both
+// partners add the same two operands in the same order.
+template <int k>
+__device__ __forceinline__ void lane_swap(uint32_t u, uint32_t& first, uint32_t& second) {
+  static_assert(k == 16 || k == 32, "rows or half-waves");
+  if constexpr (k == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    first = r[0];
+    second = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    first = r[0];
+    second = r[1];
+  }
+}
+template <int k>
+__device__ __forceinline__ float swap_sum(float x) {
+  uint32_t a = 0, b = 0;
+  lane_swap<k>(__float_as_uint(x), a, b);
+  return __uint_as_float(a) + __uint_as_float(b);
+}
+template <int k>
+__device__ __forceinline__ double swap_sum(double x) {
+  const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(x));
+  uint32_t la = 0, lb = 0, ha = 0, hb = 0;
+  lane_swap<k>(static_cast<uint32_t>(u), la, lb);
+  lane_swap<k>(static_cast<uint32_t>(u >> 32), ha, hb);
+  const double a = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(ha) << 32) | la));
+  const double b = __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hb) << 32) | lb));
+  return a + b;
+}
+
 // Sum over aligned groups of L lanes (L a power of two, at most 64; every lane
 // of a group active), every lane of a group getting the same bits: at each
 // step the two partners add the same two values.  Pairs and quads exchange by
 // DPP; after that every lane of a quad holds the quad's sum, so the mirror of
 // a half-row pairs whole quads and the mirror of a row whole half-rows; rows
-// exchange by shuffles.  A fixed order: the same inputs give the same bits.
+// and half-waves by the lane swaps above.  All on the vector ALU, in a fixed
+// order: the same inputs give the same bits.
 template <int L, class T>
 __device__ __forceinline__ T group_allsum(T x) {
   static_assert(L >= 1 && L <= 64 && (L & (L - 1)) == 0, "L a power of two up to 64");
@@ -41,8 +77,8 @@ __device__ __forceinline__ T group_allsum(T x) {
   if constexpr (L >= 4) x += dpp_move<kDppXor2>(x);
   if constexpr (L >= 8) x += dpp_move<kDppHalfMirror>(x);
   if constexpr (L >= 16) x += dpp_move<kDppMirror>(x);
-  if constexpr (L >= 32) x += __shfl_xor(x, 16, 64);
-  if constexpr (L >= 64) x += __shfl_xor(x, 32, 64);
+  if constexpr (L >= 32) x = swap_sum<16>(x);
+  if constexpr (L >= 64) x = swap_sum<32>(x);
   return x;
 }
 
