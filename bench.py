@@ -208,8 +208,8 @@ def main():
     ap.add_argument("--format", default="auto", choices=["auto", "csr", "sell"],
                     help="layout of A_s for the sparse passes (auto: the set-up autotuner picks)")
     ap.add_argument("--cg-max", type=int, default=8)
-    ap.add_argument("--dense-launches", type=int, default=4, choices=[4, 5],
-                    help="dense x-update: four launches per iteration (default) or the five-launch order")
+    ap.add_argument("--dense-launches", type=int, default=3, choices=[3, 4],
+                    help="dense x-update: three launches per iteration (default) or four, each iteration complete at its end")
     ap.add_argument("--xupdate", default="auto", choices=["auto", "cg", "dense"],
                     help="x-update: warm-started CG on the sparse A_s, or the cached dense inverse")
     ap.add_argument("--seed", type=int, default=0)
@@ -293,7 +293,7 @@ def main():
     if xmode == "dense":
         # x-update roofline: every launch reads each scenario's packed fp32
         # inverse once (upper 64 x 64 tiles of M_s, 16 KiB each) and its fp64
-        # right-hand side; in the four-launch order the same launch (k_dense_x)
+        # right-hand side; in the three-launch order the same launch (k_dense_x)
         # runs the previous iteration's stopping test in its workgroup 0
         nb = (P.n + 63) // 64
         tiles = nb * (nb + 1) // 2
@@ -302,14 +302,14 @@ def main():
         achieved = bytes_per_launch / (tm["pass_ms"] * 1e-3) / 1e9 if tm["pass_ms"] > 0 else 0.0
         traffic = None
         src = os.path.join(ROOT, "paper_2304_14568_amd", "csrc", "factor.hip")
-        if (args.seed == 0 and args.dense_launches == 4 and os.path.exists(src) and
+        if (args.seed == 0 and args.dense_launches == 3 and os.path.exists(src) and
                 XSYM_TRAFFIC["source_hashes"] is not None and
                 kernel_source_hash(src, "__device__ __forceinline__ void xsym_tile(") +
                 kernel_source_hash(src, "__global__ __launch_bounds__(256) void k_dense_x(") ==
                 XSYM_TRAFFIC["source_hashes"]):
             traffic = XSYM_TRAFFIC["fetch_bytes"] + XSYM_TRAFFIC["write_bytes"]
         kname = ("k_dense_x (x_s = M_s c_s over the packed upper tiles of the cached fp32 inverses, beside the "
-                 "previous iteration's stopping test)" if args.dense_launches == 4 else
+                 "previous iteration's stopping test)" if args.dense_launches == 3 else
                  "k_xsym (x_s = M_s c_s over the packed upper tiles of the cached fp32 inverses)")
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,

@@ -162,12 +162,12 @@ typedef struct {
                           fixed-point column accumulators, lds_acc -1 or 2 required), so runs and
                           resumed runs repeat bit for bit; default 0 (the autotuner may pick fp64
                           LDS atomics, whose sums depend on the order of the additions) */
-  int32_t dense_launches; /* dense x-update: 4 (default) = four launches per iteration, the
+  int32_t dense_launches; /* dense x-update: 3 (default) = three launches per iteration, the
                           stopping test of an iteration evaluated beside the next iteration's
                           x-update (and after the last one in a launch of its own) and the dual
-                          update beside the dual step; 5 = five launches, each iteration
+                          update beside the dual step; 4 = four launches, each iteration
                           complete at its end.  The iterates, scalars and stopping decisions
-                          are the same bit for bit; with 4 the device computes one more
+                          are the same bit for bit; with 3 the device computes one more
                           x-update of a patient that has just stopped, and discards it */
   void* stream;        /* hipStream_t for all device work; NULL = library-owned stream */
 } admm_options;

@@ -130,11 +130,10 @@ struct admm_ctx {
   float* d_Mp = nullptr;
   double *d_xpart = nullptr, *d_c64 = nullptr, *d_b64 = nullptr;
   double* d_rw64 = nullptr;
-  RJob* d_rjobs = nullptr;
   XJob* d_fjobs = nullptr;
   uint32_t* d_Gq = nullptr;
   XTile* d_xtiles = nullptr;
-  int n_xjobs = 0, n_rjobs = 0, n_fjobs = 0, ld_max = 0;
+  int n_xjobs = 0, n_fjobs = 0, ld_max = 0;
   int64_t gp_elems = 0;
   std::vector<double> factored_rho;  // per patient: penalty of the cached inverse
   std::vector<int> chunk_scen;       // per patient: scenarios per set-up chunk
@@ -339,7 +338,6 @@ struct admm_ctx {
     f.xpart = d_xpart;
     f.xtiles = d_xtiles;
     f.nxtiles = n_xjobs;
-    f.rjobs = d_rjobs;
     f.fjobs = d_fjobs;
     f.Gq = d_Gq;
     f.fpart = d_fpart;
@@ -459,7 +457,7 @@ struct admm_ctx {
     VecArgs va = vec_args(stop_enabled);
     if (dense) {
       const FactorArgs f = fargs();
-      if (opts.dense_launches == 4) {
+      if (opts.dense_launches == 3) {
         // the previous iteration's stopping test beside the x-update tiles;
         // the reduction and z-update; residual norms and dual step beside the
         // dual update, the next right-hand sides and the objective tiles
@@ -467,8 +465,7 @@ struct admm_ctx {
           launch_dense_x(f, va, d_c64, n_xjobs, stream, ev[0], ev[1]);
         else
           launch_dense_x(f, va, d_c64, n_xjobs, stream);
-        launch_xsym_reduce(f, d_x, n_rjobs, stream);
-        launch_zres(va, NPB, stream);
+        launch_xzres(f, va, NPB, stream);
         launch_dense_tail_dual(f, va, n_fjobs, NB, stream);
         return;
       }
@@ -476,8 +473,7 @@ struct admm_ctx {
         launch_xsym(f, d_c64, n_xjobs, stream, ev[0], ev[1]);
       else
         launch_xsym(f, d_c64, n_xjobs, stream);
-      launch_xsym_reduce(f, d_x, n_rjobs, stream);
-      launch_zres(va, NPB, stream);
+      launch_xzres(f, va, NPB, stream);
       // residual norms and BB step beside the objective tiles at the new z,
       // then the stopping test beside the dual update and the next right-hand
       // sides: the iteration ends complete, with no head of its own next time
@@ -563,9 +559,9 @@ struct admm_ctx {
   // final head completes the bookkeeping of the last one.  Dense x-update: one
   // head before the first iteration forms the right-hand sides and the
   // objective of the state the run starts from (completing a pending dual
-  // update, as left by a checkpoint); in the five-launch order each iteration
+  // update, as left by a checkpoint); in the four-launch order each iteration
   // then ends complete (stopping test, dual update, next right-hand sides), in
-  // the four-launch order the stopping test of each iteration runs in the
+  // the three-launch order the stopping test of each iteration runs in the
   // next one's first launch, and a final one follows the loop.  There the host
   // sees a stop one iteration late; the iteration between is skipped on the
   // device.
@@ -591,7 +587,7 @@ struct admm_ctx {
       }
     }
     if (!dense) launch_head(stop_enabled, 0);
-    if (dense && opts.dense_launches == 4) launch_dense_head(vec_args(stop_enabled), 0, stream);
+    if (dense && opts.dense_launches == 3) launch_dense_head(vec_args(stop_enabled), 0, stream);
     if (timing) {
       check(hipEventRecord(ev_b, stream), "hipEventRecord");
       check(hipEventSynchronize(ev_b), "hipEventSynchronize");
@@ -892,7 +888,7 @@ admm_status admm_default_options(admm_options* o) {
   o->pass_unroll = 0;
   o->format = -1;
   o->deterministic = 0;
-  o->dense_launches = 4;
+  o->dense_launches = 3;
   o->xupdate = ADMM_XUPDATE_AUTO;
   o->stream = nullptr;
   return ADMM_OK;
@@ -1103,7 +1099,6 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
     c->trace_cap = std::max(1, o.max_iter + 2);
 
     // dense x-update: sizes, offsets and work lists (before the tables go to the device)
-    std::vector<RJob> rjobs;
     std::vector<XJob> fjobs;
     std::vector<XTile> xtiles;
     // dense set-up works on chunks of scenarios: G and the sweep matrix (fp64,
@@ -1153,11 +1148,9 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
               xt.J = J;
               xtiles.push_back(xt);
             }
-          for (int I = 0; I < pt.nbk; ++I) rjobs.push_back(RJob{(sc.mpack_off / 4096) * 128, sc.vec_base, I, pt.nbk, pt.n, p});
         }
       }
       c->n_xjobs = static_cast<int>(xtiles.size());
-      c->n_rjobs = static_cast<int>(rjobs.size());
       c->n_fjobs = static_cast<int>(fjobs.size());
       c->d_G = c->alloc<double>(static_cast<size_t>(chunk_elems));
       c->d_Aw = c->alloc<double>(static_cast<size_t>(chunk_elems));
@@ -1172,7 +1165,6 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       c->d_R = c->alloc<double>(static_cast<size_t>(c->G) * 64 * c->ld_max);
       c->d_fpart = c->alloc<double>(fjobs.size());
       c->d_xtiles = c->upload(xtiles);
-      c->d_rjobs = c->upload(rjobs);
       c->d_fjobs = c->upload(fjobs);
       c->d_Gq = c->alloc<uint32_t>(static_cast<size_t>(goff / 4096) * 6144);
       std::vector<double> g0all(static_cast<size_t>(H.zvec_total));
@@ -1206,7 +1198,8 @@ admm_status admm_setup_batch(const admm_problem* probs, int32_t num_patients, co
       std::vector<ZJob> zj(H.pblk.size());
       for (size_t b = 0; b < H.pblk.size(); ++b) {
         const Pat& pt = H.pat[static_cast<size_t>(H.pblk[b].owner)];
-        zj[b] = ZJob{pt.vec_base, pt.zvec_base, pt.n, pt.num_scen, H.pblk[b].col0, H.pblk[b].owner};
+        const int64_t xt0 = c->dense ? H.scen[static_cast<size_t>(pt.scen_begin)].mpack_off / 4096 : 0;
+        zj[b] = ZJob{pt.vec_base, pt.zvec_base, pt.n, pt.num_scen, H.pblk[b].col0, H.pblk[b].owner, xt0};
       }
       c->d_zjobs = c->upload(zj);
     }

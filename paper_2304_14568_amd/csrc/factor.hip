@@ -20,9 +20,10 @@
 //     after the last block A = -B_s^-1.  The sweep matrix stays symmetric, so
 //     only its upper 64 x 64 tiles are updated (half the work).  k_sweep_store writes M_s = B_s^-1 in fp32.
 //  4. k_gq_pack: sum_s G_s rounded to 48 bits for the objective tiles.
-//  5. every iteration, four launches: k_dense_x (x_s = M_s c_s tile by tile,
-//     the previous iteration's stopping test in workgroup 0), k_xsym_reduce,
-//     the z-update, k_dense_tail_dual (residual norms and dual step, the dual
+//  5. every iteration, three launches: k_dense_x (x_s = M_s c_s tile by tile,
+//     the previous iteration's stopping test in workgroup 0), k_xzres (the
+//     partial sums of x_s with the z-update), k_dense_tail_dual (residual
+//     norms and dual step, the dual
 //     update with the next right-hand sides c_s, the objective at the new z
 //     from the quadratic form).  k_fheadobj forms the right-hand sides and the
 //     objective of the state a run starts from.
@@ -639,38 +640,129 @@ __global__ __launch_bounds__(256) void k_xsym(FactorArgs f, const double* __rest
   xsym_tile<kLoadsFirst>(f, c, xsym_order(f, static_cast<int>(blockIdx.x)));
 }
 
-// x_s rows of block I: sum over J >= I of (T_IJ c_J) and over J < I of
-// (T_JI^T c_J).  Wave w of kXrWaves adds the blocks J = w, w + kXrWaves, ...;
-// the wave sums are then added pairwise in a fixed order.
-constexpr int kXrWaves = 8;  // the final sum below adds eight wave sums
-static_assert(kXrWaves == 8, "the pairwise sum of the wave sums is written out for eight waves");
-__global__ __launch_bounds__(64 * kXrWaves) void k_xsym_reduce(FactorArgs f, float* __restrict__ x) {
-  __shared__ double part[kXrWaves][kFb];
-  const RJob job = f.rjobs[blockIdx.x];
-  const int I = job.I, nb = job.nb;
-  const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
-  const double* base = f.xpart + job.part;
-  const int stopped = f.ps[job.patient].stopped;  // read beside the partials; gates the write only
-  // four independent accumulators keep four loads in flight per lane
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  auto ld = [&](int J) {
-    return (J < I) ? base[tile_index(J, I, nb) * (2 * kFb) + kFb + i] : base[tile_index(I, J, nb) * (2 * kFb) + i];
-  };
-  int J = w;
-  for (; J + 3 * kXrWaves < nb; J += 4 * kXrWaves) {
-    s0 += ld(J);
-    s1 += ld(J + kXrWaves);
-    s2 += ld(J + 2 * kXrWaves);
-    s3 += ld(J + 3 * kXrWaves);
+// The reduction of the x-update partials fused with the z-update (the dense
+// x-update's iteration, both launch orders): one workgroup per 16 spots of a
+// patient (a quarter of a column block, the z-update's job), one wave per
+// scenario (waves w, w + 16, ... for more than 16).  For the wave's scenario
+// its four 16-lane groups g add the partials of the tiles J = g, g + 4, ...
+// of the spots' row block I (T_IJ c_J for J >= I, T_JI^T c_J below), each
+// lane one spot, then across the groups by lane swaps: x_s of the 16 spots,
+// rounded to fp32 as stored.  Then the z-update of k_zres on the same spots:
+// z = P(mean_s(x_s + y_s / rho)) in a fixed order over the waves, d = x_s - z
+// and the eight fp64 partial sums of the residuals and the dual step.
+constexpr int kXzWaves = 16;
+constexpr int kXzCols = 16;
+__global__ __launch_bounds__(64 * kXzWaves) void k_xzres(FactorArgs f, VecArgs a) {
+  __shared__ double sacc[kXzWaves][kXzCols];
+  __shared__ float zsh[kXzCols];
+  __shared__ double sred[kXzWaves][8];
+  const int bi4 = static_cast<int>(blockIdx.x);
+  const ZJob pt = a.zjobs[bi4 >> 2];
+  const PatState* ps = a.ps + pt.patient;
+  const int stopped = ps->stopped;  // read beside the loads below; checked before any write
+  const double rho = ps->rho;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  const int r = (bi4 & 3) * kXzCols + c;  // row within the block of 64 spots
+  const int j = pt.col0 + r;
+  const bool valid = j < pt.n;
+  const int I = pt.col0 / kFb, nb = (pt.n + kFb - 1) / kFb;
+  const int64_t ntile = static_cast<int64_t>(nb) * (nb + 1) / 2;
+  const int64_t zi = pt.zvec_base + j;
+  // the first scenario's vectors and the projection's inputs, requested first
+  float y0 = 0.0f, lbv = 0.0f, ubv = 0.0f, zold = 0.0f;
+  double dp0 = 0.0;
+  if (valid && g == 0 && w < pt.N) {
+    const int64_t vi = pt.vec_base + static_cast<int64_t>(w) * pt.n + j;
+    y0 = a.y[vi];
+    dp0 = a.dprev[vi];
   }
-  for (; J < nb; J += kXrWaves) s0 += ld(J);
-  part[w][i] = (s0 + s1) + (s2 + s3);
+  if (valid && tid < kXzCols) {
+    lbv = a.lb[zi];
+    ubv = a.ub[zi];
+    zold = a.z[zi];
+  }
+  // x_s of the wave's scenarios and their sum with y_s / rho
+  float x0 = 0.0f;
+  double zacc = 0.0;
+  const int wu = __builtin_amdgcn_readfirstlane(w);  // the wave's index, as a scalar
+  for (int s = wu; s < pt.N; s += kXzWaves) {
+    // the scenario's partials (a scalar base) and 32-bit offsets per lane
+    const double* xp = f.xpart + (pt.xtile0 + static_cast<int64_t>(s) * ntile) * (2 * kFb);
+    // the group's tiles J = g + 4k, twelve loads in flight per lane, added in
+    // the order of k
+    double acc = 0.0;
+    if (valid) {
+      for (int J0 = g; J0 < nb; J0 += 48) {
+        double q[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          const int J = J0 + 4 * k;
+          const int off = J < I ? static_cast<int>(tile_index(J, I, nb)) * (2 * kFb) + kFb + r
+                                : static_cast<int>(tile_index(I, J, nb)) * (2 * kFb) + r;
+          q[k] = J >= nb ? 0.0 : xp[off];
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc += q[k];
+      }
+    }
+    const double xs = swap_sum<32>(swap_sum<16>(acc));
+    const float xf = static_cast<float>(xs);
+    const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
+    if (g == 0 && valid) {
+      const float yv = s == wu ? y0 : a.y[vi];
+      if (!stopped) a.x[vi] = xf;
+      zacc += static_cast<double>(xf);
+      if (a.prm.z_mode == 0) zacc += static_cast<double>(yv) / rho;
+    }
+    if (s == wu) x0 = xf;
+  }
+  if (stopped) return;  // the whole workgroup: one patient
+  if (g == 0) sacc[w][c] = zacc;
   __syncthreads();
-  if (w == 0 && !stopped) {
-    const int row = I * kFb + i;
-    if (row < job.n)
-      x[job.vbase + row] = static_cast<float>(((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) +
-                                              ((part[4][i] + part[5][i]) + (part[6][i] + part[7][i])));
+  // ||dz||^2, ||z||^2, ||d||^2, <dd,d_prev>, ||dd||^2, ||x||^2, <y,d>, ||y||^2
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (tid < kXzCols) {
+    float znf = 0.0f;
+    if (valid) {
+      double sum = 0.0;
+      for (int q = 0; q < kXzWaves; ++q) sum += sacc[q][c];
+      double zn = sum / pt.N;
+      zn = fmin(fmax(zn, static_cast<double>(lbv)), static_cast<double>(ubv));
+      znf = static_cast<float>(zn);
+      const double dz = static_cast<double>(znf) - static_cast<double>(zold);
+      a.z[zi] = znf;
+      v[0] = dz * dz;
+      v[1] = static_cast<double>(znf) * znf;
+    }
+    zsh[c] = znf;
+  }
+  __syncthreads();
+  if (valid && g == 0) {
+    const double znd = static_cast<double>(zsh[c]);
+    for (int s = w; s < pt.N; s += kXzWaves) {
+      const int64_t vi = pt.vec_base + static_cast<int64_t>(s) * pt.n + j;
+      const double xv = static_cast<double>(s == w ? x0 : a.x[vi]);
+      const double yv = static_cast<double>(s == w ? y0 : a.y[vi]);
+      const double d = xv - znd;
+      const double dp = s == w ? dp0 : a.dprev[vi];
+      const double dd = d - dp;
+      v[2] += d * d;
+      v[3] += dd * dp;
+      v[4] += dd * dd;
+      v[5] += xv * xv;
+      v[6] += yv * d;
+      v[7] += yv * yv;
+      a.dprev[vi] = d;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = group_allsum<64>(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < 8; ++k) sred[w][k] = v[k];
+  __syncthreads();
+  if (tid < 8) {
+    auto q4 = [&](int b) { return (sred[b][tid] + sred[b + 1][tid]) + (sred[b + 2][tid] + sred[b + 3][tid]); };
+    a.bpartp[static_cast<int64_t>(bi4) * 8 + tid] = (q4(0) + q4(4)) + (q4(8) + q4(12));
   }
 }
 
@@ -796,7 +888,7 @@ __device__ __forceinline__ void fobj_tile(const FactorArgs& f, const float* __re
   if (tid == 0) f.fpart[jb] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// The five-launch dense iteration ends with two launches that each pair one
+// The four-launch dense iteration ends with two launches that each pair one
 // scalar workgroup with independent wide work:
 //   tail: workgroup 0 the residual norms, tolerances and BB step of every
 //         patient (body_scalars_run), the others the objective tiles at the
@@ -876,7 +968,7 @@ __global__ __launch_bounds__(256) void k_dense_head(VecArgs a, int nblk) {
   if (bi < nblk) dense_head_block(a, bi, threadIdx.x & 63);
 }
 
-// The four-launch dense iteration (the reduction and the z-update between them):
+// The three-launch dense iteration (the reduction and the z-update between them):
 //   x:    workgroup 0 the objective sums and stopping test of the previous
 //         iteration (head_scalars_run), the others the x-update tiles.  The
 //         tiles read the stop flag that workgroup 0 may be setting: a tile of
@@ -887,7 +979,7 @@ __global__ __launch_bounds__(256) void k_dense_head(VecArgs a, int nblk) {
 //         (body_scalars_run), then the dual update with the next right-hand
 //         sides (each wave forms tau itself, dense_dual_block), then the
 //         objective tiles at the new z.
-// Every value equals the five-launch order's; the stopping test of the last
+// Every value equals the four-launch order's; the stopping test of the last
 // iteration of a run follows in a launch of its own.
 template <bool kLoadsFirst>
 __global__ __launch_bounds__(256) void k_dense_x(FactorArgs f, VecArgs a, const double* __restrict__ c) {
@@ -1008,9 +1100,9 @@ void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, f, c);
 }
 
-void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st) {
-  if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_xsym_reduce, dim3(njobs), dim3(64 * kXrWaves), 0, st, f, x);
+void launch_xzres(const FactorArgs& f, const VecArgs& a, int npblk, hipStream_t st) {
+  if (npblk <= 0) return;
+  hipLaunchKernelGGL(k_xzres, dim3(static_cast<unsigned>(4 * npblk)), dim3(64 * kXzWaves), 0, st, f, a);
 }
 
 void launch_dense_tail(const FactorArgs& f, const VecArgs& a, int nfobj, hipStream_t st) {

@@ -90,7 +90,7 @@ struct PatState {
   int32_t status;      // 0 running, 1 converged, 2 diverged (non-finite)
   int32_t cg_steps;    // CG steps (summed over scenarios) of the last iteration
   int32_t cg_total;
-  int32_t dual_go;     // dense five-launch iteration: the head launch applies the pending dual update
+  int32_t dual_go;     // dense four-launch iteration: the head launch applies the pending dual update
   int32_t bb_iter0;    // iter and tau as the last head left them: the inputs of the next
   double bb_tau0;      // dual step, stable while the dense iteration's tail forms it
 };
@@ -175,6 +175,7 @@ struct ZJob {
   int64_t vec_base;   // the patient's first scenario in the stacked n-vectors
   int64_t zvec_base;  // the patient in the per-patient n-vectors
   int32_t n, N, col0, patient;
+  int64_t xtile0;     // dense x-update: table index of the first tile of the patient's first scenario
 };
 
 struct VecArgs {
@@ -236,11 +237,6 @@ struct XJob {
 
 // x-update reduction: block row I of one scenario's x_s, with every address
 // it needs, so that its loads depend on this entry only
-struct RJob {
-  int64_t part;   // offset in xpart of the scenario's first tile partials
-  int64_t vbase;  // the scenario's offset in the stacked n-vectors
-  int32_t I, nb, n, patient;
-};
 
 // Symmetric matrices of the dense x-update are stored as their upper 64 x 64
 // tiles (I <= J) in the order t(I, J) = I nb - I (I - 1) / 2 + (J - I), each
@@ -260,7 +256,6 @@ struct FactorArgs {
   double* xpart;      // per packed tile of every scenario: T c_J (64) and T^T c_I (64), fp64
   const XTile* xtiles; // x-update: one per packed tile of every scenario
   int32_t nxtiles;
-  const RJob* rjobs;  // x-update reduction: one per block row of every scenario
   const XJob* fjobs;  // objective: one per packed tile of every patient
   uint32_t* Gq;       // objective: Gp rounded to 48 bits, tile k of fjobs at 6144 k (layout in fobj_tile)
   double* fpart;      // objective partial per objective job
@@ -314,15 +309,15 @@ void launch_sweep_store(FactorArgs f, int patient, int scen_begin, int nscen, in
 void launch_gq_pack(const double* Gp, uint32_t* Gq, int64_t ntiles, hipStream_t st);
 void launch_xsym(const FactorArgs& f, const double* c, int njobs, hipStream_t st, hipEvent_t e0 = nullptr,
                  hipEvent_t e1 = nullptr);
-void launch_xsym_reduce(const FactorArgs& f, float* x, int njobs, hipStream_t st);
 void launch_fheadobj(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st);
-// dense five-launch iteration: body scalars beside the objective tiles, then
+// dense four-launch iteration: body scalars beside the objective tiles, then
 // the stopping test beside the dual update and right-hand sides
 void launch_dense_tail(const FactorArgs& f, const VecArgs& a, int nfobj, hipStream_t st);
 void launch_dense_head(const VecArgs& a, int nblk, hipStream_t st);
-// dense four-launch iteration: the stopping test of the previous iteration
+// dense three-launch iteration: the stopping test of the previous iteration
 // beside the x-update tiles; the reduction; the z-update; body scalars beside
 // the dual update with the next right-hand sides and the objective tiles
+void launch_xzres(const FactorArgs& f, const VecArgs& a, int npblk, hipStream_t st);
 void launch_dense_x(const FactorArgs& f, const VecArgs& a, const double* c, int njobs, hipStream_t st,
                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_dense_tail_dual(const FactorArgs& f, const VecArgs& a, int nfobj, int nblk, hipStream_t st);

@@ -145,7 +145,7 @@ admm_status validate_options(const admm_options* o, std::string* msg) {
   if (o->deterministic && o->lds_acc >= 0 && o->lds_acc != 2)
     return fail(msg, ADMM_E_ARG, "deterministic needs lds_acc -1 or 2 (64-bit fixed-point column sums)");
   if (o->xupdate < -1 || o->xupdate > 1) return fail(msg, ADMM_E_ARG, "xupdate must be -1, 0 or 1");
-  if (o->dense_launches != 4 && o->dense_launches != 5) return fail(msg, ADMM_E_ARG, "dense_launches must be 4 or 5");
+  if (o->dense_launches != 3 && o->dense_launches != 4) return fail(msg, ADMM_E_ARG, "dense_launches must be 3 or 4");
   return ADMM_OK;
 }
 

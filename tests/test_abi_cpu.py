@@ -139,7 +139,7 @@ def test_bad_options_rejected_before_device_work():
     for kw in (dict(cg_max=0), dict(cg_max=65), dict(z_mode=2), dict(lds_acc=3), dict(pass_threads=128),
                dict(pass_unroll=3), dict(max_iter=-1), dict(check_every=0), dict(precision=7),
                dict(xupdate=2), dict(format=2), dict(deterministic=2), dict(deterministic=1, lds_acc=1),
-               dict(dense_launches=3)):
+               dict(dense_launches=5)):
         with pytest.raises(A.AdmmError) as e:
             A.Solver(P, **kw)
         assert e.value.code == -1, kw

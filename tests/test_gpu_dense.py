@@ -274,21 +274,21 @@ def test_dense_set_up_and_iterations_are_bitwise_reproducible(monkeypatch):
 def _run_both_orders(Ps, **kw):
     import paper_2304_14568_amd as A
     out = {}
-    for nl in (5, 4):
+    for nl in (4, 3):
         with A.Solver(Ps, xupdate="dense", dense_launches=nl, max_iter=3000, **kw) as S:
             S.iterate(7)
             st7 = [S.get_state(p) for p in range(len(Ps))]
             S.reset()
             zs, info, status = S.solve()
             out[nl] = (st7, zs, info, [S.trace(p) for p in range(len(Ps))], status)
-    return out[5], out[4]
+    return out[4], out[3]
 
 
 @pytest.mark.parametrize("case", ["tiny", "hn_small", "batch_of_both", "no_graph"])
-def test_four_launch_iteration_equals_five_launch_order(probs, case):
-    """The four-launch dense iteration (the stopping test of an iteration
+def test_three_launch_iteration_equals_four_launch_order(probs, case):
+    """The three-launch dense iteration (the stopping test of an iteration
     beside the next x-update, the dual update beside the Barzilai-Borwein step
-    that every wave forms itself) against the five-launch order: the same
+    that every wave forms itself) against the four-launch order: the same
     duals, differences and scalars after 7 iterations, and the same solve
     (iterates, trace and stopping decision of every patient), bit for bit.
     The batch stops its two patients at different iterations."""
