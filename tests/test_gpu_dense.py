@@ -15,10 +15,10 @@ from oracle import admm as oadmm, exact, wls
 pytestmark = pytest.mark.gpu
 
 
-def _oracle_path(W, iters, rho=None, z0=None):
+def _oracle_path(W, iters, rho=None, z0=None, z_mode=0):
     zs, fs = [], []
     oadmm.admm_bb(W, rho=rho, max_iter=iters, obj_rel_tol=0.0, eps_abs=0.0, eps_rel=0.0, z0=z0, record=False,
-                  callback=lambda k, z, f: (zs.append(z.copy()), fs.append(f)))
+                  z_mode=z_mode, callback=lambda k, z, f: (zs.append(z.copy()), fs.append(f)))
     return zs, fs
 
 
@@ -72,6 +72,36 @@ def test_dense_iterates_follow_the_oracle(probs, which):
         # sparse-pass objective at the same z up to the fp32 rounding of p in the pass
         assert abs(tr[K - 1]["obj"] - S.objective(S.z())) <= 1e-7 * tr[K - 1]["obj"]
         assert abs(tr[K - 1]["obj"] - wls.objective(W, S.z())) <= 1e-9 * tr[K - 1]["obj"]
+
+
+@pytest.mark.parametrize("z_mode", [0, 1])
+def test_dense_iterates_with_more_scenarios_than_waves(z_mode):
+    """x_s and the z-update are formed with one wave per scenario at a time,
+    sixteen waves per workgroup: with 20 scenarios four waves take a second
+    scenario, whose x_s, dual and residual terms enter the fixed-order sums
+    after their first.  9 x 11 = 99 spots: the last 16-spot group of the last
+    64-spot block holds 3 spots.  z after k iterations and the objective
+    trace against the oracle, at the bounds of the 13-scenario test, for both
+    z-updates (the projected average of x_s + y_s / rho, and the literal
+    reading that averages x_s alone)."""
+    import paper_2304_14568_amd as A
+    P = synth.make_tiny(4, spots=(9, 11), num_scen=20,
+                        range_scales=tuple(np.linspace(0.96, 1.04, 20)))
+    assert P.num_scen == 20 and P.n == 99
+    W = wls.from_problem(P)
+    K = 8
+    zr, fr = _oracle_path(W, K, z_mode=z_mode)
+    with A.Solver(P, xupdate="dense", max_iter=1000, z_mode=z_mode) as S:
+        assert S.xupdate()[0] == "dense"
+        for k in (1, 2, 5, K):
+            S.reset()
+            S.iterate(k)
+            z = S.z()
+            err = np.linalg.norm(z - zr[k - 1]) / max(1e-30, np.linalg.norm(zr[k - 1]))
+            assert err <= 2e-5 * k, (k, err)
+        for t in S.trace()[:K]:
+            k = t["iter"]
+            assert abs(t["obj"] - fr[k - 1]) <= 1e-7 * fr[k - 1], (k, t["obj"], fr[k - 1])
 
 
 @pytest.mark.parametrize("which", [0, 1])
